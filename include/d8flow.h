@@ -1,0 +1,173 @@
+/*
+ * d8flow.h -- C ABI of the MI355X (gfx950) D8 flow-accumulation library.
+ *
+ * The library computes flow accumulation, Eq. (1) of Barnes, "Parallel
+ * Non-divergent Flow Accumulation For Trillion Cell Digital Elevation Models
+ * On Desktops Or Clusters" (arXiv:1608.04431), for non-divergent (D8) flow:
+ *
+ *     A(p) = w(p) + sum of A(n) over the neighbours n whose flow goes to p,
+ *
+ * with the paper's tile decomposition (Section "The Algorithm"; Algorithms 1-3):
+ * every tile is accumulated locally, the tiles' perimeter links and partial
+ * sums form one small global graph that is solved, and a second pass over each
+ * tile adds the resolved inflows (the EVICT strategy).  It also provides the
+ * D8 directions that feed it and the adjoint of the accumulation.
+ *
+ * Conventions for every call
+ *   - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors),
+ *     owned by the caller, row-major and contiguous: cell (r, c) is element
+ *     r * cols + c.  The library never frees, retains or reallocates them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls only enqueue work on it and return; they do not synchronise and do
+ *     not allocate device memory.  Scratch memory is the caller's workspace
+ *     `ws` of at least d8_workspace_bytes(...) bytes.
+ *   - Synchronous argument errors are returned as negative codes before
+ *     anything is enqueued.  Errors that depend on the data (an invalid
+ *     direction code, a cycle) are recorded in a status word inside `ws` and
+ *     read with d8_check_status(); outputs are then undefined.
+ *   - Work sharing one workspace must be ordered (same stream or events): the
+ *     workspace holds intermediate results between kernels.
+ */
+#ifndef D8FLOW_H
+#define D8FLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One byte per cell (Section "Data Types": ten distinct values).  The paper
+ * does not fix the encoding; this one is a 3x3 scan without the centre, so
+ * the opposite of direction k is 7 - k. */
+enum d8_code {
+    D8_NW = 0, D8_N = 1, D8_NE = 2, D8_W = 3, D8_E = 4, D8_SW = 5, D8_S = 6, D8_SE = 7,
+    D8_NOFLOW = 8, /* part of the DEM, no flow direction: an outlet */
+    D8_NODATA = 9  /* not part of the DEM; codes 10..255 are invalid */
+};
+
+enum d8_status {
+    D8_OK = 0,
+    D8_EINVAL = -1,     /* bad argument: null pointer, size, tile shape, type   */
+    D8_EWORKSPACE = -2, /* workspace missing or smaller than required            */
+    D8_EHIP = -3,       /* a HIP launch or runtime call failed                   */
+    D8_EDIRCODE = -4,   /* (data) a direction code above 9 was found             */
+    D8_ECYCLE = -5      /* (data) the directions contain a cycle                 */
+};
+
+enum d8_acc_type {
+    D8_ACC_U32 = 0, /* unit weights, exact 32-bit counts (weights must be NULL)  */
+    D8_ACC_F32 = 1  /* float32 weights (NULL = unit), float32 result             */
+};
+
+/* Largest tile area supported by the in-LDS tile kernels, in cells. */
+#define D8_MAX_TILE_CELLS 8192
+
+/*
+ * D8 flow directions (O'Callaghan & Mark 1984; the paper's non-divergent
+ * example, Introduction, and the "separate algorithm" that produces its input,
+ * Section "The Algorithm").  For every cell:
+ *   NoData (9)  if dem == nodata or dem is NaN;
+ *   else the neighbour k (0..7) with the steepest strictly positive descent,
+ *        the float32 drop d = z_c - z_n divided by 1 (cardinal) or sqrt(2)
+ *        (diagonal), compared exactly (2 d^2 vs d^2 in double); equal slopes
+ *        keep the lowest k; off-raster and NoData neighbours are not candidates;
+ *   else NoFlow (8).
+ * dem: float32 [rows*cols] (in); dirs: uint8 [rows*cols] (out).
+ * rows, cols >= 0 (an empty raster is a no-op).  Returns D8_OK, D8_EINVAL
+ * (null pointer with a non-empty raster, negative size) or D8_EHIP.
+ */
+int d8_directions(const float *dem, uint8_t *dirs, int64_t rows, int64_t cols, float nodata,
+                  void *stream);
+
+/*
+ * Workspace needed by flow_accum / flow_accum_adjoint for this raster and tile
+ * shape (tile_rows = tile_cols = 0 picks the default shape).  One workspace
+ * serves both calls.  Returns 0 for an invalid tile shape.
+ */
+size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols);
+
+/*
+ * Flow accumulation, Eq. (1) with alpha in {0,1} (Introduction), by the tiled
+ * method of Algorithms 1-3:
+ *   pass 1   per tile, dependency counts and the Kahn order of Algorithm 1 in
+ *            LDS, and Algorithm 2's links for every perimeter cell;
+ *   resolve  the global flow graph of perimeter cells, joined across tile
+ *            edges and corners (Section "Constructing a Global Solution");
+ *   pass 2   per tile, Algorithm 1 again with each perimeter cell's resolved
+ *            cross-tile inflow added to its own weight (EVICT, Section
+ *            "Broadcasting & Finalizing").
+ * A data cell whose direction leaves the raster, enters a NoData cell or is
+ * NoFlow is an outlet (it keeps its accumulation).
+ *
+ * dirs:     uint8 [rows*cols] direction codes (in).
+ * weights:  float32 [rows*cols] per-cell w (in), or NULL for w = 1.
+ * acc:      out, [rows*cols]: uint32 for D8_ACC_U32, float32 for D8_ACC_F32;
+ *           NoData cells are set to 0.
+ * tile_rows, tile_cols: tile shape (0, 0 = default 64 x 64); each >= 1; a
+ *           side longer than the raster is cut to the raster; after that
+ *           tile_rows * tile_cols <= D8_MAX_TILE_CELLS.
+ * ws, ws_bytes: workspace (device), at least d8_workspace_bytes(...).
+ * U32 counts are exact while every true count is below 2^32.
+ * F32: each tile sums in float32, the cross-tile resolve in float64.
+ * Returns D8_OK, D8_EINVAL, D8_EWORKSPACE or D8_EHIP (asynchronous data errors
+ * via d8_check_status).
+ */
+int flow_accum(const uint8_t *dirs, const float *weights, void *acc, int acc_type, int64_t rows,
+               int64_t cols, int tile_rows, int tile_cols, void *ws, size_t ws_bytes,
+               void *stream);
+
+/*
+ * Adjoint of flow_accum.  Eq. (1) is linear in w: A = (I - P)^-1 w, with
+ * P(p, n) = 1 when n's flow goes to p.  For a loss L(A) with g = dL/dA the
+ * weight gradient is lambda = (I - P)^-T g, i.e.
+ *     lambda(c) = g(c) + lambda(receiver of c)   (0 if c is an outlet),
+ * the sum of g along c's downstream flow path.  Computed with the same tiles:
+ * pass 1 sums g along each perimeter cell's in-tile path (Algorithm 2's walk),
+ * the perimeter graph resolves the downstream sums across tiles, and pass 2
+ * fills in every cell.  This operation is not in the paper; it follows from
+ * the linearity of Eq. (1).
+ *
+ * dirs: uint8 [rows*cols] (in); grad_acc: float32 [rows*cols] g (in);
+ * grad_weights: float32 [rows*cols] lambda (out), 0 on NoData cells.
+ * Other arguments and returns as for flow_accum.
+ */
+int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_weights,
+                       int64_t rows, int64_t cols, int tile_rows, int tile_cols, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/*
+ * Waits for `stream`, then returns the data-dependent status recorded in
+ * `ws` by the last flow_accum / flow_accum_adjoint call on it: D8_OK,
+ * D8_EDIRCODE or D8_ECYCLE (or D8_EHIP if the wait itself fails, D8_EINVAL for
+ * a NULL workspace).
+ */
+int d8_check_status(const void *ws, void *stream);
+
+/*
+ * Kernel timing, a profiling aid.  While enabled, every kernel launched by the
+ * calls above is bracketed by two HIP events recorded on its launch stream.
+ * d8_timing_report waits for the recorded events, writes up to max_entries
+ * (kernel name, summed milliseconds, launch count) triples -- names are static
+ * strings owned by the library -- forgets the records, and returns the number
+ * of entries written (or D8_EHIP).  Host memory only; never captured in a graph.
+ */
+int d8_timing_enable(int on);
+int d8_timing_report(const char **names, double *total_ms, int64_t *launches, int max_entries);
+
+/* The HIP error behind the calling thread's last D8_EHIP (kernel name and
+ * HIP message), or "" -- a diagnostic string owned by the library. */
+const char *d8_last_error_message(void);
+
+/* Static description of a status code. */
+const char *d8_strerror(int code);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int d8_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* D8FLOW_H */

@@ -1,0 +1,162 @@
+"""d8flow: MI355X-native D8 flow accumulation (Barnes, arXiv:1608.04431).
+
+Thin Python binding over the C ABI of ``libd8flow.so`` (include/d8flow.h).
+PyTorch provides device memory and the current stream; every step of the
+computation runs in the library's HIP kernels.  Calls are asynchronous on
+``torch.cuda.current_stream()``; data-dependent errors are reported by
+``check_status``.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+from ._lib import D8_ACC_F32, D8_ACC_U32, D8Error  # noqa: F401
+
+NOFLOW = 8
+NODATA = 9
+
+__all__ = ["d8_directions", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
+           "check_status", "FlowAccum", "D8Error"]
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else t.data_ptr()
+
+
+def _check_raster(t: torch.Tensor, dtype: torch.dtype, name: str):
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 2-D tensor")
+
+
+def workspace_bytes(rows: int, cols: int, tile: tuple[int, int] = (0, 0)) -> int:
+    n = _lib.load().d8_workspace_bytes(rows, cols, tile[0], tile[1])
+    if n == 0:
+        raise D8Error(_lib.D8_EINVAL, f"tile {tile} for {rows}x{cols}")
+    return n
+
+
+class Workspace:
+    """Caller-owned device scratch for flow_accum / flow_accum_adjoint."""
+
+    def __init__(self, rows: int, cols: int, tile: tuple[int, int] = (0, 0), device=None):
+        self.rows, self.cols, self.tile = rows, cols, tuple(tile)
+        self.nbytes = workspace_bytes(rows, cols, self.tile)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device or "cuda")
+
+    def fits(self, rows: int, cols: int, tile) -> bool:
+        return workspace_bytes(rows, cols, tuple(tile)) <= self.nbytes
+
+
+def _workspace(ws, rows, cols, tile, device):
+    if ws is None:
+        return Workspace(rows, cols, tile, device)
+    return ws
+
+
+def d8_directions(dem: torch.Tensor, nodata: float = -9999.0, out: torch.Tensor | None = None):
+    """D8 codes (uint8) of a float32 DEM (see d8_directions in d8flow.h)."""
+    _check_raster(dem, torch.float32, "dem")
+    if out is None:
+        out = torch.empty(dem.shape, dtype=torch.uint8, device=dem.device)
+    _check_raster(out, torch.uint8, "out")
+    rc = _lib.load().d8_directions(_ptr(dem), _ptr(out), dem.shape[0], dem.shape[1],
+                                   float(nodata), _stream(dem.device))
+    _lib.check(rc, "d8_directions")
+    return out
+
+
+def flow_accum(dirs: torch.Tensor, weights: torch.Tensor | None = None, acc_type: str = "auto",
+               tile: tuple[int, int] = (0, 0), ws: Workspace | None = None,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """Flow accumulation A (Eq. (1)).  acc_type 'u32' (unit weights, returned
+    as int32 storage holding uint32 bits) or 'f32'; 'auto' = u32 without
+    weights, f32 with."""
+    _check_raster(dirs, torch.uint8, "dirs")
+    if acc_type == "auto":
+        acc_type = "u32" if weights is None else "f32"
+    if acc_type not in ("u32", "f32"):
+        raise ValueError("acc_type must be 'u32' or 'f32'")
+    if weights is not None:
+        _check_raster(weights, torch.float32, "weights")
+        if weights.shape != dirs.shape:
+            raise ValueError("weights and dirs differ in shape")
+    rows, cols = dirs.shape
+    dt = torch.int32 if acc_type == "u32" else torch.float32
+    if out is None:
+        out = torch.empty((rows, cols), dtype=dt, device=dirs.device)
+    _check_raster(out, dt, "out")
+    ws = _workspace(ws, rows, cols, tile, dirs.device)
+    rc = _lib.load().flow_accum(_ptr(dirs), _ptr(weights), _ptr(out),
+                                D8_ACC_U32 if acc_type == "u32" else D8_ACC_F32, rows, cols,
+                                tile[0], tile[1], _ptr(ws.buf), ws.nbytes, _stream(dirs.device))
+    _lib.check(rc, "flow_accum")
+    return out
+
+
+def flow_accum_adjoint(dirs: torch.Tensor, grad_acc: torch.Tensor, tile=(0, 0),
+                       ws: Workspace | None = None, out: torch.Tensor | None = None):
+    """lambda = (I-P)^-T g: the sum of grad_acc along each cell's downstream path."""
+    _check_raster(dirs, torch.uint8, "dirs")
+    _check_raster(grad_acc, torch.float32, "grad_acc")
+    if grad_acc.shape != dirs.shape:
+        raise ValueError("grad_acc and dirs differ in shape")
+    rows, cols = dirs.shape
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float32, device=dirs.device)
+    _check_raster(out, torch.float32, "out")
+    ws = _workspace(ws, rows, cols, tile, dirs.device)
+    rc = _lib.load().flow_accum_adjoint(_ptr(dirs), _ptr(grad_acc), _ptr(out), rows, cols,
+                                        tile[0], tile[1], _ptr(ws.buf), ws.nbytes,
+                                        _stream(dirs.device))
+    _lib.check(rc, "flow_accum_adjoint")
+    return out
+
+
+def check_status(ws: Workspace) -> None:
+    """Synchronise the current stream and raise on a recorded data error."""
+    rc = _lib.load().d8_check_status(_ptr(ws.buf), _stream(ws.buf.device))
+    _lib.check(rc, "status")
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events (profiling aid)."""
+    _lib.load().d8_timing_enable(1 if on else 0)
+
+
+def timing_report(max_entries: int = 64) -> dict:
+    """{kernel name: (summed ms, launches)} since the last report; waits for
+    the recorded events."""
+    import ctypes
+    names = (ctypes.c_char_p * max_entries)()
+    ms = (ctypes.c_double * max_entries)()
+    cnt = (ctypes.c_int64 * max_entries)()
+    n = _lib.load().d8_timing_report(names, ms, cnt, max_entries)
+    if n < 0:
+        raise D8Error(n, "timing_report")
+    return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(n)}
+
+
+class FlowAccum(torch.autograd.Function):
+    """A = FlowAccum.apply(w, dirs[, tile]): differentiable in the weights w;
+    the backward pass is flow_accum_adjoint."""
+
+    @staticmethod
+    def forward(ctx, w, dirs, tile=(0, 0)):
+        ctx.save_for_backward(dirs)
+        ctx.tile = tuple(tile)
+        return flow_accum(dirs, w.contiguous(), acc_type="f32", tile=ctx.tile)
+
+    @staticmethod
+    def backward(ctx, grad_a):
+        (dirs,) = ctx.saved_tensors
+        gw = flow_accum_adjoint(dirs, grad_a.contiguous(), tile=ctx.tile)
+        return gw, None, None

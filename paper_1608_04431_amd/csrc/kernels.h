@@ -1,0 +1,225 @@
+// kernels.h -- gfx950 kernels of libd8flow (included by d8flow.hip).
+//
+// Forward (Eq. (1), alpha in {0,1}), the paper's three stages on one GPU:
+//   fwd_tile<1>       per tile in LDS (tiles.h): Algorithm 1's accumulation
+//                     and Algorithm 2's perimeter links; writes one record
+//                     (link, A_loc) per perimeter cell.
+//   graph_build       joins every FlowExternal perimeter cell to the perimeter
+//                     cell it flows into in the neighbouring tile (across an
+//                     edge or a corner) and to that cell's exit.
+//   resolve_fwd       accumulates the forest of exit cells and records each
+//                     perimeter cell's cross-tile inflow.
+//   fwd_tile<2>       Algorithm 1 again per tile with the inflow added to the
+//                     receiving cell's own weight (EVICT), writes A.
+// Adjoint (lambda = (I-P)^-T g, not in the paper):
+//   adj_tile<1>       per tile: sum of g along each perimeter cell's in-tile
+//                     path and the same links;
+//   graph_build, adj_jump_*   downstream sums over the exit forest by pointer
+//                     jumping;
+//   adj_tile<2>       per tile: lambda for every cell by pointer jumping in LDS.
+#pragma once
+#include "d8_common.h"
+#include "tiles.h"
+
+namespace d8 {
+
+// ------------------------------------------------------------------ misc ---
+
+__global__ void fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------- D8 ----
+// One thread per cell; neighbours come through L1/L2.  The drop is a single
+// float32 subtraction and the slope compare is exact in double (a float32
+// squared fits a double): cardinal key 2 d^2, diagonal key d^2.
+__global__ void d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t rows,
+                          int64_t cols, float nodata)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t r = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+    if (r >= rows || c >= cols) return;
+    float zc = dem[r * cols + c];
+    if (zc == nodata || zc != zc) {
+        dirs[r * cols + c] = kNoData;
+        return;
+    }
+    int best = kNoFlow;
+    double best_key = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int64_t rr = r + dir_dr(k), cc = c + dir_dc(k);
+        if (rr < 0 || rr >= rows || cc < 0 || cc >= cols) continue;
+        float zn = dem[rr * cols + cc];
+        if (zn == nodata || zn != zn) continue;
+        float d = __fsub_rn(zc, zn);
+        if (!(d > 0.0f)) continue;
+        double dd = (double)d;
+        double key = (dir_dr(k) == 0 || dir_dc(k) == 0) ? 2.0 * dd * dd : dd * dd;
+        if (key > best_key) {
+            best_key = key;
+            best = k;
+        }
+    }
+    dirs[r * cols + c] = (uint8_t)best;
+}
+
+// ------------------------------------------------------------ perimeter graph
+// For every FlowExternal node e: entry(e) = the perimeter node its flow enters
+// (in the tile across the edge or corner), succ(e) = that node's exit node
+// (itself if it is FlowExternal, none if its path terminates).  Counts each
+// exit node's in-degree in the exit forest (into `packed` or `indeg`).
+__global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
+                            const uint16_t *__restrict__ link, uint32_t *__restrict__ entry,
+                            uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg,
+                            unsigned long long *__restrict__ packed)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    uint32_t e = kNone, s = kNone;
+    if (link[id] == kLinkExt) {
+        int ty, tx, p, r, c;
+        node_tile(g, id, ty, tx, p);
+        ring_cell(p, tile_h(g, ty), tile_w(g, tx), r, c);
+        int64_t gr = (int64_t)ty * g.th + r, gc = (int64_t)tx * g.tw + c;
+        int k = dirs[gr * g.cols + gc];
+        int64_t nr = gr + dir_dr(k), nc = gc + dir_dc(k);
+        int uty = (int)(nr / g.th), utx = (int)(nc / g.tw);
+        int lr = (int)(nr - (int64_t)uty * g.th), lc = (int)(nc - (int64_t)utx * g.tw);
+        int64_t ub = node_base(g, uty, utx);
+        int q = ring_index(lr, lc, tile_h(g, uty), tile_w(g, utx));  // >= 0: borders a tile edge
+        int64_t n = ub + (q < 0 ? 0 : q);
+        uint16_t L = q < 0 ? kLinkNoData : link[n];
+        if (L != kLinkNoData) {
+            e = (uint32_t)n;
+            s = (L == kLinkExt) ? (uint32_t)n : (L == kLinkTerm ? kNone : (uint32_t)(ub + L));
+        }
+    }
+    entry[id] = e;
+    succ[id] = s;
+    if (s != kNone) {
+        if (packed) atomicAdd(&packed[s], 1ull);  // pending children in the low word
+        else if (indeg) atomicAdd(&indeg[s], 1u);
+    }
+}
+
+// Forest accumulation over exit nodes (the paper's modified Algorithm 1 on the
+// global graph): V(e) = A_loc(e) + sum of V over exits flowing into e; every
+// V(e) is also added to the inflow ext(entry(e)).  Walkers start at leaves and
+// continue from a node only as its last arriving child.
+//
+// Unit counts: one 64-bit atomic per step updates (inflow sum : pending
+// children) together -- adding ((v-1) << 32) + 0xFFFFFFFF subtracts one child
+// (the borrow carries +1 into the high word) and adds v -- so the last child
+// reads the complete sum from the returned value and no fence is needed.
+__global__ void resolve_fwd_u32(Geo g, const uint16_t *__restrict__ link,
+                                const uint32_t *__restrict__ aloc, const uint32_t *__restrict__ entry,
+                                const uint32_t *__restrict__ succ, unsigned long long *packed,
+                                uint32_t *ext)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    if (link[id] != kLinkExt || (uint32_t)packed[id] != 0) return;
+    uint32_t v = aloc[id];
+    uint32_t e = (uint32_t)id;
+    for (;;) {
+        uint32_t n = entry[e];
+        if (n == kNone) break;
+        atomicAdd(&ext[n], v);
+        uint32_t s = succ[e];
+        if (s == kNone) break;
+        unsigned long long add = ((unsigned long long)(v - 1u) << 32) + 0xFFFFFFFFull;
+        unsigned long long old = atomicAdd(&packed[s], add);
+        if ((uint32_t)old != 1u) break;
+        v = aloc[s] + (uint32_t)(old >> 32) + v;
+        e = s;
+    }
+}
+
+// Float weights: inflow sums in double; the pending count is separate, so the
+// last child's acquire pairs with the other children's releases.
+template <typename T>
+__global__ void resolve_fwd_f64(Geo g, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
+                                const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
+                                uint32_t *indeg, double *acc, double *ext)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    if (link[id] != kLinkExt || indeg[id] != 0) return;
+    double v = (double)aloc[id];
+    uint32_t e = (uint32_t)id;
+    for (;;) {
+        uint32_t n = entry[e];
+        if (n == kNone) break;
+        atomicAdd(&ext[n], v);
+        uint32_t s = succ[e];
+        if (s == kNone) break;
+        atomicAdd(&acc[s], v);
+        uint32_t old = __hip_atomic_fetch_sub(&indeg[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old != 1) break;
+        v = (double)aloc[s] + __hip_atomic_load(&acc[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        e = s;
+    }
+}
+
+// -------------------------------------------------------------- adjoint ----
+// mu(e) = lambda(entry(e)) = S(entry(e)) + mu(succ(e)): a downstream path sum
+// over the exit forest.  Initial state: ptr = succ, val = S(entry) (0 without
+// an entry).  Non-exit nodes are inert (ptr = none, val = 0).
+__global__ void adj_jump_init(Geo g, const uint16_t *__restrict__ link,
+                              const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
+                              const float *__restrict__ S, uint32_t *ptr, double *val)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    uint32_t n = entry[id];
+    ptr[id] = (link[id] == kLinkExt) ? succ[id] : kNone;
+    val[id] = (link[id] == kLinkExt && n != kNone) ? (double)S[n] : 0.0;
+}
+
+// One synchronous pointer-jumping round r: reads buffer r&1, writes buffer
+// (r+1)&1: val' = val + val[ptr], ptr' = ptr[ptr].  live[r%3] is set when any
+// pointer is still live after the round; round r reads live[(r-1)%3] and, if
+// nothing was live, records the final buffer in state[0] and does nothing.
+// live[(r+1)%3] is cleared here for the next round (its previous contents were
+// read by round r-1, which has completed).
+__global__ void adj_jump_round(Geo g, const uint32_t *__restrict__ ptr_in,
+                               const double *__restrict__ val_in, uint32_t *__restrict__ ptr_out,
+                               double *__restrict__ val_out, uint32_t *state, int round)
+{
+    uint32_t *live = state + 1;
+    if (live[(round + 2) % 3] == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (state[0] == kNone) state[0] = (uint32_t)(round & 1);
+            live[(round + 1) % 3] = 0;
+        }
+        return;
+    }
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id == 0) live[(round + 1) % 3] = 0;
+    if (id >= g.nnodes) return;
+    uint32_t p = ptr_in[id];
+    double v = val_in[id];
+    uint32_t np = kNone;
+    if (p != kNone) {
+        v += val_in[p];
+        np = ptr_in[p];
+    }
+    ptr_out[id] = np;
+    val_out[id] = v;
+    if (__ballot(np != kNone) != 0 && (threadIdx.x & (warpSize - 1)) == 0) live[round % 3] = 1;
+}
+
+// After the last round: if no round found convergence, the final buffer is
+// rounds&1, and pointers still live mean a cycle.
+__global__ void adj_jump_finish(uint32_t *state, int rounds, uint32_t *status)
+{
+    if (state[0] == kNone) {
+        if (state[1 + (rounds + 2) % 3] != 0) set_status(status, kStatusCycle);
+        state[0] = (uint32_t)(rounds & 1);
+    }
+}
+
+}  // namespace d8

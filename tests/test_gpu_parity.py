@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Unit counts must match bit-exactly; float32 results
+within the stated tolerances of the float64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+F32_RTOL = 1e-4  # max relative error against the float64 oracle
+
+
+@pytest.fixture(scope="module")
+def d8m():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    import paper_1608_04431_amd as m
+    m._lib.load()  # raises if the HIP library is not built
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def random_acyclic_dirs(rows, cols, seed, nodata_frac=0.1, noflow_frac=0.02):
+    rng = np.random.default_rng(seed)
+    z = rng.permutation(rows * cols).astype(np.float32).reshape(rows, cols)
+    z[rng.random((rows, cols)) < nodata_frac] = -9999.0
+    d = oracle.d8(z)
+    d[(rng.random((rows, cols)) < noflow_frac) & (d != 9)] = 8
+    return d
+
+
+def gpu_u32(m, d, tile=(0, 0)):
+    out = m.flow_accum(dev(d), acc_type="u32", tile=tile)
+    return out.cpu().numpy().view(np.uint32)
+
+
+def assert_u32_exact(got, d):
+    want = oracle.accum_u64(d)
+    assert want.max() < 2**32
+    np.testing.assert_array_equal(got.astype(np.uint64), want)
+
+
+def assert_rel(got, want, valid, rtol=F32_RTOL, what=""):
+    got = got.astype(np.float64)
+    pos = valid & (want > 0)
+    rel = np.abs(got[pos] - want[pos]) / want[pos]
+    assert rel.size == 0 or rel.max() <= rtol, f"{what} max rel err {rel.max():.3e}"
+    zero = valid & (want == 0)
+    assert (got[zero] == 0).all(), what
+    assert (got[~valid] == 0).all(), what
+
+
+def assert_adjoint(got, want, valid, what=""):
+    """Normwise bound, plus per-cell relative where |lambda| is not tiny."""
+    got = got.astype(np.float64)
+    scale = np.abs(want[valid]).max() if valid.any() else 0.0
+    if scale == 0:
+        assert (got == 0).all()
+        return
+    assert np.abs(got - want)[valid].max() <= F32_RTOL * scale, what
+    big = valid & (np.abs(want) >= 1e-3 * scale)
+    rel = np.abs(got[big] - want[big]) / np.abs(want[big])
+    assert rel.max() <= F32_RTOL, f"{what} max rel err {rel.max():.3e}"
+    assert (got[~valid] == 0).all()
+
+
+# ----------------------------------------------------------------- D8 -------
+def test_d8_directions_match_oracle(d8m):
+    rng = np.random.default_rng(1)
+    cases = [synth.workload_dem("dem512"),
+             rng.integers(0, 4, (37, 61)).astype(np.float32),          # many exact ties
+             (rng.random((1, 100)) * 5).astype(np.float32),
+             (rng.random((100, 1)) * 5).astype(np.float32),
+             synth.dem(300, 257, seed=7, lambda0=64, ocean=True)]
+    z = cases[1]
+    z[rng.random(z.shape) < 0.1] = -9999.0
+    z[3, 3] = np.nan
+    for z in cases:
+        got = d8m.d8_directions(dev(z)).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.d8(z))
+
+
+# ------------------------------------------------------------ hand fixtures --
+def test_golden_fixtures_u32(d8m):
+    from conftest import GOLDEN_FILES, load_golden
+    for name in GOLDEN_FILES:
+        d, A_hand, tile = load_golden(name)
+        for t in [tile or (0, 0), (1, 1), (2, 2), (1, 3), (0, 0)]:
+            got = gpu_u32(d8m, d, t)
+            np.testing.assert_array_equal(got.astype(np.uint64), A_hand, err_msg=f"{name} {t}")
+
+
+# ------------------------------------------------------- forward, unit counts
+@pytest.mark.parametrize("shape,tile", [
+    ((1, 1), (0, 0)), ((1, 300), (1, 64)), ((300, 1), (64, 1)), ((1, 300), (0, 0)),
+    ((64, 64), (64, 64)), ((65, 63), (64, 64)), ((200, 150), (16, 16)), ((200, 150), (1, 1)),
+    ((129, 257), (7, 9)), ((128, 512), (64, 128)), ((300, 200), (32, 96)),
+    ((257, 300), (32, 256)),
+])
+def test_forward_u32_random(d8m, shape, tile):
+    d = random_acyclic_dirs(*shape, seed=hash((shape, tile)) % 1000)
+    assert_u32_exact(gpu_u32(d8m, d, tile), d)
+
+
+def test_forward_all_nodata_and_outlets(d8m):
+    d = np.full((50, 70), 9, dtype=np.uint8)
+    assert (gpu_u32(d8m, d) == 0).all()
+    d = np.full((50, 70), 8, dtype=np.uint8)          # all NoFlow: every cell 1
+    assert (gpu_u32(d8m, d, (16, 16)) == 1).all()
+    d = np.full((40, 40), 4, dtype=np.uint8)          # all east, off the raster
+    assert_u32_exact(gpu_u32(d8m, d, (8, 8)), d)
+    d = np.full((40, 40), 7, dtype=np.uint8)          # diagonal flow across corners
+    assert_u32_exact(gpu_u32(d8m, d, (8, 8)), d)
+    d = np.full((40, 40), 0, dtype=np.uint8)
+    assert_u32_exact(gpu_u32(d8m, d, (5, 3)), d)
+
+
+def test_tiling_invariance_terrain(d8m):
+    z = synth.dem(700, 650, seed=11, lambda0=128, ocean=True)
+    d = oracle.d8(z)
+    want = oracle.accum_u64(d)
+    for tile in [(0, 0), (16, 16), (32, 64), (64, 32), (64, 128), (128, 64), (100, 37), (8, 512)]:
+        np.testing.assert_array_equal(gpu_u32(d8m, d, tile).astype(np.uint64), want,
+                                      err_msg=str(tile))
+
+
+def test_dem512_unit_counts(d8m):
+    """512 x 512, noise wavelength 128, unit weights, uint32: bit-exact."""
+    z = synth.workload_dem("dem512")
+    d = oracle.d8(z)
+    np.testing.assert_array_equal(d8m.d8_directions(dev(z)).cpu().numpy(), d)
+    assert_u32_exact(gpu_u32(d8m, d), d)
+
+
+# ------------------------------------------------------------ forward, f32 --
+@pytest.mark.parametrize("shape,tile", [((200, 150), (16, 16)), ((513, 300), (0, 0)),
+                                        ((1, 500), (1, 64)), ((300, 300), (64, 128))])
+def test_forward_f32_random(d8m, shape, tile):
+    d = random_acyclic_dirs(*shape, seed=7)
+    w = synth.uniform(shape, 8)
+    got = d8m.flow_accum(dev(d), dev(w), acc_type="f32", tile=tile).cpu().numpy()
+    assert_rel(got, oracle.accum_f64(d, w), d != 9, what=str(tile))
+    # unit weights through the float path
+    got1 = d8m.flow_accum(dev(d), None, acc_type="f32", tile=tile).cpu().numpy()
+    assert_rel(got1, oracle.accum_f64(d), d != 9)
+
+
+def test_forward_f32_deterministic(d8m):
+    z = synth.dem(600, 600, seed=12, lambda0=128, ocean=False)
+    d = dev(oracle.d8(z))
+    w = dev(synth.uniform((600, 600), 13))
+    a = d8m.flow_accum(d, w, acc_type="f32")
+    for _ in range(3):
+        b = d8m.flow_accum(d, w, acc_type="f32")
+        assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------- adjoint ----
+@pytest.mark.parametrize("shape,tile", [((200, 150), (16, 16)), ((513, 300), (0, 0)),
+                                        ((1, 500), (1, 64)), ((77, 1), (0, 0)),
+                                        ((300, 300), (64, 128)), ((100, 100), (1, 1))])
+def test_adjoint_dense(d8m, shape, tile):
+    d = random_acyclic_dirs(*shape, seed=21)
+    g = synth.uniform(shape, 22)
+    got = d8m.flow_accum_adjoint(dev(d), dev(g), tile=tile).cpu().numpy()
+    want = oracle.transpose_f64(d, g)
+    valid = d != 9
+    assert_rel(got, want, valid, what=str(tile))
+
+
+def test_adjoint_terrain_and_identity(d8m):
+    z = synth.dem(640, 700, seed=23, lambda0=128, ocean=True)
+    d = oracle.d8(z)
+    rng = np.random.default_rng(24)
+    w = synth.uniform(d.shape, 25)
+    g = np.zeros(d.shape, dtype=np.float32)
+    idx = rng.choice(d.size, 64, replace=False)
+    g.ravel()[idx] = rng.standard_normal(64).astype(np.float32)
+    lam = d8m.flow_accum_adjoint(dev(d), dev(g)).cpu().numpy()
+    assert_adjoint(lam, oracle.transpose_f64(d, g), d != 9)
+    A = d8m.flow_accum(dev(d), dev(w), acc_type="f32").cpu().numpy().astype(np.float64)
+    lhs = float((g.astype(np.float64) * A).sum())
+    rhs = float((lam.astype(np.float64) * w).sum())
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), 1.0)
+
+
+def test_adjoint_unit_cotangent_catchment(d8m):
+    z = synth.dem(300, 300, seed=26, lambda0=64, ocean=False)
+    d = oracle.d8(z)
+    A = oracle.accum_u64(d)
+    r, c = np.unravel_index(np.argmax(A), A.shape)
+    g = np.zeros(d.shape, dtype=np.float32)
+    g[r, c] = 1.0
+    lam = d8m.flow_accum_adjoint(dev(d), dev(g), tile=(32, 32)).cpu().numpy()
+    assert set(np.unique(lam)) <= {0.0, 1.0}
+    assert lam.sum() == A[r, c]
+
+
+# ----------------------------------------------------------------- errors ----
+def test_data_errors_reported(d8m):
+    d = random_acyclic_dirs(64, 64, 31)
+    d[5, 5] = 200
+    ws = d8m.Workspace(64, 64)
+    d8m.flow_accum(dev(d), ws=ws)
+    with pytest.raises(d8m.D8Error) as e:
+        d8m.check_status(ws)
+    assert e.value.code == -4
+    # a two-cell cycle inside one tile, and one across a tile boundary
+    for (r, c), tile in [((10, 10), (0, 0)), ((10, 31), (32, 32))]:
+        d = random_acyclic_dirs(64, 64, 32)
+        d[r, c], d[r, c + 1] = 4, 3
+        ws = d8m.Workspace(64, 64, tile)
+        for fn in (lambda: d8m.flow_accum(dev(d), ws=ws, tile=tile),
+                   lambda: d8m.flow_accum_adjoint(dev(d), dev(np.ones_like(d, np.float32)),
+                                                  ws=ws, tile=tile)):
+            fn()
+            with pytest.raises(d8m.D8Error) as e:
+                d8m.check_status(ws)
+            assert e.value.code == -5
+    # a clean call afterwards resets the status
+    d = random_acyclic_dirs(64, 64, 33)
+    d8m.flow_accum(dev(d), ws=ws, tile=(32, 32))
+    d8m.check_status(ws)
+
+
+def test_argument_errors(d8m):
+    d = dev(random_acyclic_dirs(16, 16, 1))
+    with pytest.raises(TypeError):
+        d8m.flow_accum(d.float())
+    d8m.flow_accum(d, tile=(200, 200))  # clipped to the 16x16 raster: valid
+    with pytest.raises(d8m.D8Error):
+        d8m.flow_accum(d, tile=(0, 5))
+    small = d8m.Workspace(4, 4)
+    with pytest.raises(d8m.D8Error) as e:
+        d8m.flow_accum(d, ws=small)
+    assert e.value.code == -2
+
+
+def test_empty_raster(d8m):
+    d = torch.empty((0, 7), dtype=torch.uint8, device="cuda")
+    assert d8m.flow_accum(d).shape == (0, 7)
+    g = torch.empty((0, 7), dtype=torch.float32, device="cuda")
+    assert d8m.flow_accum_adjoint(d, g).shape == (0, 7)
