@@ -61,8 +61,9 @@ enum d8_acc_type {
     D8_ACC_F32 = 1  /* float32 weights (NULL = unit), float32 result             */
 };
 
-/* Largest tile area supported by the in-LDS tile kernels, in cells. */
-#define D8_MAX_TILE_CELLS 8192
+/* Largest tile side supported by the tile kernels (one wavefront per tile,
+ * one lane per tile row), in cells. */
+#define D8_MAX_TILE_SIDE 64
 
 /*
  * D8 flow directions (O'Callaghan & Mark 1984; the paper's non-divergent
@@ -107,7 +108,7 @@ size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_co
  *           NoData cells are set to 0.
  * tile_rows, tile_cols: tile shape (0, 0 = default 64 x 64); each >= 1; a
  *           side longer than the raster is cut to the raster; after that
- *           tile_rows * tile_cols <= D8_MAX_TILE_CELLS.
+ *           each side <= D8_MAX_TILE_SIDE.
  * ws, ws_bytes: workspace (device), at least d8_workspace_bytes(...).
  * U32 counts are exact while every true count is below 2^32.
  * F32: each tile sums in float32, the cross-tile resolve in float64.

@@ -18,7 +18,7 @@ EXPORTS = ("d8_directions", "d8_workspace_bytes", "flow_accum", "flow_accum_adjo
 
 D8_OK, D8_EINVAL, D8_EWORKSPACE, D8_EHIP, D8_EDIRCODE, D8_ECYCLE = 0, -1, -2, -3, -4, -5
 D8_ACC_U32, D8_ACC_F32 = 0, 1
-D8_MAX_TILE_CELLS = 8192
+D8_MAX_TILE_SIDE = 64
 
 _lib = None
 

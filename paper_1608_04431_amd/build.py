@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libd8flow.so")
 SOURCES = [os.path.join(CSRC, "d8flow.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.h", "d8_common.h")] + \
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.h", "walk.h", "d8_common.h")] + \
     [os.path.join(ROOT, "include", "d8flow.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

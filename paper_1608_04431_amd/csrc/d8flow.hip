@@ -57,7 +57,7 @@ int check_common(int64_t rows, int64_t cols, int &th, int &tw, Geo &g, bool &emp
     // a tile larger than the raster is the raster
     if (th > rows) th = (int)rows;
     if (tw > cols) tw = (int)cols;
-    if ((int64_t)th * tw > D8_MAX_TILE_CELLS) return D8_EINVAL;
+    if (th > D8_MAX_TILE_SIDE || tw > D8_MAX_TILE_SIDE) return D8_EINVAL;
     g = make_geo(rows, cols, th, tw);
     if (g.nnodes >= (int64_t)kNone || (int64_t)g.nty * g.ntx > INT_MAX) return D8_EINVAL;
     return D8_OK;
@@ -129,15 +129,8 @@ thread_local int g_launch_rc = D8_OK;
 
 inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-// kCPT cells per thread, whole wavefronts
-inline int tile_threads(int n)
-{
-    int t = (n + kCPT - 1) / kCPT;
-    return (t + 63) / 64 * 64;
-}
-
-// per tile: an 8-byte state word and a code byte per cell
-inline size_t tile_lds_bytes(int n) { return ((size_t)n * 9 + 15) & ~size_t(15); }
+// one wavefront per tile
+constexpr int kTileThreads = 64;
 
 __global__ void init_state(uint32_t *status, uint32_t *jstate)
 {
@@ -146,6 +139,7 @@ __global__ void init_state(uint32_t *status, uint32_t *jstate)
     jstate[1] = 0;      // live flags of rounds r % 3 (round 0 reads slot 2)
     jstate[2] = 0;
     jstate[3] = 1;
+    jstate[4] = 0;      // number of listed leaves of the exit forest
 }
 
 // Start of a C-ABI call: forget earlier launch errors.
@@ -202,31 +196,35 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
     E *ext = reinterpret_cast<E *>(ws + L.ext64);
 
     int ntiles = g.nty * g.ntx;
-    int nmax = g.th * g.tw;
-    int thr = tile_threads(nmax);
-    size_t lds = tile_lds_bytes(nmax);
-    if (allow_lds(fwd_tile<1, T, V, E>, lds) || allow_lds(fwd_tile<2, T, V, E>, lds))
+    const int thr = kTileThreads;
+    size_t lds = walk_lds_bytes(g.th, g.tw);
+    if (allow_lds(fwd_walk<1, T, V, E>, lds) || allow_lds(fwd_walk<2, T, V, E>, lds))
         return D8_EHIP;
 
     init_state<<<1, 1, 0, st>>>(status, jstate);
     unsigned nb = blocks_for(g.nnodes, kNodeBlock);
     D8_LAUNCH("fwd_pass1", st,
-              (fwd_tile<1, T, V, E><<<ntiles, thr, lds, st>>>(dirs, w, g, link, aloc, indeg, acc,
+              (fwd_walk<1, T, V, E><<<ntiles, thr, lds, st>>>(dirs, w, g, link, aloc, indeg, acc,
                                                               ext, nullptr, status)));
     unsigned long long *packed = nullptr;
     if constexpr (kCounts) packed = acc;
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, packed)));
+    uint32_t *leaves = reinterpret_cast<uint32_t *>(ws + L.ptr2);
+    uint32_t *nleaves = jstate + 4;
+    D8_LAUNCH("list_leaves", st,
+              (list_leaves<<<nb, kNodeBlock, 0, st>>>(g, link, indeg, packed, leaves, nleaves)));
     if constexpr (kCounts) {
         D8_LAUNCH("resolve_fwd", st,
-                  (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g, link, aloc, entry, succ, acc, ext)));
+                  (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(leaves, nleaves, aloc, entry, succ, acc,
+                                                              ext)));
     } else {
         D8_LAUNCH("resolve_fwd", st,
-                  (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(g, link, aloc, entry, succ, indeg,
-                                                                 acc, ext)));
+                  (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(leaves, nleaves, aloc, entry, succ,
+                                                                 indeg, acc, ext)));
     }
     D8_LAUNCH("fwd_pass2", st,
-              (fwd_tile<2, T, V, E><<<ntiles, thr, lds, st>>>(dirs, w, g, link, aloc, indeg, acc,
+              (fwd_walk<2, T, V, E><<<ntiles, thr, lds, st>>>(dirs, w, g, link, aloc, indeg, acc,
                                                               ext, out, status)));
     return last_error();
 }
@@ -344,16 +342,15 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                       reinterpret_cast<double *>(w8 + L.ext64)};
 
     int ntiles = g.nty * g.ntx;
-    int nmax = g.th * g.tw;
-    int thr = tile_threads(nmax);
-    size_t lds = tile_lds_bytes(nmax);
+    const int thr = kTileThreads;
+    size_t lds = walk_lds_bytes(g.th, g.tw);
     begin_call();
-    if (allow_lds(adj_tile<1>, lds) || allow_lds(adj_tile<2>, lds)) return D8_EHIP;
+    if (allow_lds(adj_walk<1>, lds) || allow_lds(adj_walk<2>, lds)) return D8_EHIP;
     unsigned nb = blocks_for(g.nnodes, kNodeBlock);
 
     init_state<<<1, 1, 0, st>>>(status, jstate);
     D8_LAUNCH("adj_pass1", st,
-              (adj_tile<1><<<ntiles, thr, lds, st>>>(dirs, grad_acc, g, link, S, nullptr, nullptr,
+              (adj_walk<1><<<ntiles, thr, lds, st>>>(dirs, grad_acc, g, link, S, nullptr, nullptr,
                                                      jstate, nullptr, status)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr,
@@ -369,7 +366,7 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                                                              jstate, r)));
     D8_LAUNCH("adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
     D8_LAUNCH("adj_pass2", st,
-              (adj_tile<2><<<ntiles, thr, lds, st>>>(dirs, grad_acc, g, link, nullptr, val[0],
+              (adj_walk<2><<<ntiles, thr, lds, st>>>(dirs, grad_acc, g, link, nullptr, val[0],
                                                      val[1], jstate, grad_weights, status)));
     return last_error();
 }

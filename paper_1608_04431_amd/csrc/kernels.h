@@ -1,25 +1,25 @@
 // kernels.h -- gfx950 kernels of libd8flow (included by d8flow.hip).
 //
 // Forward (Eq. (1), alpha in {0,1}), the paper's three stages on one GPU:
-//   fwd_tile<1>       per tile in LDS (tiles.h): Algorithm 1's accumulation
-//                     and Algorithm 2's perimeter links; writes one record
-//                     (link, A_loc) per perimeter cell.
+//   fwd_walk<1>       one wavefront per tile (walk.h): Algorithm 1's
+//                     accumulation and Algorithm 2's perimeter links; writes
+//                     one record (link, A_loc) per perimeter cell.
 //   graph_build       joins every FlowExternal perimeter cell to the perimeter
 //                     cell it flows into in the neighbouring tile (across an
 //                     edge or a corner) and to that cell's exit.
 //   resolve_fwd       accumulates the forest of exit cells and records each
 //                     perimeter cell's cross-tile inflow.
-//   fwd_tile<2>       Algorithm 1 again per tile with the inflow added to the
+//   fwd_walk<2>       Algorithm 1 again per tile with the inflow added to the
 //                     receiving cell's own weight (EVICT), writes A.
 // Adjoint (lambda = (I-P)^-T g, not in the paper):
-//   adj_tile<1>       per tile: sum of g along each perimeter cell's in-tile
+//   adj_walk<1>       per tile: sum of g along each entry cell's in-tile
 //                     path and the same links;
 //   graph_build, adj_jump_*   downstream sums over the exit forest by pointer
 //                     jumping;
-//   adj_tile<2>       per tile: lambda for every cell by pointer jumping in LDS.
+//   adj_walk<2>       per tile: lambda for every cell by upstream walks in LDS.
 #pragma once
 #include "d8_common.h"
-#include "tiles.h"
+#include "walk.h"
 
 namespace d8 {
 
@@ -105,6 +105,28 @@ __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
     }
 }
 
+// Leaves of the exit forest (exit nodes without children), listed before any
+// walker runs: deciding "leaf" while walkers are already decrementing counts
+// would let a finished node look like a leaf and be walked twice.
+__global__ void list_leaves(Geo g, const uint16_t *__restrict__ link,
+                            const uint32_t *__restrict__ indeg,
+                            const unsigned long long *__restrict__ packed, uint32_t *list,
+                            uint32_t *count)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool leaf = false;
+    if (id < g.nnodes && link[id] == kLinkExt)
+        leaf = packed ? (uint32_t)packed[id] == 0 : indeg[id] == 0;
+    // one atomic per wavefront
+    uint64_t b = __ballot(leaf);
+    if (b == 0) return;
+    int lane = __lane_id();
+    uint32_t base = 0;
+    if (lane == __ffsll((unsigned long long)b) - 1) base = atomicAdd(count, (uint32_t)__popcll(b));
+    base = __shfl(base, __ffsll((unsigned long long)b) - 1, 64);
+    if (leaf) list[base + __popcll(b & ((1ull << lane) - 1ull))] = (uint32_t)id;
+}
+
 // Forest accumulation over exit nodes (the paper's modified Algorithm 1 on the
 // global graph): V(e) = A_loc(e) + sum of V over exits flowing into e; every
 // V(e) is also added to the inflow ext(entry(e)).  Walkers start at leaves and
@@ -114,16 +136,16 @@ __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
 // children) together -- adding ((v-1) << 32) + 0xFFFFFFFF subtracts one child
 // (the borrow carries +1 into the high word) and adds v -- so the last child
 // reads the complete sum from the returned value and no fence is needed.
-__global__ void resolve_fwd_u32(Geo g, const uint16_t *__restrict__ link,
+__global__ void resolve_fwd_u32(const uint32_t *__restrict__ leaves, const uint32_t *__restrict__ nleaves,
                                 const uint32_t *__restrict__ aloc, const uint32_t *__restrict__ entry,
                                 const uint32_t *__restrict__ succ, unsigned long long *packed,
                                 uint32_t *ext)
 {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
-    if (link[id] != kLinkExt || (uint32_t)packed[id] != 0) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *nleaves) return;
+    const uint32_t id = leaves[i];
     uint32_t v = aloc[id];
-    uint32_t e = (uint32_t)id;
+    uint32_t e = id;
     for (;;) {
         uint32_t n = entry[e];
         if (n == kNone) break;
@@ -141,15 +163,16 @@ __global__ void resolve_fwd_u32(Geo g, const uint16_t *__restrict__ link,
 // Float weights: inflow sums in double; the pending count is separate, so the
 // last child's acquire pairs with the other children's releases.
 template <typename T>
-__global__ void resolve_fwd_f64(Geo g, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
-                                const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
-                                uint32_t *indeg, double *acc, double *ext)
+__global__ void resolve_fwd_f64(const uint32_t *__restrict__ leaves, const uint32_t *__restrict__ nleaves,
+                                const T *__restrict__ aloc, const uint32_t *__restrict__ entry,
+                                const uint32_t *__restrict__ succ, uint32_t *indeg, double *acc,
+                                double *ext)
 {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
-    if (link[id] != kLinkExt || indeg[id] != 0) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *nleaves) return;
+    const uint32_t id = leaves[i];
     double v = (double)aloc[id];
-    uint32_t e = (uint32_t)id;
+    uint32_t e = id;
     for (;;) {
         uint32_t n = entry[e];
         if (n == kNone) break;

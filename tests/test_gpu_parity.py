@@ -100,8 +100,8 @@ def test_golden_fixtures_u32(d8m):
 @pytest.mark.parametrize("shape,tile", [
     ((1, 1), (0, 0)), ((1, 300), (1, 64)), ((300, 1), (64, 1)), ((1, 300), (0, 0)),
     ((64, 64), (64, 64)), ((65, 63), (64, 64)), ((200, 150), (16, 16)), ((200, 150), (1, 1)),
-    ((129, 257), (7, 9)), ((128, 512), (64, 128)), ((300, 200), (32, 96)),
-    ((257, 300), (32, 256)),
+    ((129, 257), (7, 9)), ((128, 512), (64, 64)), ((300, 200), (32, 48)),
+    ((257, 300), (16, 64)),
 ])
 def test_forward_u32_random(d8m, shape, tile):
     d = random_acyclic_dirs(*shape, seed=hash((shape, tile)) % 1000)
@@ -125,7 +125,7 @@ def test_tiling_invariance_terrain(d8m):
     z = synth.dem(700, 650, seed=11, lambda0=128, ocean=True)
     d = oracle.d8(z)
     want = oracle.accum_u64(d)
-    for tile in [(0, 0), (16, 16), (32, 64), (64, 32), (64, 128), (128, 64), (100, 37), (8, 512)]:
+    for tile in [(0, 0), (16, 16), (32, 64), (64, 32), (64, 48), (48, 64), (50, 37), (8, 60), (1, 64), (64, 1)]:
         np.testing.assert_array_equal(gpu_u32(d8m, d, tile).astype(np.uint64), want,
                                       err_msg=str(tile))
 
@@ -140,7 +140,7 @@ def test_dem512_unit_counts(d8m):
 
 # ------------------------------------------------------------ forward, f32 --
 @pytest.mark.parametrize("shape,tile", [((200, 150), (16, 16)), ((513, 300), (0, 0)),
-                                        ((1, 500), (1, 64)), ((300, 300), (64, 128))])
+                                        ((1, 500), (1, 64)), ((300, 300), (64, 64))])
 def test_forward_f32_random(d8m, shape, tile):
     d = random_acyclic_dirs(*shape, seed=7)
     w = synth.uniform(shape, 8)
@@ -164,7 +164,7 @@ def test_forward_f32_deterministic(d8m):
 # ---------------------------------------------------------------- adjoint ----
 @pytest.mark.parametrize("shape,tile", [((200, 150), (16, 16)), ((513, 300), (0, 0)),
                                         ((1, 500), (1, 64)), ((77, 1), (0, 0)),
-                                        ((300, 300), (64, 128)), ((100, 100), (1, 1))])
+                                        ((300, 300), (48, 64)), ((100, 100), (1, 1))])
 def test_adjoint_dense(d8m, shape, tile):
     d = random_acyclic_dirs(*shape, seed=21)
     g = synth.uniform(shape, 22)
