@@ -139,7 +139,6 @@ __global__ void init_state(uint32_t *status, uint32_t *jstate)
     jstate[1] = 0;      // live flags of rounds r % 3 (round 0 reads slot 2)
     jstate[2] = 0;
     jstate[3] = 1;
-    jstate[4] = 0;      // number of listed leaves of the exit forest
 }
 
 // Start of a C-ABI call: forget earlier launch errors.
@@ -190,42 +189,37 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
     uint16_t *link = reinterpret_cast<uint16_t *>(ws + L.link);
     uint32_t *entry = reinterpret_cast<uint32_t *>(ws + L.entry);
     uint32_t *succ = reinterpret_cast<uint32_t *>(ws + L.succ);
-    uint32_t *indeg = kCounts ? nullptr : reinterpret_cast<uint32_t *>(ws + L.indeg);
+    uint32_t *indeg = reinterpret_cast<uint32_t *>(ws + L.indeg);
+    uint32_t *cnt = kCounts ? nullptr : reinterpret_cast<uint32_t *>(ws + L.ptr2);
     T *aloc = reinterpret_cast<T *>(ws + L.val32);
     V *acc = reinterpret_cast<V *>(ws + L.acc64);
     E *ext = reinterpret_cast<E *>(ws + L.ext64);
 
     int ntiles = g.nty * g.ntx;
     const int thr = kTileThreads;
-    size_t lds = walk_lds_bytes(g.th, g.tw);
-    if (allow_lds(fwd_walk<1, T, V, E>, lds) || allow_lds(fwd_walk<2, T, V, E>, lds))
+    size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1), lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2);
+    if (allow_lds(fwd_walk<1, T, V, E>, lds1) || allow_lds(fwd_walk<2, T, V, E>, lds2))
         return D8_EHIP;
 
     init_state<<<1, 1, 0, st>>>(status, jstate);
     unsigned nb = blocks_for(g.nnodes, kNodeBlock);
     D8_LAUNCH("fwd_pass1", st,
-              (fwd_walk<1, T, V, E><<<ntiles, thr, lds, st>>>(dirs, w, g, link, aloc, indeg, acc,
-                                                              ext, nullptr, status)));
-    unsigned long long *packed = nullptr;
-    if constexpr (kCounts) packed = acc;
+              (fwd_walk<1, T, V, E><<<ntiles, thr, lds1, st>>>(dirs, w, g, link, aloc, indeg, cnt,
+                                                               acc, ext, nullptr, status)));
     D8_LAUNCH("graph_build", st,
-              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, packed)));
-    uint32_t *leaves = reinterpret_cast<uint32_t *>(ws + L.ptr2);
-    uint32_t *nleaves = jstate + 4;
-    D8_LAUNCH("list_leaves", st,
-              (list_leaves<<<nb, kNodeBlock, 0, st>>>(g, link, indeg, packed, leaves, nleaves)));
+              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg)));
     if constexpr (kCounts) {
         D8_LAUNCH("resolve_fwd", st,
-                  (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(leaves, nleaves, aloc, entry, succ, acc,
+                  (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g, link, aloc, entry, succ, indeg, acc,
                                                               ext)));
     } else {
         D8_LAUNCH("resolve_fwd", st,
-                  (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(leaves, nleaves, aloc, entry, succ,
-                                                                 indeg, acc, ext)));
+                  (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(g, link, aloc, entry, succ, indeg,
+                                                                 cnt, acc, ext)));
     }
     D8_LAUNCH("fwd_pass2", st,
-              (fwd_walk<2, T, V, E><<<ntiles, thr, lds, st>>>(dirs, w, g, link, aloc, indeg, acc,
-                                                              ext, out, status)));
+              (fwd_walk<2, T, V, E><<<ntiles, thr, lds2, st>>>(dirs, w, g, link, aloc, indeg, cnt,
+                                                               acc, ext, out, status)));
     return last_error();
 }
 
@@ -343,18 +337,17 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
 
     int ntiles = g.nty * g.ntx;
     const int thr = kTileThreads;
-    size_t lds = walk_lds_bytes(g.th, g.tw);
+    size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1), lds2 = walk_lds_bytes(g.th, g.tw, kWalkAdj2);
     begin_call();
-    if (allow_lds(adj_walk<1>, lds) || allow_lds(adj_walk<2>, lds)) return D8_EHIP;
+    if (allow_lds(adj_walk<1>, lds1) || allow_lds(adj_walk<2>, lds2)) return D8_EHIP;
     unsigned nb = blocks_for(g.nnodes, kNodeBlock);
 
     init_state<<<1, 1, 0, st>>>(status, jstate);
     D8_LAUNCH("adj_pass1", st,
-              (adj_walk<1><<<ntiles, thr, lds, st>>>(dirs, grad_acc, g, link, S, nullptr, nullptr,
-                                                     jstate, nullptr, status)));
+              (adj_walk<1><<<ntiles, thr, lds1, st>>>(dirs, grad_acc, g, link, S, nullptr, nullptr,
+                                                      jstate, nullptr, status)));
     D8_LAUNCH("graph_build", st,
-              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr,
-                                                      nullptr)));
+              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr)));
     D8_LAUNCH("adj_jump_init", st,
               (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(g, link, entry, succ, S, ptr[0], val[0])));
     int rounds = 1;
@@ -366,7 +359,7 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                                                              jstate, r)));
     D8_LAUNCH("adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
     D8_LAUNCH("adj_pass2", st,
-              (adj_walk<2><<<ntiles, thr, lds, st>>>(dirs, grad_acc, g, link, nullptr, val[0],
+              (adj_walk<2><<<ntiles, thr, lds2, st>>>(dirs, grad_acc, g, link, nullptr, val[0],
                                                      val[1], jstate, grad_weights, status)));
     return last_error();
 }

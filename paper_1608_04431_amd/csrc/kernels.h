@@ -69,12 +69,12 @@ __global__ void d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ d
 // ------------------------------------------------------------ perimeter graph
 // For every FlowExternal node e: entry(e) = the perimeter node its flow enters
 // (in the tile across the edge or corner), succ(e) = that node's exit node
-// (itself if it is FlowExternal, none if its path terminates).  Counts each
-// exit node's in-degree in the exit forest (into `packed` or `indeg`).
+// (itself if it is FlowExternal, none if its path terminates).  indeg (when
+// given) counts each exit node's children in the exit forest; it is not
+// changed afterwards, so the resolve can tell leaves from inner nodes.
 __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
                             const uint16_t *__restrict__ link, uint32_t *__restrict__ entry,
-                            uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg,
-                            unsigned long long *__restrict__ packed)
+                            uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= g.nnodes) return;
@@ -99,80 +99,53 @@ __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
     }
     entry[id] = e;
     succ[id] = s;
-    if (s != kNone) {
-        if (packed) atomicAdd(&packed[s], 1ull);  // pending children in the low word
-        else if (indeg) atomicAdd(&indeg[s], 1u);
-    }
-}
-
-// Leaves of the exit forest (exit nodes without children), listed before any
-// walker runs: deciding "leaf" while walkers are already decrementing counts
-// would let a finished node look like a leaf and be walked twice.
-__global__ void list_leaves(Geo g, const uint16_t *__restrict__ link,
-                            const uint32_t *__restrict__ indeg,
-                            const unsigned long long *__restrict__ packed, uint32_t *list,
-                            uint32_t *count)
-{
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool leaf = false;
-    if (id < g.nnodes && link[id] == kLinkExt)
-        leaf = packed ? (uint32_t)packed[id] == 0 : indeg[id] == 0;
-    // one atomic per wavefront
-    uint64_t b = __ballot(leaf);
-    if (b == 0) return;
-    int lane = __lane_id();
-    uint32_t base = 0;
-    if (lane == __ffsll((unsigned long long)b) - 1) base = atomicAdd(count, (uint32_t)__popcll(b));
-    base = __shfl(base, __ffsll((unsigned long long)b) - 1, 64);
-    if (leaf) list[base + __popcll(b & ((1ull << lane) - 1ull))] = (uint32_t)id;
+    if (indeg && s != kNone) atomicAdd(&indeg[s], 1u);
 }
 
 // Forest accumulation over exit nodes (the paper's modified Algorithm 1 on the
 // global graph): V(e) = A_loc(e) + sum of V over exits flowing into e; every
-// V(e) is also added to the inflow ext(entry(e)).  Walkers start at leaves and
-// continue from a node only as its last arriving child.
+// V(e) is also added to the inflow ext(entry(e)).  Walkers start at leaves
+// (indeg 0) and continue from a node only as its last arriving child.
 //
-// Unit counts: one 64-bit atomic per step updates (inflow sum : pending
-// children) together -- adding ((v-1) << 32) + 0xFFFFFFFF subtracts one child
-// (the borrow carries +1 into the high word) and adds v -- so the last child
-// reads the complete sum from the returned value and no fence is needed.
-__global__ void resolve_fwd_u32(const uint32_t *__restrict__ leaves, const uint32_t *__restrict__ nleaves,
+// Unit counts: one 64-bit atomic per step updates (inflow sum : arrivals)
+// together -- adding (v << 32) + 1 -- so the last child reads the complete
+// sum from the returned value and no fence is needed.
+__global__ void resolve_fwd_u32(Geo g, const uint16_t *__restrict__ link,
                                 const uint32_t *__restrict__ aloc, const uint32_t *__restrict__ entry,
-                                const uint32_t *__restrict__ succ, unsigned long long *packed,
-                                uint32_t *ext)
+                                const uint32_t *__restrict__ succ, const uint32_t *__restrict__ indeg,
+                                unsigned long long *packed, uint32_t *ext)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *nleaves) return;
-    const uint32_t id = leaves[i];
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    if (link[id] != kLinkExt || indeg[id] != 0) return;
     uint32_t v = aloc[id];
-    uint32_t e = id;
+    uint32_t e = (uint32_t)id;
     for (;;) {
         uint32_t n = entry[e];
         if (n == kNone) break;
         atomicAdd(&ext[n], v);
         uint32_t s = succ[e];
         if (s == kNone) break;
-        unsigned long long add = ((unsigned long long)(v - 1u) << 32) + 0xFFFFFFFFull;
-        unsigned long long old = atomicAdd(&packed[s], add);
-        if ((uint32_t)old != 1u) break;
+        unsigned long long old = atomicAdd(&packed[s], ((unsigned long long)v << 32) | 1ull);
+        if ((uint32_t)old + 1u != indeg[s]) break;
         v = aloc[s] + (uint32_t)(old >> 32) + v;
         e = s;
     }
 }
 
-// Float weights: inflow sums in double; the pending count is separate, so the
-// last child's acquire pairs with the other children's releases.
+// Float weights: inflow sums in double; arrivals are counted separately, so
+// the last child's acquire pairs with the other children's releases.
 template <typename T>
-__global__ void resolve_fwd_f64(const uint32_t *__restrict__ leaves, const uint32_t *__restrict__ nleaves,
-                                const T *__restrict__ aloc, const uint32_t *__restrict__ entry,
-                                const uint32_t *__restrict__ succ, uint32_t *indeg, double *acc,
+__global__ void resolve_fwd_f64(Geo g, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
+                                const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
+                                const uint32_t *__restrict__ indeg, uint32_t *cnt, double *acc,
                                 double *ext)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *nleaves) return;
-    const uint32_t id = leaves[i];
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    if (link[id] != kLinkExt || indeg[id] != 0) return;
     double v = (double)aloc[id];
-    uint32_t e = id;
+    uint32_t e = (uint32_t)id;
     for (;;) {
         uint32_t n = entry[e];
         if (n == kNone) break;
@@ -180,8 +153,8 @@ __global__ void resolve_fwd_f64(const uint32_t *__restrict__ leaves, const uint3
         uint32_t s = succ[e];
         if (s == kNone) break;
         atomicAdd(&acc[s], v);
-        uint32_t old = __hip_atomic_fetch_sub(&indeg[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old != 1) break;
+        uint32_t old = __hip_atomic_fetch_add(&cnt[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u != indeg[s]) break;
         v = (double)aloc[s] + __hip_atomic_load(&acc[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         e = s;
     }

@@ -1,23 +1,31 @@
 // walk.h -- one wavefront per tile: flow walkers in LDS.
 //
-// Tile shape: up to 64 rows x 64 columns.  Lane r owns tile row r during
-// setup; its 64 direction codes sit in 16 registers (4 codes per word) and
-// the donor counts of all 64 cells are found with byte-parallel compares
-// against the rows above and below (fetched from lanes r-1 / r+1).  LDS then
-// holds one byte per cell (code | pending donors of a confluence << 4) and
-// one 32-bit value per cell (seed, then accumulation), with padded row strides.
+// Tile shape: up to 64 rows x 64 columns, one 64-lane wavefront per tile.
 //
-// Forward walks (Algorithm 1's Kahn order, done by walkers): every source
-// (a data cell without in-tile donors) starts a walk downstream.  Entering a
-// cell with one donor, the walk simply adds that cell's seed.  Entering a
-// confluence, the walk decrements its pending-donor count; only the last
-// arriving donor continues, after gathering the donors' totals in fixed
-// neighbour order.  All walks of a tile run in one wavefront, so the order of
-// LDS operations -- and therefore every float sum -- is fixed by the input.
+// Setup.  Lane r owns tile row r: its 64 direction codes sit in 16 registers
+// (4 codes per word) and the in-tile donor counts of all 64 cells come from
+// byte-parallel compares against the rows above and below (lanes r-1, r+1).
 //
-// Link walks (Algorithm 2, FollowPath): from every entry cell (a perimeter
-// cell with a donor in another tile) to the end of its in-tile path; the
-// adjoint's pass 1 sums g along the way.
+// LDS.  One byte per cell and one 32-bit value per cell, both indexed by the
+// same cell index (r + 1) * S + 1 + c with S = w + 2: the tile sits inside a
+// one-cell frame, so a step in direction k is `idx + offset(k)` and leaving
+// the tile shows up as a frame byte -- no bounds arithmetic on the walk path.
+// Cell bytes hold the code in the low nibble and, for confluences of the
+// forward pass, the number of donors still to arrive in the high nibble.
+// Frame bytes hold kFrameTile (a cell of a neighbouring tile) or kFrameOut
+// (outside the raster) in the low nibble.
+//
+// Walks.  Start cells wait in an LDS queue; idle lanes claim the next ones in
+// a single step (lane rank among idle lanes by mbcnt).  Forward walks
+// (Algorithm 1's Kahn order, done by walkers) start at sources; a walk adds
+// each cell's seed; at a confluence it adds its total to the cell's value and
+// decrements the cell's pending count with LDS atomics, and only the last
+// arriving donor continues.  Link walks (Algorithm 2's FollowPath) run from
+// entry cells (perimeter cells with a donor in another tile) to the end of
+// their in-tile path.  Upstream walks (the adjoint) run from roots against
+// the flow; side donors of a branching cell are finished on the spot and
+// queued.  All walks of a tile run in one wavefront, so the order of LDS
+// operations is fixed by the input.
 #pragma once
 
 #include "d8_common.h"
@@ -25,12 +33,17 @@
 namespace d8 {
 namespace wk {
 
-constexpr int kW = 64;           // max tile width (columns)
-constexpr int kH = 64;           // max tile height (rows) = lanes
-constexpr int kWords = kW / 4;   // code words per row
+constexpr int kW = 64;          // max tile width (columns)
+constexpr int kH = 64;          // max tile height (rows) = lanes
+constexpr int kWords = kW / 4;  // code words per row
+
+constexpr uint32_t kFrameTile = 0x0Eu;  // frame cell inside the raster (another tile)
+constexpr uint32_t kFrameOut = 0x0Fu;   // frame cell outside the raster
 
 struct WTile {
     int ty, tx, h, w, P;
+    int S;          // LDS row stride (cells) = w + 2
+    uint32_t invS;  // ceil(2^20 / S), for dividing cell indices by S
     int64_t r0, c0, base;
 };
 
@@ -42,11 +55,51 @@ __device__ inline WTile wtile_of(const Geo &g, int t)
     T.h = tile_h(g, T.ty);
     T.w = tile_w(g, T.tx);
     T.P = ring_size(T.h, T.w);
+    T.S = T.w + 2;
+    T.invS = ((1u << 20) + (uint32_t)T.S - 1u) / (uint32_t)T.S;
     T.r0 = (int64_t)T.ty * g.th;
     T.c0 = (int64_t)T.tx * g.tw;
     T.base = node_base(g, T.ty, T.tx);
     return T;
 }
+
+__device__ inline int cidx(const WTile &T, int r, int c) { return (r + 1) * T.S + 1 + c; }
+
+// Row and column of a cell index (exact for every index of a tile up to
+// 66 x 66 frame cells: the error of the scaled reciprocal is below 1/S).
+__device__ inline void idx_rc(const WTile &T, int idx, int &r, int &c)
+{
+    int r1 = (int)(((uint32_t)idx * T.invS) >> 20);
+    r = r1 - 1;
+    c = idx - r1 * T.S - 1;
+}
+
+// Index offset of the neighbour in direction k (0..7).  Codes 8..15 give
+// -(S + 1), a valid index for any cell of the tile, so speculative reads
+// stay inside the tile's LDS.
+__device__ inline int dir_off(uint32_t k, int S)
+{
+    uint32_t dr = (0xA940u >> (2u * k)) & 3u;  // row offset + 1 of directions 0..7
+    uint32_t dc = (0x9224u >> (2u * k)) & 3u;  // column offset + 1
+    return (int)(dr * (uint32_t)S + dc) - (S + 1);
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// number of set bits of m in lanes below this one
+__device__ inline uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ----------------------------------------------------------- byte SWAR ---
 
 // 0x80 in every zero byte of x, 0 elsewhere (exact, no carries between bytes).
 __device__ inline uint32_t zero_bytes(uint32_t x)
@@ -57,8 +110,24 @@ __device__ inline uint32_t eq_bytes(uint32_t x, uint32_t k) { return zero_bytes(
 // bytes [4m-1 .. 4m+2] and [4m+1 .. 4m+4] of a row given words m-1, m, m+1
 __device__ inline uint32_t left1(uint32_t cur, uint32_t prev) { return __builtin_amdgcn_alignbyte(cur, prev, 3); }
 __device__ inline uint32_t right1(uint32_t next, uint32_t cur) { return __builtin_amdgcn_alignbyte(next, cur, 1); }
-
-__device__ inline int lane_id() { return __lane_id(); }
+// 0x80 in bytes holding a data code 0..8
+__device__ inline uint32_t valid_markers(uint32_t x)
+{
+    uint32_t ge9 = (((x & 0x7F7F7F7Fu) + 0x77777777u) | x) & 0x80808080u;
+    return ~ge9 & 0x80808080u;
+}
+// byte b (0..3) of each 0x80-marker word packed into bit b
+__device__ inline uint32_t marker_bits(uint32_t z)
+{
+    return ((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) | ((z >> 28) & 8u);
+}
+// Set byte (col - 4m) of word m of a row to `v` when that column falls in the word.
+__device__ inline uint32_t put_byte(uint32_t word, int m, int col, uint32_t v)
+{
+    int b = col - 4 * m;
+    if (b < 0 || b > 3) return word;
+    return (word & ~(0xFFu << (8 * b))) | (v << (8 * b));
+}
 
 // value of lane-1 (row above); lane 0 gets `edge`
 __device__ inline uint32_t from_above(uint32_t x, uint32_t edge)
@@ -73,7 +142,7 @@ __device__ inline uint32_t from_below(uint32_t x, uint32_t edge)
     return lane_id() == 63 ? edge : v;
 }
 
-// codes of tile row r (lane r), padded with 0xFF outside the tile; codes
+// Codes of tile row r (lane r), padded with 0xFF outside the tile; codes
 // above 9 are reported and replaced by NoData.
 __device__ inline void load_row(const uint8_t *__restrict__ dirs, const Geo &g, const WTile &T,
                                 uint32_t (&W)[kWords], uint32_t *status)
@@ -83,7 +152,18 @@ __device__ inline void load_row(const uint8_t *__restrict__ dirs, const Geo &g, 
     for (int m = 0; m < kWords; ++m) W[m] = 0xFFFFFFFFu;
     if (r >= T.h) return;
     const uint8_t *row = dirs + (T.r0 + r) * g.cols + T.c0;
-    if ((((uintptr_t)row) & 3) == 0 && (T.w & 3) == 0) {
+    if ((((uintptr_t)row) & 15) == 0 && (T.w & 15) == 0) {
+        const uint4 *row16 = reinterpret_cast<const uint4 *>(row);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (16 * i < T.w) {
+                uint4 v = row16[i];
+                W[4 * i] = v.x;
+                W[4 * i + 1] = v.y;
+                W[4 * i + 2] = v.z;
+                W[4 * i + 3] = v.w;
+            }
+    } else if ((((uintptr_t)row) & 3) == 0 && (T.w & 3) == 0) {
         const uint32_t *row4 = reinterpret_cast<const uint32_t *>(row);
 #pragma unroll
         for (int m = 0; m < kWords; ++m)
@@ -134,123 +214,6 @@ __device__ inline void load_row(const uint8_t *__restrict__ dirs, const Geo &g, 
     }
 }
 
-// Donor counts of the 4 cells of word m: each byte += 1 per neighbour whose
-// code points at the cell (neighbour in direction j has code 7 - j).
-// A/N/B: row above / own / below, words m-1, m, m+1.
-__device__ inline uint32_t donor_count_word(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t n0,
-                                            uint32_t n1, uint32_t n2, uint32_t b0, uint32_t b1,
-                                            uint32_t b2)
-{
-    uint32_t cnt = 0;
-    cnt += eq_bytes(left1(a1, a0), 7) >> 7;   // NW neighbour flows SE
-    cnt += eq_bytes(a1, 6) >> 7;              // N flows S
-    cnt += eq_bytes(right1(a2, a1), 5) >> 7;  // NE flows SW
-    cnt += eq_bytes(left1(n1, n0), 4) >> 7;   // W flows E
-    cnt += eq_bytes(right1(n2, n1), 3) >> 7;  // E flows W
-    cnt += eq_bytes(left1(b1, b0), 2) >> 7;   // SW flows NE
-    cnt += eq_bytes(b1, 1) >> 7;              // S flows N
-    cnt += eq_bytes(right1(b2, b1), 0) >> 7;  // SE flows NW
-    return cnt;
-}
-
-// byte b (0..3) of each 0x80-marker word packed into bit b
-__device__ inline uint32_t marker_bits(uint32_t z)
-{
-    return ((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) | ((z >> 28) & 8u);
-}
-
-// j-th set bit (0-based) of a 64-bit mask
-__device__ inline int nth_set_bit(uint64_t s, int j)
-{
-    int pos = 0;
-#pragma unroll
-    for (int half = 32; half >= 1; half >>= 1) {
-        uint64_t low = s & ((1ull << half) - 1ull);
-        int c = __popcll(low);
-        if (j >= c) {
-            j -= c;
-            s >>= half;
-            pos += half;
-        }
-    }
-    return pos;
-}
-
-__device__ inline uint64_t clear_lowest(uint64_t s, int k)
-{
-    for (int i = 0; i < k; ++i) s &= s - 1ull;
-    return s;
-}
-
-// Work dispenser over per-lane bit masks (lane = row, bit = column): hands
-// out tasks in row-major order to idle lanes, ranks by lane order.  State is
-// wavefront-uniform.
-struct Dispenser {
-    uint64_t rows_left;  // rows that still have tasks
-    int row;             // current row, or -1
-    uint64_t pend;       // tasks of the current row not yet handed out
-
-    __device__ void init(uint64_t my_mask)
-    {
-        rows_left = __ballot(my_mask != 0);
-        row = -1;
-        pend = 0;
-    }
-    __device__ bool empty() const { return pend == 0 && rows_left == 0; }
-    // Returns true and sets (r, c) for idle lanes that get a task.
-    __device__ bool take(bool idle, uint64_t my_mask, int &r, int &c)
-    {
-        uint64_t free_lanes = __ballot(idle);
-        bool got = false;
-        while (free_lanes != 0 && !(pend == 0 && rows_left == 0)) {
-            if (pend == 0) {
-                row = __ffsll((unsigned long long)rows_left) - 1;
-                rows_left &= rows_left - 1ull;
-                uint32_t lo = __builtin_amdgcn_readlane((uint32_t)my_mask, row);
-                uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(my_mask >> 32), row);
-                pend = ((uint64_t)hi << 32) | lo;
-                continue;
-            }
-            int nfree = __popcll(free_lanes), ntask = __popcll(pend);
-            int k = nfree < ntask ? nfree : ntask;
-            if (idle && !got) {
-                uint64_t below = free_lanes & ((1ull << lane_id()) - 1ull);
-                bool mine = (free_lanes >> lane_id()) & 1ull;
-                int rank = __popcll(below);
-                if (mine && rank < k) {
-                    r = row;
-                    c = nth_set_bit(pend, rank);
-                    got = true;
-                }
-            }
-            pend = clear_lowest(pend, k);
-            free_lanes = clear_lowest(free_lanes, k);
-        }
-        return got;
-    }
-};
-
-}  // namespace wk
-}  // namespace d8
-
-namespace d8 {
-namespace wk {
-
-// Per-tile LDS strides (words), odd so that lanes walking one column hit
-// different banks.
-struct Layout {
-    int cbs, as;  // code-byte row stride, value row stride
-    __device__ __host__ static int odd(int x) { return x | 1; }
-    __device__ __host__ Layout(int tw) : cbs(odd((tw + 3) / 4 + 1)), as(odd(tw + 1)) {}
-    __device__ int cbw(int r, int c) const { return r * cbs + (c >> 2); }
-    __device__ int ai(int r, int c) const { return r * as + c; }
-};
-
-__device__ inline uint32_t cbyte(const uint32_t *cb, const Layout &L, int r, int c)
-{
-    return (cb[L.cbw(r, c)] >> (8 * (c & 3))) & 0xFFu;
-}
-
 // Codes of a row outside the tile (the halo rows above / below), for columns
 // -1 .. w; bytes outside the raster are 0xFF.  Returns words for columns
 // 0..63 in H and the corner bytes in left / right.
@@ -278,85 +241,22 @@ __device__ inline void load_halo_row(const uint8_t *__restrict__ dirs, const Geo
     if (T.c0 + T.w < g.cols) right = row[T.w];
 }
 
-// Walk state of one lane.
-template <typename T>
-struct Walker {
-    int r = -1, c = -1;  // current cell, r < 0: idle
-    uint32_t code = 0;
-    T a = (T)0;
-};
-
-// One step of a forward walk from (w.r, w.c).  Returns false when the walk ends.
-template <typename T>
-__device__ inline bool fwd_step(Walker<T> &wk, const WTile &Tl, const Layout &L, uint32_t *cb, T *av,
-                                int &visited)
-{
-    uint32_t k = wk.code;
-    if (k >= (uint32_t)kNoFlow) return false;
-    int rr = wk.r + dir_dr(k), cc = wk.c + dir_dc(k);
-    if (rr < 0 || rr >= Tl.h || cc < 0 || cc >= Tl.w) return false;
-    const int wi = L.cbw(rr, cc), sh = 8 * (cc & 3);
-    uint32_t b = (cb[wi] >> sh) & 0xFFu;
-    uint32_t kn = b & 15u;
-    if (kn >= (uint32_t)kNoData) return false;
-    const int ai = L.ai(rr, cc);
-    if ((b >> 4) != 0u) {
-        // confluence: only the last arriving donor continues
-        uint32_t old = atomicSub(&cb[wi], 0x10u << sh);
-        if (((old >> (sh + 4)) & 15u) != 1u) return false;
-        T s = av[ai];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            int nr = rr + dir_dr(j), nc = cc + dir_dc(j);
-            if (nr < 0 || nr >= Tl.h || nc < 0 || nc >= Tl.w) continue;
-            if ((cbyte(cb, L, nr, nc) & 15u) == (uint32_t)(7 - j)) s += av[L.ai(nr, nc)];
-        }
-        wk.a = s;
-    } else {
-        wk.a += av[ai];
-    }
-    av[ai] = wk.a;
-    wk.r = rr;
-    wk.c = cc;
-    wk.code = kn;
-    ++visited;
-    return true;
-}
-
-}  // namespace wk
-}  // namespace d8
-
-namespace d8 {
-namespace wk {
-
-__device__ inline uint32_t valid_markers(uint32_t x)  // bytes with a data code 0..8
-{
-    uint32_t ge9 = (((x & 0x7F7F7F7Fu) + 0x77777777u) | x) & 0x80808080u;
-    return ~ge9 & 0x80808080u;
-}
-
-// Set byte (col - 4m) of word m of a row to `v` when that column falls in the word.
-__device__ inline uint32_t put_byte(uint32_t word, int m, int col, uint32_t v)
-{
-    int b = col - 4 * m;
-    if (b < 0 || b > 3) return word;
-    return (word & ~(0xFFu << (8 * b))) | (v << (8 * b));
-}
-
-// Per-lane setup result.
+// Per-lane setup result (bit c = column c of this lane's row).
 struct Setup {
-    uint64_t src;    // forward: cells without in-tile donors (bit = column)
-    uint64_t entry;  // cells with a donor in another tile
-    uint64_t root;   // adjoint: cells without an in-tile receiver
-    int valid;       // data cells in this row
+    uint64_t src;    // forward: data cells without in-tile donors
+    uint64_t entry;  // data cells with a donor in another tile
+    uint64_t root;   // adjoint: data cells without an in-tile receiver
+    uint64_t valid;  // data cells
 };
 
-// MODE 0: forward (writes code | confluence count << 4 into cb); MODE 1: adjoint pass 1
-// (codes only); MODE 2: adjoint pass 2 (donor masks into cb).  Entries are
-// found when WANT_ENTRY, roots when MODE == 2.
+// Writes the cell bytes of the tile and its frame.
+//   MODE 0 (forward): code | pending donors of a confluence << 4;
+//   MODE 1 (links only): code;
+//   MODE 2 (upstream walks): bit j = the neighbour in direction j is a donor.
+// Entries are found when WANT_ENTRY, roots when MODE == 2.
 template <int MODE, bool WANT_ENTRY>
 __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &g, const WTile &Tl,
-                                   const Layout &L, uint32_t *cb, uint32_t *status)
+                                   uint8_t *cb8, uint32_t *status)
 {
     const int r = lane_id();
     uint32_t W[kWords], A[kWords], B[kWords];
@@ -366,17 +266,19 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
         A[m] = from_above(W[m], 0xFFFFFFFFu);
         B[m] = from_below(W[m], 0xFFFFFFFFu);
     }
-    Setup S;
-    S.src = S.entry = S.root = 0;
-    S.valid = 0;
+    Setup St;
+    St.src = St.entry = St.root = St.valid = 0;
     const uint32_t G = 0xFFFFFFFFu;  // guard word outside the tile
+    const bool own = r < Tl.h;
+    uint8_t *rowb = cb8 + (r + 1) * Tl.S + 1;
 #pragma unroll
     for (int m = 0; m < kWords; ++m) {
         uint32_t a0 = m ? A[m - 1] : G, a2 = m + 1 < kWords ? A[m + 1] : G;
         uint32_t n0 = m ? W[m - 1] : G, n2 = m + 1 < kWords ? W[m + 1] : G;
         uint32_t b0 = m ? B[m - 1] : G, b2 = m + 1 < kWords ? B[m + 1] : G;
         uint32_t vm = valid_markers(W[m]);
-        S.valid += __popc(vm);
+        St.valid |= (uint64_t)marker_bits(vm) << (4 * m);
+        uint32_t bytes;
         if (MODE == 0 || MODE == 2) {
             // per direction j: 0x80 where the neighbour in direction j flows in
             uint32_t e[8];
@@ -393,16 +295,15 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
 #pragma unroll
                 for (int j = 0; j < 8; ++j) cnt += e[j] >> 7;
                 // the high nibble keeps the pending-donor count of confluences
-                // only; 0 marks a cell with one donor (or none), so a walk that
-                // finds a non-zero nibble knows it entered a confluence
+                // only; 0 marks a cell with one donor (or none)
                 uint32_t single = (eq_bytes(cnt, 1) >> 7) * 0xFFu;
-                if (r < Tl.h && 4 * m < g.tw) cb[r * L.cbs + m] = W[m] | ((cnt & ~single) << 4);
-                S.src |= (uint64_t)marker_bits(zero_bytes(cnt) & vm) << (4 * m);
+                bytes = W[m] | ((cnt & ~single) << 4);
+                St.src |= (uint64_t)marker_bits(zero_bytes(cnt) & vm) << (4 * m);
             } else {
                 uint32_t mask = 0;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) mask |= (e[j] >> 7) << j;
-                if (r < Tl.h && 4 * m < g.tw) cb[r * L.cbs + m] = mask & (vm >> 7) * 0xFFu;
+                bytes = mask & ((vm >> 7) * 0xFFu);
                 // roots: NoFlow, or a direction whose target is outside the tile / NoData
                 uint32_t va = valid_markers(A[m]), vw = vm, vb = valid_markers(B[m]);
                 uint32_t va0 = valid_markers(a0), va2 = valid_markers(a2);
@@ -420,16 +321,35 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
                 uint32_t root = eq_bytes(W[m], kNoFlow);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) root |= eq_bytes(W[m], k) & ~tv[k];
-                S.root |= (uint64_t)marker_bits(root & vm) << (4 * m);
+                St.root |= (uint64_t)marker_bits(root & vm) << (4 * m);
             }
         } else {
-            if (r < Tl.h && 4 * m < g.tw) cb[r * L.cbs + m] = W[m];
+            bytes = W[m];
+        }
+        if (own) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (4 * m + b < Tl.w) rowb[4 * m + b] = (uint8_t)(bytes >> (8 * b));
+        }
+    }
+    if (MODE != 2) {
+        // frame: rows -1 and h (columns -1 .. w), columns -1 and w
+        const int S = Tl.S;
+        for (int j = r; j < S; j += 64) {
+            int64_t gc = Tl.c0 + j - 1;
+            bool cin = gc >= 0 && gc < g.cols;
+            cb8[j] = (uint8_t)((Tl.r0 > 0 && cin) ? kFrameTile : kFrameOut);
+            cb8[(Tl.h + 1) * S + j] = (uint8_t)((Tl.r0 + Tl.h < g.rows && cin) ? kFrameTile : kFrameOut);
+        }
+        if (own) {
+            cb8[(r + 1) * S] = (uint8_t)(Tl.c0 > 0 ? kFrameTile : kFrameOut);
+            cb8[(r + 1) * S + Tl.w + 1] = (uint8_t)(Tl.c0 + Tl.w < g.cols ? kFrameTile : kFrameOut);
         }
     }
     if (WANT_ENTRY) {
         // halo: left / right neighbours of this row, rows above / below the tile
         uint32_t HL = 0xFFu, HR = 0xFFu;
-        if (r < Tl.h) {
+        if (own) {
             const uint8_t *row = dirs + (Tl.r0 + r) * g.cols + Tl.c0;
             if (Tl.c0 > 0) HL = row[-1];
             if (Tl.c0 + Tl.w < g.cols) HR = row[Tl.w];
@@ -483,377 +403,499 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
                                  eq_bytes(right1(h2, h1), 0);
                     ent |= (uint64_t)marker_bits(e) << (4 * m);
                 }
-                uint32_t HLb1 = Hl2, HRb1 = Hr2;
-                if (HLb1 == 2u) ent |= 1ull;
-                if (HRb1 == 0u) ent |= 1ull << (Tl.w - 1);
+                if (Hl2 == 2u) ent |= 1ull;
+                if (Hr2 == 0u) ent |= 1ull << (Tl.w - 1);
             }
         }
-        // data cells of this row only
-        uint64_t vbits = 0;
-#pragma unroll
-        for (int m = 0; m < kWords; ++m) vbits |= (uint64_t)marker_bits(valid_markers(W[m])) << (4 * m);
-        S.entry = (r < Tl.h) ? (ent & vbits) : 0;
+        St.entry = own ? (ent & St.valid) : 0;
     }
-    return S;
+    return St;
 }
 
-// Algorithm 2's link for a walk from perimeter cell (qr, qc) that ended at
-// (er, ec) because its direction leaves the tile (dir_out) or it terminates.
-__device__ inline uint16_t link_for(const Geo &g, const WTile &Tl, int qr, int qc, int er, int ec,
-                                    uint32_t code_e)
+// ---------------------------------------------------------------- queue ---
+// Start cells wait in an LDS array of 16-bit entries: cell index, bit 15 =
+// link walk.  fill_queue appends the cells of every lane's masks (lane r =
+// tile row r, row-major order) at positions 0.. of the queue, at most `cap`,
+// and clears the bits it wrote; returns how many it wrote (wave-uniform).
+__device__ inline uint32_t fill_queue(uint16_t *q, uint32_t cap, const WTile &Tl, uint64_t &m0,
+                                      uint64_t &m1)
 {
-    if (code_e >= (uint32_t)kNoFlow) return kLinkTerm;
-    int rr = er + dir_dr(code_e), cc = ec + dir_dc(code_e);
-    if (rr >= 0 && rr < Tl.h && cc >= 0 && cc < Tl.w) return kLinkTerm;  // into NoData
-    int64_t gr = Tl.r0 + rr, gc = Tl.c0 + cc;
-    if (gr < 0 || gr >= g.rows || gc < 0 || gc >= g.cols) return kLinkTerm;
-    if (er == qr && ec == qc) return kLinkExt;
-    return (uint16_t)ring_index(er, ec, Tl.h, Tl.w);
+    const int lane = lane_id();
+    uint32_t n = (uint32_t)(__popcll(m0) + __popcll(m1));
+    uint32_t incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    uint32_t total = __shfl(incl, 63, 64);
+    uint32_t pos = incl - n;
+    const int rowbase = (lane + 1) * Tl.S + 1;
+    while (m0 != 0 && pos < cap) {
+        int c = __ffsll((unsigned long long)m0) - 1;
+        m0 &= m0 - 1ull;
+        q[pos++] = (uint16_t)(rowbase + c);
+    }
+    while (m1 != 0 && pos < cap) {
+        int c = __ffsll((unsigned long long)m1) - 1;
+        m1 &= m1 - 1ull;
+        q[pos++] = (uint16_t)((rowbase + c) | 0x8000);
+    }
+    return total < cap ? total : cap;
 }
 
-// Link walks from every entry cell; SUM: also sum av along the path (the
-// adjoint's pass 1).  Results go to ll[p] / sl[p] by ring index.
-template <bool SUM>
-__device__ inline void link_walks(const Geo &g, const WTile &Tl, const Layout &L, const uint32_t *cb,
-                                  const float *av, uint64_t entry, uint16_t *ll, float *sl,
-                                  uint32_t *status)
+// ---------------------------------------------------------------- walks ---
+
+// Algorithm 2's link of a walk from cell `start` that ended at cell `cur`
+// (code `code`) before the cell whose byte is `nb`: the ring index of `cur`
+// when its flow leaves the tile into the raster, else FlowTerminates.
+__device__ inline uint16_t walk_link(const WTile &Tl, int cur, uint32_t code, uint32_t nb)
 {
-    Dispenser ds;
-    ds.init(entry);
-    int qr = -1, qc = -1, r = -1, c = -1, steps = 0;
-    const int max_steps = Tl.h * Tl.w;
+    if (code >= (uint32_t)kNoFlow || (nb & 15u) != kFrameTile) return kLinkTerm;
+    int r, c;
+    idx_rc(Tl, cur, r, c);
+    return (uint16_t)ring_index(r, c, Tl.h, Tl.w);
+}
+
+__device__ inline int ring_of_idx(const WTile &Tl, int idx)
+{
+    int r, c;
+    idx_rc(Tl, idx, r, c);
+    return ring_index(r, c, Tl.h, Tl.w);
+}
+
+// Forward walks from every source (and, when LINKS, link walks from every
+// entry, in the same loop).  avp[idx] holds each cell's seed and receives
+// its accumulation.  Returns the number of cells this lane finished.
+template <typename T, bool LINKS>
+__device__ inline int fwd_walks(const WTile &Tl, uint8_t *cb8, uint32_t *cbw, T *avp, uint16_t *q,
+                                uint32_t qcap, uint64_t src, uint64_t ent, uint16_t *ll,
+                                uint32_t *status)
+{
+    const int S = Tl.S;
+    int visited = 0;
+    uint32_t ntask = fill_queue(q, qcap, Tl, src, ent), head = 0;
+    bool more = __ballot(src != 0 || ent != 0) != 0;
+    int cur = -1, start = 0, steps = 0;
     uint32_t code = 0;
-    float s = 0.0f;
+    bool link = false;
+    T a = (T)0;
+    const int max_steps = Tl.h * Tl.w;
     for (;;) {
-        bool idle = r < 0;
-        if (!__any(!idle) && ds.empty()) break;
-        int nr, nc;
-        if (ds.take(idle, entry, nr, nc)) {
-            qr = r = nr;
-            qc = c = nc;
-            code = cbyte(cb, L, r, c) & 15u;
-            s = 0.0f;
-            steps = 0;
+        uint64_t idle = __ballot(cur < 0);
+        if (head >= ntask) {
+            if (more) {
+                // the queue has been handed out completely: refill it
+                ntask = fill_queue(q, qcap, Tl, src, ent);
+                head = 0;
+                more = __ballot(src != 0 || ent != 0) != 0;
+            } else if (idle == ~0ull) {
+                break;
+            }
         }
-        if (r < 0) continue;
-        if (SUM) s += av[L.ai(r, c)];
-        bool end = true;
-        if (++steps > max_steps) {
-            // longer than the tile has cells: the path runs into a cycle
-            set_status(status, kStatusCycle);
-            code = kNoFlow;
-        }
-        if (code < (uint32_t)kNoFlow) {
-            int rr = r + dir_dr(code), cc = c + dir_dc(code);
-            if (rr >= 0 && rr < Tl.h && cc >= 0 && cc < Tl.w) {
-                uint32_t kn = cbyte(cb, L, rr, cc) & 15u;
-                if (kn < (uint32_t)kNoData) {
-                    r = rr;
-                    c = cc;
-                    code = kn;
-                    end = false;
+        if (idle != 0 && head < ntask) {
+            uint32_t j = head + lanes_below(idle);
+            if (cur < 0 && j < ntask) {
+                uint32_t t = q[j];
+                cur = (int)(t & 0x7FFFu);
+                link = LINKS && (t & 0x8000u);
+                start = cur;
+                steps = 0;
+                code = cb8[cur] & 15u;
+                if (!link) {
+                    a = avp[cur];
+                    ++visited;
                 }
             }
+            uint32_t nidle = (uint32_t)__popcll(idle);
+            head = (ntask - head < nidle) ? ntask : head + nidle;
         }
-        if (end) {
-            int p = ring_index(qr, qc, Tl.h, Tl.w);
-            ll[p] = link_for(g, Tl, qr, qc, r, c, code);
-            if (SUM) sl[p] = s;
-            r = -1;
+        if (cur >= 0) {
+            const int ni = cur + dir_off(code, S);
+            const uint32_t nb = cb8[ni];
+            const T sv = avp[ni];
+            const uint32_t nk = nb & 15u;
+            bool end = code >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData;
+            if (LINKS && link && ++steps > max_steps) {
+                // longer than the tile has cells: the path runs into a cycle
+                set_status(status, kStatusCycle);
+                end = true;
+            }
+            bool stop = end;
+            if (!end && !link) {
+                if ((nb >> 4) != 0u) {
+                    // confluence: add this donor's total, count the arrival
+                    const int sh = 8 * (ni & 3) + 4;
+                    atomicAdd(&avp[ni], a);
+                    uint32_t old = atomicSub(&cbw[ni >> 2], 1u << sh);
+                    if (((old >> sh) & 15u) == 1u) {
+                        a = avp[ni];
+                        ++visited;
+                    } else {
+                        stop = true;
+                    }
+                } else {
+                    a += sv;
+                    avp[ni] = a;
+                    ++visited;
+                }
+            }
+            if (LINKS && link && end) ll[ring_of_idx(Tl, start)] = walk_link(Tl, cur, code, nb);
+            if (stop) {
+                cur = -1;
+            } else {
+                cur = ni;
+                code = nk;
+            }
         }
-    }
-}
-
-// Forward walks over all sources; returns the number of cells finished by
-// this lane (sources included).
-template <typename T>
-__device__ inline int forward_walks(const WTile &Tl, const Layout &L, uint32_t *cb, T *av,
-                                    uint64_t src)
-{
-    Dispenser ds;
-    ds.init(src);
-    Walker<T> wk;
-    int visited = 0;
-    for (;;) {
-        bool idle = wk.r < 0;
-        if (!__any(!idle) && ds.empty()) break;
-        int nr, nc;
-        if (ds.take(idle, src, nr, nc)) {
-            wk.r = nr;
-            wk.c = nc;
-            wk.code = cbyte(cb, L, nr, nc) & 15u;
-            wk.a = av[L.ai(nr, nc)];
-            ++visited;
-        }
-        if (wk.r < 0) continue;
-        if (!fwd_step(wk, Tl, L, cb, av, visited)) wk.r = -1;
     }
     return visited;
 }
 
-__device__ inline int wave_sum(int v)
+// Link walks from every entry (at most the ring size, so one queue fill):
+// the link and the sum of avp along the in-tile path (the adjoint's pass 1).
+__device__ inline void link_sum_walks(const WTile &Tl, const uint8_t *cb8, const float *avp,
+                                      uint16_t *q, uint32_t qcap, uint64_t ent, uint16_t *ll,
+                                      float *Sg, uint32_t *status)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const int S = Tl.S;
+    uint64_t none = 0;
+    uint32_t ntask = fill_queue(q, qcap, Tl, ent, none), head = 0;
+    int cur = -1, start = 0, steps = 0;
+    uint32_t code = 0;
+    float s = 0.0f;
+    const int max_steps = Tl.h * Tl.w;
+    for (;;) {
+        uint64_t idle = __ballot(cur < 0);
+        if (head >= ntask && idle == ~0ull) break;
+        if (idle != 0 && head < ntask) {
+            uint32_t j = head + lanes_below(idle);
+            if (cur < 0 && j < ntask) {
+                cur = (int)(q[j] & 0x7FFFu);
+                start = cur;
+                steps = 0;
+                code = cb8[cur] & 15u;
+                s = avp[cur];
+            }
+            uint32_t nidle = (uint32_t)__popcll(idle);
+            head = (ntask - head < nidle) ? ntask : head + nidle;
+        }
+        if (cur >= 0) {
+            const int ni = cur + dir_off(code, S);
+            const uint32_t nb = cb8[ni];
+            const float sv = avp[ni];
+            const uint32_t nk = nb & 15u;
+            bool end = code >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData;
+            if (++steps > max_steps) {
+                set_status(status, kStatusCycle);
+                end = true;
+            }
+            if (end) {
+                int p = ring_of_idx(Tl, start);
+                ll[p] = walk_link(Tl, cur, code, nb);
+                Sg[p] = s;
+                cur = -1;
+            } else {
+                s += sv;
+                cur = ni;
+                code = nk;
+            }
+        }
+    }
+}
+
+// Upstream walks for the adjoint: lambda(d) = g(d) + lambda(receiver).  avp
+// holds the seeds (g, plus the downstream sum at exits) and receives lambda.
+// A walk starts at a finished cell and moves to its first donor; the other
+// donors of a branching cell are finished on the spot and queued (a ring of
+// qcap entries; when full, they go to the pending bitmap pend, one 64-bit
+// row mask per tile row, which also holds the roots not yet queued).
+// Returns the number of cells this lane finished, roots excluded.
+__device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, uint16_t *q,
+                               uint32_t qcap, uint64_t roots, uint64_t *pend)
+{
+    const int S = Tl.S;
+    const int lane = lane_id();
+    int visited = 0;
+    uint64_t none = 0;
+    uint32_t head = 0, tail = fill_queue(q, qcap, Tl, roots, none);
+    pend[lane] = roots;  // roots that did not fit
+    bool more = __ballot(roots != 0) != 0;
+    int cur = -1;
+    float a = 0.0f;
+    for (;;) {
+        uint64_t idle = __ballot(cur < 0);
+        if (head >= tail) {
+            if (more) {
+                // queue empty: move pending cells into it
+                uint64_t m = pend[lane];
+                pend[lane] = 0;
+                head = 0;
+                tail = fill_queue(q, qcap, Tl, m, none);
+                if (m != 0) pend[lane] = m;
+                more = __ballot(m != 0) != 0;
+            } else if (idle == ~0ull) {
+                break;
+            }
+        }
+        if (idle != 0 && head < tail) {
+            uint32_t j = head + lanes_below(idle);
+            if (cur < 0 && j < tail) {
+                cur = q[j & (qcap - 1)];
+                a = avp[cur];
+            }
+            uint32_t nidle = (uint32_t)__popcll(idle);
+            head = (tail - head < nidle) ? tail : head + nidle;
+        }
+        uint32_t rest = 0;
+        const int from = cur;
+        const float af = a;
+        if (cur >= 0) {
+            uint32_t mask = cb8[cur];
+            if (mask == 0) {
+                cur = -1;
+            } else {
+                uint32_t j0 = (uint32_t)__ffs(mask) - 1u;
+                rest = mask & (mask - 1u);
+                const int d = cur + dir_off(j0, S);
+                a += avp[d];
+                avp[d] = a;
+                ++visited;
+                cur = d;
+            }
+        }
+        // side donors: finish and queue them
+        while (__ballot(rest != 0) != 0) {
+            const bool has = rest != 0;
+            int d = 0;
+            if (has) {
+                uint32_t j = (uint32_t)__ffs(rest) - 1u;
+                rest &= rest - 1u;
+                d = from + dir_off(j, S);
+                avp[d] += af;
+                ++visited;
+            }
+            uint64_t b = __ballot(has);
+            uint32_t slot = tail + lanes_below(b);
+            uint32_t room = qcap - (tail - head);
+            if (has) {
+                if (slot - tail < room) {
+                    q[slot & (qcap - 1)] = (uint16_t)d;
+                } else {
+                    int rr, cc;
+                    idx_rc(Tl, d, rr, cc);
+                    atomicOr(reinterpret_cast<unsigned long long *>(&pend[rr]), 1ull << cc);
+                }
+            }
+            uint32_t nb = (uint32_t)__popcll(b);
+            if (nb > room) {
+                more = true;
+                nb = room;
+            }
+            tail += nb;
+        }
+    }
+    return visited;
 }
 
 }  // namespace wk
 
+// ------------------------------------------------------------ LDS layout --
+// Per tile: cell bytes (with frame), values (one per cell, frame columns
+// included, frame rows excluded), the queue, and a tail area.  Speculative
+// value reads of frame rows land in the cell bytes (before) or the queue
+// (after), both at least 4 (S + 1) bytes long.
+struct WLayout {
+    int av, q, tail, total;
+    uint32_t qcap;
+};
+
+enum WalkKind { kWalkFwd1 = 0, kWalkFwd2 = 1, kWalkAdj1 = 2, kWalkAdj2 = 3 };
+
+__host__ __device__ inline WLayout walk_layout(int th, int tw, int kind)
+{
+    WLayout L;
+    const int S = tw + 2;
+    int cb = (th + 2) * S;
+    if (cb < 4 * (S + 1)) cb = 4 * (S + 1);
+    L.av = (cb + 15) & ~15;
+    L.q = L.av + th * S * 4;
+    L.qcap = kind == kWalkAdj1 ? 256u : 512u;  // entries <= ring size <= 252
+    L.tail = L.q + (int)L.qcap * 2;
+    int tail = 0;
+    if (kind == kWalkFwd1 || kind == kWalkAdj1) tail = (ring_size(th, tw) * 2 + 15) & ~15;
+    if (kind == kWalkAdj2) tail = 64 * 8;
+    L.total = L.tail + tail;
+    return L;
+}
+
 // ---------------------------------------------------------------- kernels --
+// Coalesced row transfers between a global array (row-major, `cols` wide)
+// and the tile's LDS values: lane = column, one row per step.
+template <typename T, typename F>
+__device__ inline void rows_in(const wk::WTile &Tl, const Geo &g, T *avp, F load)
+{
+    const int c = wk::lane_id();
+    if (c >= Tl.w) return;
+#pragma unroll 8
+    for (int r = 0; r < Tl.h; ++r) avp[wk::cidx(Tl, r, c)] = load((Tl.r0 + r) * g.cols + Tl.c0 + c);
+}
+
+// out = avp for data cells, 0 for NoData (valid: this lane's row mask)
+template <typename T>
+__device__ inline void rows_out(const wk::WTile &Tl, const Geo &g, const T *avp, uint64_t valid, T *out)
+{
+    const int c = wk::lane_id();
+    const uint32_t vlo = (uint32_t)valid, vhi = (uint32_t)(valid >> 32);
+    for (int r = 0; r < Tl.h; ++r) {
+        uint32_t lo = __builtin_amdgcn_readlane(vlo, r), hi = __builtin_amdgcn_readlane(vhi, r);
+        uint64_t row_valid = ((uint64_t)hi << 32) | lo;
+        if (c < Tl.w) {
+            T v = ((row_valid >> c) & 1ull) ? avp[wk::cidx(Tl, r, c)] : (T)0;
+            out[(Tl.r0 + r) * g.cols + Tl.c0 + c] = v;
+        }
+    }
+}
+
 // One wavefront per tile (tiles up to 64 x 64).  Forward:
-//   PASS 1: A_loc and links -> one record per perimeter cell, resolve state zeroed
+//   PASS 1: A_loc and links -> one record per perimeter cell; resolve state zeroed
 //   PASS 2: seeds w + cross-tile inflow -> A for every cell
+// Resolve state: indeg = children in the exit forest (graph_build); unit
+// counts keep (inflow sum << 32 | arrivals) in acc; float weights keep the
+// double sum in acc and arrivals in cnt.
 template <int PASS, typename T, typename V, typename E>
 __global__ void __launch_bounds__(64)
 fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
          uint16_t *__restrict__ link, T *__restrict__ aloc, uint32_t *__restrict__ indeg,
-         V *__restrict__ acc, E *__restrict__ ext, T *__restrict__ out, uint32_t *status)
+         uint32_t *__restrict__ cnt, V *__restrict__ acc, E *__restrict__ ext, T *__restrict__ out,
+         uint32_t *status)
 {
     using namespace wk;
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint8_t lds8[];
     const WTile Tl = wtile_of(g, blockIdx.x);
-    const Layout L(g.tw);
-    uint32_t *cb = lds;
-    T *av = reinterpret_cast<T *>(lds + g.th * L.cbs);
-    uint16_t *ll = reinterpret_cast<uint16_t *>(lds + g.th * (L.cbs + L.as));
-    const int r = lane_id();
+    const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkFwd1 : kWalkFwd2);
+    uint8_t *cb8 = lds8;
+    uint32_t *cbw = reinterpret_cast<uint32_t *>(lds8);
+    T *avp = reinterpret_cast<T *>(lds8 + L.av) - Tl.S;
+    uint16_t *q = reinterpret_cast<uint16_t *>(lds8 + L.q);
+    uint16_t *ll = reinterpret_cast<uint16_t *>(lds8 + L.tail);
+    const int lane = lane_id();
 
-    Setup S = setup_tile<0, PASS == 1>(dirs, g, Tl, L, cb, status);
+    Setup St = setup_tile<0, PASS == 1>(dirs, g, Tl, cb8, status);
 
     // seeds: own weight (+ resolved inflow on the perimeter in pass 2)
-    if (r < Tl.h) {
-        const float *wrow = w ? w + (Tl.r0 + r) * g.cols + Tl.c0 : nullptr;
-        const bool edge_row = (r == 0 || r == Tl.h - 1);
-        for (int c = 0; c < Tl.w; ++c) {
-            T s = wrow ? (T)wrow[c] : (T)1;
-            if (PASS == 2 && (edge_row || c == 0 || c == Tl.w - 1)) {
-                int p = ring_index(r, c, Tl.h, Tl.w);
-                s += (T)ext[Tl.base + p];
-            }
-            av[L.ai(r, c)] = s;
-        }
-    }
-    for (int p = r; p < Tl.P; p += 64) ll[p] = kLinkTerm;
-    __syncthreads();
-
-    int visited = forward_walks<T>(Tl, L, cb, av, S.src);
-    if (wave_sum(visited) != wave_sum(S.valid) && r == 0) set_status(status, kStatusCycle);
-
+    if (w) rows_in(Tl, g, avp, [&](int64_t i) { return (T)w[i]; });
+    else rows_in(Tl, g, avp, [&](int64_t) { return (T)1; });
     if (PASS == 2) {
         __syncthreads();
-        if (r < Tl.h) {
-            T *orow = out + (Tl.r0 + r) * g.cols + Tl.c0;
-            for (int c = 0; c < Tl.w; ++c) {
-                uint32_t k = cbyte(cb, L, r, c) & 15u;
-                orow[c] = k < (uint32_t)kNoData ? av[L.ai(r, c)] : (T)0;
-            }
+        for (int p = lane; p < Tl.P; p += 64) {
+            int qr, qc;
+            ring_cell(p, Tl.h, Tl.w, qr, qc);
+            avp[cidx(Tl, qr, qc)] += (T)ext[Tl.base + p];
         }
-        for (int p = r; p < Tl.P; p += 64) {
+    } else {
+        for (int p = lane; p < Tl.P; p += 64) ll[p] = kLinkTerm;
+    }
+    __syncthreads();
+
+    int visited = fwd_walks<T, PASS == 1>(Tl, cb8, cbw, avp, q, L.qcap, St.src, St.entry, ll, status);
+    if (wave_sum(visited) != wave_sum(__popcll(St.valid)) && lane == 0) set_status(status, kStatusCycle);
+    __syncthreads();
+
+    if (PASS == 2) {
+        rows_out(Tl, g, avp, St.valid, out);
+        // an exit whose children never all arrived sits on a cycle of exits
+        for (int p = lane; p < Tl.P; p += 64) {
             int64_t id = Tl.base + p;
             if (link[id] != kLinkExt) continue;
-            bool pending = indeg ? indeg[id] != 0 : (uint32_t)acc[id] != 0;
-            if (pending) set_status(status, kStatusCycle);
+            uint32_t arrived = cnt ? cnt[id] : (uint32_t)(unsigned long long)acc[id];
+            if (arrived != indeg[id]) set_status(status, kStatusCycle);
         }
         return;
     }
 
-    link_walks<false>(g, Tl, L, cb, nullptr, S.entry, ll, nullptr, status);
-    __syncthreads();
-    for (int p = r; p < Tl.P; p += 64) {
+    for (int p = lane; p < Tl.P; p += 64) {
         int qr, qc;
         ring_cell(p, Tl.h, Tl.w, qr, qc);
-        uint32_t k = cbyte(cb, L, qr, qc) & 15u;
+        const int idx = cidx(Tl, qr, qc);
+        uint32_t k = cb8[idx] & 15u;
         uint16_t Lk;
         if (k >= (uint32_t)kNoData) Lk = kLinkNoData;
-        else {
-            uint16_t out_link = link_for(g, Tl, qr, qc, qr, qc, k);
-            Lk = (out_link == kLinkExt) ? kLinkExt : ll[p];
-        }
+        else if (k < (uint32_t)kNoFlow && (cb8[idx + dir_off(k, Tl.S)] & 15u) == kFrameTile) Lk = kLinkExt;
+        else Lk = ll[p];
         int64_t id = Tl.base + p;
         link[id] = Lk;
-        aloc[id] = k < (uint32_t)kNoData ? av[L.ai(qr, qc)] : (T)0;
-        if (indeg) indeg[id] = 0;
+        aloc[id] = k < (uint32_t)kNoData ? avp[idx] : (T)0;
+        indeg[id] = 0;
+        if (cnt) cnt[id] = 0;
         acc[id] = (V)0;
         ext[id] = (E)0;
     }
 }
 
-}  // namespace d8
-
-namespace d8 {
-namespace wk {
-
-// Upstream walks for the adjoint: lambda(d) = g(d) + lambda(receiver).  A walk
-// starts at a root (finished) and moves to one donor at a time; the other
-// donors of a branching cell are finished on the spot and queued in a bitmap
-// (one 64-bit row mask per tile row plus a summary) for idle lanes.
-__device__ inline int upstream_walks(const WTile &Tl, const Layout &L, const uint32_t *cb,
-                                     float *av, uint64_t roots, uint32_t *pend, uint32_t *summ)
-{
-    Dispenser ds;
-    ds.init(roots);
-    int r = -1, c = -1, visited = 0;
-    float a = 0.0f;
-    const int lane = lane_id();
-    for (;;) {
-        bool idle = r < 0;
-        uint64_t sm = ((uint64_t)summ[1] << 32) | summ[0];
-        if (!__any(!idle) && ds.empty() && sm == 0) break;
-        int nr, nc;
-        if (ds.take(idle, roots, nr, nc)) {
-            r = nr;
-            c = nc;
-            a = av[L.ai(r, c)];
-            ++visited;
-            idle = false;
-        }
-        // queued donors, once the roots are handed out
-        if (ds.empty()) {
-            uint64_t free_lanes = __ballot(idle);
-            bool got = false;
-            while (free_lanes != 0 && sm != 0) {
-                int R = __ffsll((unsigned long long)sm) - 1;
-                uint64_t rb = ((uint64_t)pend[2 * R + 1] << 32) | pend[2 * R];
-                int k = __popcll(free_lanes) < __popcll(rb) ? __popcll(free_lanes) : __popcll(rb);
-                if (idle && !got) {
-                    bool mine = (free_lanes >> lane) & 1ull;
-                    int rank = __popcll(free_lanes & ((1ull << lane) - 1ull));
-                    if (mine && rank < k) {
-                        r = R;
-                        c = nth_set_bit(rb, rank);
-                        a = av[L.ai(r, c)];
-                        got = true;
-                    }
-                }
-                rb = clear_lowest(rb, k);
-                free_lanes = clear_lowest(free_lanes, k);
-                if (lane == 0) {
-                    pend[2 * R] = (uint32_t)rb;
-                    pend[2 * R + 1] = (uint32_t)(rb >> 32);
-                }
-                if (rb == 0) {
-                    sm &= ~(1ull << R);
-                    if (lane == 0) {
-                        summ[0] = (uint32_t)sm;
-                        summ[1] = (uint32_t)(sm >> 32);
-                    }
-                }
-            }
-        }
-        if (r < 0) continue;
-        uint32_t mask = cbyte(cb, L, r, c);
-        if (mask == 0) {
-            r = -1;
-            continue;
-        }
-        int j0 = __ffs(mask) - 1;
-        uint32_t rest = mask & (mask - 1u);
-        while (rest) {
-            int j = __ffs(rest) - 1;
-            rest &= rest - 1u;
-            // the donor in direction j sits at offset dir(j)
-            int dr = r + dir_dr(j), dc = c + dir_dc(j);
-            const int ai = L.ai(dr, dc);
-            av[ai] += a;
-            ++visited;
-            atomicOr(&pend[2 * dr + (dc >> 5)], 1u << (dc & 31));
-            atomicOr(&summ[dr >> 5], 1u << (dr & 31));
-        }
-        r += dir_dr(j0);
-        c += dir_dc(j0);
-        const int ai = L.ai(r, c);
-        a += av[ai];
-        av[ai] = a;
-        ++visited;
-    }
-    return visited;
-}
-
-}  // namespace wk
-
 // Adjoint, one wavefront per tile.
-//   PASS 1: per perimeter cell, the link and the sum of g along its in-tile path
+//   PASS 1: per perimeter cell, the link and (entries) the sum of g along its in-tile path
 //   PASS 2: lambda for every cell, exits seeded with the resolved downstream sum
 template <int PASS>
 __global__ void __launch_bounds__(64)
 adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
-         uint16_t *__restrict__ link, float *__restrict__ S, const double *__restrict__ mu0,
+         uint16_t *__restrict__ link, float *__restrict__ Sg, const double *__restrict__ mu0,
          const double *__restrict__ mu1, const uint32_t *__restrict__ jstate,
          float *__restrict__ out, uint32_t *status)
 {
     using namespace wk;
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint8_t lds8[];
     const WTile Tl = wtile_of(g, blockIdx.x);
-    const Layout L(g.tw);
-    uint32_t *cb = lds;
-    float *av = reinterpret_cast<float *>(lds + g.th * L.cbs);
-    uint32_t *tail = lds + g.th * (L.cbs + L.as);
-    const int r = lane_id();
+    const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkAdj1 : kWalkAdj2);
+    uint8_t *cb8 = lds8;
+    float *avp = reinterpret_cast<float *>(lds8 + L.av) - Tl.S;
+    uint16_t *q = reinterpret_cast<uint16_t *>(lds8 + L.q);
+    const int lane = lane_id();
 
-    Setup St = setup_tile<PASS == 1 ? 1 : 2, PASS == 1>(dirs, g, Tl, L, cb, status);
-    if (r < Tl.h) {
-        const float *grow = gin + (Tl.r0 + r) * g.cols + Tl.c0;
-        for (int c = 0; c < Tl.w; ++c) av[L.ai(r, c)] = grow[c];
-    }
+    Setup St = setup_tile<PASS == 1 ? 1 : 2, PASS == 1>(dirs, g, Tl, cb8, status);
+    rows_in(Tl, g, avp, [&](int64_t i) { return gin[i]; });
 
     if (PASS == 1) {
-        uint16_t *ll = reinterpret_cast<uint16_t *>(tail);
-        float *sl = reinterpret_cast<float *>(tail + (Tl.P + 1) / 2);
-        for (int p = r; p < Tl.P; p += 64) {
-            ll[p] = kLinkTerm;
-            sl[p] = 0.0f;
-        }
+        uint16_t *ll = reinterpret_cast<uint16_t *>(lds8 + L.tail);
+        for (int p = lane; p < Tl.P; p += 64) ll[p] = kLinkTerm;
         __syncthreads();
-        link_walks<true>(g, Tl, L, cb, av, St.entry, ll, sl, status);
+        link_sum_walks(Tl, cb8, avp, q, L.qcap, St.entry, ll, Sg + Tl.base, status);
         __syncthreads();
-        for (int p = r; p < Tl.P; p += 64) {
+        for (int p = lane; p < Tl.P; p += 64) {
             int qr, qc;
             ring_cell(p, Tl.h, Tl.w, qr, qc);
-            uint32_t k = cbyte(cb, L, qr, qc) & 15u;
+            const int idx = cidx(Tl, qr, qc);
+            uint32_t k = cb8[idx] & 15u;
             uint16_t Lk;
             if (k >= (uint32_t)kNoData) Lk = kLinkNoData;
-            else Lk = (link_for(g, Tl, qr, qc, qr, qc, k) == kLinkExt) ? kLinkExt : ll[p];
+            else if (k < (uint32_t)kNoFlow && (cb8[idx + dir_off(k, Tl.S)] & 15u) == kFrameTile) Lk = kLinkExt;
+            else Lk = ll[p];
             link[Tl.base + p] = Lk;
-            S[Tl.base + p] = sl[p];
         }
         return;
     }
 
-    // pass 2: exits get the downstream sum mu of the cell they flow into
+    // pass 2: every perimeter cell gets the downstream sum of the cell its
+    // flow enters in another tile (zero unless it is an exit)
     const double *mu = jstate[0] == 1 ? mu1 : mu0;
-    uint32_t *pend = tail;       // 2 words per row
-    uint32_t *summ = tail + 128;  // 2 words
-    for (int i = r; i < 130; i += 64) tail[i] = 0;
-    for (int p = r; p < Tl.P; p += 64) {
+    uint64_t *pend = reinterpret_cast<uint64_t *>(lds8 + L.tail);
+    __syncthreads();
+    for (int p = lane; p < Tl.P; p += 64) {
         int qr, qc;
         ring_cell(p, Tl.h, Tl.w, qr, qc);
-        uint32_t k = dirs[(Tl.r0 + qr) * g.cols + Tl.c0 + qc];
-        if (k > (uint32_t)kNoData) continue;
-        if (link_for(g, Tl, qr, qc, qr, qc, k) == kLinkExt) av[L.ai(qr, qc)] += (float)mu[Tl.base + p];
+        avp[cidx(Tl, qr, qc)] += (float)mu[Tl.base + p];
     }
     __syncthreads();
-    int visited = upstream_walks(Tl, L, cb, av, St.root, pend, summ);
-    if (wave_sum(visited) != wave_sum(St.valid) && r == 0) set_status(status, kStatusCycle);
+    int visited = up_walks(Tl, cb8, avp, q, L.qcap, St.root, pend);
+    if (wave_sum(visited + __popcll(St.root)) != wave_sum(__popcll(St.valid)) && lane == 0)
+        set_status(status, kStatusCycle);
     __syncthreads();
-    if (r < Tl.h) {
-        float *orow = out + (Tl.r0 + r) * g.cols + Tl.c0;
-        const uint8_t *drow = dirs + (Tl.r0 + r) * g.cols + Tl.c0;
-        for (int c = 0; c < Tl.w; ++c) {
-            uint32_t k = drow[c];
-            orow[c] = k < (uint32_t)kNoData ? av[L.ai(r, c)] : 0.0f;
-        }
-    }
+    rows_out(Tl, g, avp, St.valid, out);
 }
 
-// LDS bytes per tile for the walker kernels
-__host__ inline size_t walk_lds_bytes(int th, int tw)
+__host__ inline size_t walk_lds_bytes(int th, int tw, int kind)
 {
-    wk::Layout L(tw);
-    size_t base = ((size_t)th * L.cbs + (size_t)th * L.as) * 4;
-    size_t tail = (size_t)ring_size(th, tw) * 6 + 8;  // links + sums (pass 1)
-    size_t pend = 130 * 4;                              // pending bitmap (adjoint pass 2)
-    return base + (tail > pend ? tail : pend) + 16;
+    return (size_t)walk_layout(th, tw, kind).total;
 }
 
 }  // namespace d8
