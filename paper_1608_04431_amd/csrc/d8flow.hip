@@ -197,7 +197,8 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
 
     int ntiles = g.nty * g.ntx;
     const int thr = kTileThreads;
-    size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1), lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2);
+    size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1, (int)sizeof(FwdLds<1, T>));
+    size_t lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2, (int)sizeof(FwdLds<2, T>));
     if (allow_lds(fwd_walk<1, T, V, E>, lds1) || allow_lds(fwd_walk<2, T, V, E>, lds2))
         return D8_EHIP;
 

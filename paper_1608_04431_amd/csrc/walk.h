@@ -28,6 +28,8 @@
 // operations is fixed by the input.
 #pragma once
 
+#include <type_traits>
+
 #include "d8_common.h"
 
 namespace d8 {
@@ -90,6 +92,28 @@ __device__ inline int lane_id() { return __lane_id(); }
 __device__ inline uint32_t lanes_below(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Values kept in LDS and the type they are summed in: local unit counts of
+// a tile (at most 64 x 64) fit 16 bits.
+template <typename VT> struct Acc { using type = VT; };
+template <> struct Acc<uint16_t> { using type = uint32_t; };
+
+__device__ inline void lds_add(float *p, float v) { atomicAdd(p, v); }
+__device__ inline void lds_add(uint32_t *p, uint32_t v) { atomicAdd(p, v); }
+// 16-bit slot: add to its 32-bit word (sums stay below 2^16, no carry out)
+__device__ inline void lds_add(uint16_t *p, uint32_t v)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    atomicAdd(reinterpret_cast<uint32_t *>(a & ~(uintptr_t)3), v << ((a & 2u) * 8u));
+}
+
+// Makes the compiler produce v here: a value read next to another LDS read
+// is then fetched with it instead of inside a later branch.
+template <typename T>
+__device__ inline void keep_read(T &v)
+{
+    asm volatile("" : "+v"(v));
 }
 
 __device__ inline int wave_sum(int v)
@@ -413,12 +437,25 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
 }
 
 // ---------------------------------------------------------------- queue ---
-// Start cells wait in an LDS array of 16-bit entries: cell index, bit 15 =
-// link walk.  fill_queue appends the cells of every lane's masks (lane r =
-// tile row r, row-major order) at positions 0.. of the queue, at most `cap`,
-// and clears the bits it wrote; returns how many it wrote (wave-uniform).
-__device__ inline uint32_t fill_queue(uint16_t *q, uint32_t cap, const WTile &Tl, uint64_t &m0,
-                                      uint64_t &m1)
+// Start cells wait in an LDS array of 32-bit entries: bits 0..12 the cell
+// index, 13..20 the cell's byte (code, or donor mask for upstream walks),
+// bit 21 = link walk, bits 22..29 the ring index of a link walk's start.
+constexpr uint32_t kQIdx = 0x1FFFu;
+constexpr int kQByte = 13;
+constexpr uint32_t kQLink = 1u << 21;
+constexpr int kQRing = 22;
+
+// Link walk results kept in LDS until the records are written: the index of
+// the exit cell reached, or one of these.
+constexpr uint16_t kLlTerm = 0xFFFF;
+constexpr uint16_t kLlCycle = 0xFFFE;
+
+// fill_queue appends the cells of every lane's masks (lane r = tile row r,
+// row-major order; m0's cells are plain walks, m1's link walks) at positions
+// 0.. of the queue, at most `cap`, and clears the bits it wrote; returns how
+// many it wrote (wave-uniform).
+__device__ inline uint32_t fill_queue(uint32_t *q, uint32_t cap, const WTile &Tl, const uint8_t *cb8,
+                                      uint32_t byte_mask, uint64_t &m0, uint64_t &m1)
 {
     const int lane = lane_id();
     uint32_t n = (uint32_t)(__popcll(m0) + __popcll(m1));
@@ -428,33 +465,23 @@ __device__ inline uint32_t fill_queue(uint16_t *q, uint32_t cap, const WTile &Tl
         uint32_t t = __shfl_up(incl, o, 64);
         if (lane >= o) incl += t;
     }
-    uint32_t total = __shfl(incl, 63, 64);
+    uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     uint32_t pos = incl - n;
     const int rowbase = (lane + 1) * Tl.S + 1;
     while (m0 != 0 && pos < cap) {
         int c = __ffsll((unsigned long long)m0) - 1;
         m0 &= m0 - 1ull;
-        q[pos++] = (uint16_t)(rowbase + c);
+        const int idx = rowbase + c;
+        q[pos++] = (uint32_t)idx | ((cb8[idx] & byte_mask) << kQByte);
     }
     while (m1 != 0 && pos < cap) {
         int c = __ffsll((unsigned long long)m1) - 1;
         m1 &= m1 - 1ull;
-        q[pos++] = (uint16_t)((rowbase + c) | 0x8000);
+        const int idx = rowbase + c;
+        q[pos++] = (uint32_t)idx | ((cb8[idx] & byte_mask) << kQByte) | kQLink |
+                   ((uint32_t)ring_index(lane, c, Tl.h, Tl.w) << kQRing);
     }
     return total < cap ? total : cap;
-}
-
-// ---------------------------------------------------------------- walks ---
-
-// Algorithm 2's link of a walk from cell `start` that ended at cell `cur`
-// (code `code`) before the cell whose byte is `nb`: the ring index of `cur`
-// when its flow leaves the tile into the raster, else FlowTerminates.
-__device__ inline uint16_t walk_link(const WTile &Tl, int cur, uint32_t code, uint32_t nb)
-{
-    if (code >= (uint32_t)kNoFlow || (nb & 15u) != kFrameTile) return kLinkTerm;
-    int r, c;
-    idx_rc(Tl, cur, r, c);
-    return (uint16_t)ring_index(r, c, Tl.h, Tl.w);
 }
 
 __device__ inline int ring_of_idx(const WTile &Tl, int idx)
@@ -464,29 +491,41 @@ __device__ inline int ring_of_idx(const WTile &Tl, int idx)
     return ring_index(r, c, Tl.h, Tl.w);
 }
 
+// Algorithm 2's link from a link-walk result.
+__device__ inline uint16_t link_of(const WTile &Tl, uint16_t v, uint32_t *status)
+{
+    if (v == kLlCycle) {
+        set_status(status, kStatusCycle);
+        return kLinkTerm;
+    }
+    return v == kLlTerm ? kLinkTerm : (uint16_t)ring_of_idx(Tl, v);
+}
+
+// ---------------------------------------------------------------- walks ---
+
 // Forward walks from every source (and, when LINKS, link walks from every
 // entry, in the same loop).  avp[idx] holds each cell's seed and receives
 // its accumulation.  Returns the number of cells this lane finished.
-template <typename T, bool LINKS>
-__device__ inline int fwd_walks(const WTile &Tl, uint8_t *cb8, uint32_t *cbw, T *avp, uint16_t *q,
-                                uint32_t qcap, uint64_t src, uint64_t ent, uint16_t *ll,
-                                uint32_t *status)
+template <typename VT, bool LINKS>
+__device__ inline int fwd_walks(const WTile &Tl, uint8_t *cb8, uint32_t *cbw, VT *avp, uint32_t *q,
+                                uint32_t qcap, uint64_t src, uint64_t ent, uint16_t *ll)
 {
+    using T = typename Acc<VT>::type;
     const int S = Tl.S;
     int visited = 0;
-    uint32_t ntask = fill_queue(q, qcap, Tl, src, ent), head = 0;
+    uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent));
+    uint32_t head = 0;
     bool more = __ballot(src != 0 || ent != 0) != 0;
-    int cur = -1, start = 0, steps = 0;
-    uint32_t code = 0;
-    bool link = false;
+    int cur = -1, steps = 0;
+    uint32_t code = 0, info = 0;
     T a = (T)0;
     const int max_steps = Tl.h * Tl.w;
     for (;;) {
-        uint64_t idle = __ballot(cur < 0);
+        const uint64_t idle = __ballot(cur < 0);
         if (head >= ntask) {
             if (more) {
                 // the queue has been handed out completely: refill it
-                ntask = fill_queue(q, qcap, Tl, src, ent);
+                ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent));
                 head = 0;
                 more = __ballot(src != 0 || ent != 0) != 0;
             } else if (idle == ~0ull) {
@@ -494,59 +533,60 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *cb8, uint32_t *cbw, T 
             }
         }
         if (idle != 0 && head < ntask) {
-            uint32_t j = head + lanes_below(idle);
+            const uint32_t j = head + lanes_below(idle);
             if (cur < 0 && j < ntask) {
-                uint32_t t = q[j];
-                cur = (int)(t & 0x7FFFu);
-                link = LINKS && (t & 0x8000u);
-                start = cur;
+                const uint32_t t = q[j];
+                cur = (int)(t & kQIdx);
+                code = (t >> kQByte) & 15u;
+                info = t;
                 steps = 0;
-                code = cb8[cur] & 15u;
-                if (!link) {
-                    a = avp[cur];
-                    ++visited;
-                }
+                a = (T)avp[cur];
+                if (!(LINKS && (t & kQLink))) ++visited;
             }
-            uint32_t nidle = (uint32_t)__popcll(idle);
+            const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (ntask - head < nidle) ? ntask : head + nidle;
         }
         if (cur >= 0) {
+            const bool link = LINKS && (info & kQLink);
             const int ni = cur + dir_off(code, S);
             const uint32_t nb = cb8[ni];
-            const T sv = avp[ni];
+            T sv = (T)avp[ni];
+            keep_read(sv);
             const uint32_t nk = nb & 15u;
             bool end = code >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData;
-            if (LINKS && link && ++steps > max_steps) {
+            if (LINKS) {
+                ++steps;
                 // longer than the tile has cells: the path runs into a cycle
-                set_status(status, kStatusCycle);
-                end = true;
+                end = end || (link && steps > max_steps);
             }
-            bool stop = end;
-            if (!end && !link) {
-                if ((nb >> 4) != 0u) {
-                    // confluence: add this donor's total, count the arrival
-                    const int sh = 8 * (ni & 3) + 4;
-                    atomicAdd(&avp[ni], a);
-                    uint32_t old = atomicSub(&cbw[ni >> 2], 1u << sh);
-                    if (((old >> sh) & 15u) == 1u) {
-                        a = avp[ni];
-                        ++visited;
-                    } else {
-                        stop = true;
-                    }
-                } else {
-                    a += sv;
-                    avp[ni] = a;
+            bool go = !end;
+            const bool fw = !end && !link;
+            if (fw && nb < 16u) {
+                a += sv;
+                avp[ni] = (VT)a;
+                ++visited;
+            }
+            if (fw && nb >= 16u) {
+                // confluence: add this donor's total, count the arrival; the
+                // last donor to arrive continues with the cell's total
+                const int sh = 8 * (ni & 3) + 4;
+                lds_add(&avp[ni], a);
+                const uint32_t old = atomicSub(&cbw[ni >> 2], 1u << sh);
+                if (((old >> sh) & 15u) == 1u) {
+                    a = (T)avp[ni];
                     ++visited;
+                } else {
+                    go = false;
                 }
             }
-            if (LINKS && link && end) ll[ring_of_idx(Tl, start)] = walk_link(Tl, cur, code, nb);
-            if (stop) {
-                cur = -1;
-            } else {
-                cur = ni;
-                code = nk;
+            if (LINKS && link && end) {
+                const uint16_t v = steps > max_steps ? kLlCycle
+                                   : (code < (uint32_t)kNoFlow && nk == kFrameTile) ? (uint16_t)cur
+                                                                                    : kLlTerm;
+                ll[info >> kQRing] = v;
             }
+            cur = go ? ni : -1;
+            code = nk;
         }
     }
     return visited;
@@ -555,51 +595,51 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *cb8, uint32_t *cbw, T 
 // Link walks from every entry (at most the ring size, so one queue fill):
 // the link and the sum of avp along the in-tile path (the adjoint's pass 1).
 __device__ inline void link_sum_walks(const WTile &Tl, const uint8_t *cb8, const float *avp,
-                                      uint16_t *q, uint32_t qcap, uint64_t ent, uint16_t *ll,
-                                      float *Sg, uint32_t *status)
+                                      uint32_t *q, uint32_t qcap, uint64_t ent, uint16_t *ll,
+                                      float *Sg)
 {
     const int S = Tl.S;
     uint64_t none = 0;
-    uint32_t ntask = fill_queue(q, qcap, Tl, ent, none), head = 0;
-    int cur = -1, start = 0, steps = 0;
-    uint32_t code = 0;
+    const uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, none, ent));
+    uint32_t head = 0;
+    int cur = -1, steps = 0;
+    uint32_t code = 0, info = 0;
     float s = 0.0f;
     const int max_steps = Tl.h * Tl.w;
     for (;;) {
-        uint64_t idle = __ballot(cur < 0);
+        const uint64_t idle = __ballot(cur < 0);
         if (head >= ntask && idle == ~0ull) break;
         if (idle != 0 && head < ntask) {
-            uint32_t j = head + lanes_below(idle);
+            const uint32_t j = head + lanes_below(idle);
             if (cur < 0 && j < ntask) {
-                cur = (int)(q[j] & 0x7FFFu);
-                start = cur;
+                const uint32_t t = q[j];
+                cur = (int)(t & kQIdx);
+                code = (t >> kQByte) & 15u;
+                info = t;
                 steps = 0;
-                code = cb8[cur] & 15u;
                 s = avp[cur];
             }
-            uint32_t nidle = (uint32_t)__popcll(idle);
+            const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (ntask - head < nidle) ? ntask : head + nidle;
         }
         if (cur >= 0) {
             const int ni = cur + dir_off(code, S);
             const uint32_t nb = cb8[ni];
-            const float sv = avp[ni];
+            float sv = avp[ni];
+            keep_read(sv);
             const uint32_t nk = nb & 15u;
-            bool end = code >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData;
-            if (++steps > max_steps) {
-                set_status(status, kStatusCycle);
-                end = true;
-            }
+            ++steps;
+            const bool end = code >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData || steps > max_steps;
             if (end) {
-                int p = ring_of_idx(Tl, start);
-                ll[p] = walk_link(Tl, cur, code, nb);
+                const int p = (int)(info >> kQRing);
+                ll[p] = steps > max_steps ? kLlCycle
+                        : (code < (uint32_t)kNoFlow && nk == kFrameTile) ? (uint16_t)cur
+                                                                         : kLlTerm;
                 Sg[p] = s;
-                cur = -1;
-            } else {
-                s += sv;
-                cur = ni;
-                code = nk;
             }
+            s += sv;
+            cur = end ? -1 : ni;
+            code = nk;
         }
     }
 }
@@ -611,27 +651,29 @@ __device__ inline void link_sum_walks(const WTile &Tl, const uint8_t *cb8, const
 // qcap entries; when full, they go to the pending bitmap pend, one 64-bit
 // row mask per tile row, which also holds the roots not yet queued).
 // Returns the number of cells this lane finished, roots excluded.
-__device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, uint16_t *q,
+__device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, uint32_t *q,
                                uint32_t qcap, uint64_t roots, uint64_t *pend)
 {
     const int S = Tl.S;
     const int lane = lane_id();
     int visited = 0;
     uint64_t none = 0;
-    uint32_t head = 0, tail = fill_queue(q, qcap, Tl, roots, none);
+    uint32_t head = 0;
+    uint32_t tail = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 0xFFu, roots, none));
     pend[lane] = roots;  // roots that did not fit
     bool more = __ballot(roots != 0) != 0;
     int cur = -1;
+    uint32_t mask = 0;
     float a = 0.0f;
     for (;;) {
-        uint64_t idle = __ballot(cur < 0);
+        const uint64_t idle = __ballot(cur < 0);
         if (head >= tail) {
             if (more) {
                 // queue empty: move pending cells into it
                 uint64_t m = pend[lane];
                 pend[lane] = 0;
                 head = 0;
-                tail = fill_queue(q, qcap, Tl, m, none);
+                tail = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 0xFFu, m, none));
                 if (m != 0) pend[lane] = m;
                 more = __ballot(m != 0) != 0;
             } else if (idle == ~0ull) {
@@ -639,48 +681,55 @@ __device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, 
             }
         }
         if (idle != 0 && head < tail) {
-            uint32_t j = head + lanes_below(idle);
+            const uint32_t j = head + lanes_below(idle);
             if (cur < 0 && j < tail) {
-                cur = q[j & (qcap - 1)];
+                const uint32_t t = q[j & (qcap - 1)];
+                cur = (int)(t & kQIdx);
+                mask = (t >> kQByte) & 0xFFu;
                 a = avp[cur];
             }
-            uint32_t nidle = (uint32_t)__popcll(idle);
+            const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (tail - head < nidle) ? tail : head + nidle;
         }
         uint32_t rest = 0;
         const int from = cur;
         const float af = a;
         if (cur >= 0) {
-            uint32_t mask = cb8[cur];
             if (mask == 0) {
                 cur = -1;
             } else {
-                uint32_t j0 = (uint32_t)__ffs(mask) - 1u;
+                const uint32_t j0 = (uint32_t)__ffs(mask) - 1u;
                 rest = mask & (mask - 1u);
                 const int d = cur + dir_off(j0, S);
-                a += avp[d];
+                const uint32_t nm = cb8[d];
+                float sd = avp[d];
+                keep_read(sd);
+                a += sd;
                 avp[d] = a;
                 ++visited;
                 cur = d;
+                mask = nm;
             }
         }
         // side donors: finish and queue them
         while (__ballot(rest != 0) != 0) {
             const bool has = rest != 0;
             int d = 0;
+            uint32_t dm = 0;
             if (has) {
-                uint32_t j = (uint32_t)__ffs(rest) - 1u;
+                const uint32_t j = (uint32_t)__ffs(rest) - 1u;
                 rest &= rest - 1u;
                 d = from + dir_off(j, S);
+                dm = cb8[d];
                 avp[d] += af;
                 ++visited;
             }
-            uint64_t b = __ballot(has);
-            uint32_t slot = tail + lanes_below(b);
-            uint32_t room = qcap - (tail - head);
+            const uint64_t b = __ballot(has);
+            const uint32_t slot = tail + lanes_below(b);
+            const uint32_t room = qcap - (tail - head);
             if (has) {
                 if (slot - tail < room) {
-                    q[slot & (qcap - 1)] = (uint16_t)d;
+                    q[slot & (qcap - 1)] = (uint32_t)d | (dm << kQByte);
                 } else {
                     int rr, cc;
                     idx_rc(Tl, d, rr, cc);
@@ -710,18 +759,22 @@ struct WLayout {
     uint32_t qcap;
 };
 
+// LDS value type of the forward passes: local unit counts of pass 1 in 16 bits.
+template <int PASS, typename T>
+using FwdLds = typename std::conditional<PASS == 1 && std::is_same<T, uint32_t>::value, uint16_t, T>::type;
+
 enum WalkKind { kWalkFwd1 = 0, kWalkFwd2 = 1, kWalkAdj1 = 2, kWalkAdj2 = 3 };
 
-__host__ __device__ inline WLayout walk_layout(int th, int tw, int kind)
+__host__ __device__ inline WLayout walk_layout(int th, int tw, int kind, int vbytes = 4)
 {
     WLayout L;
     const int S = tw + 2;
     int cb = (th + 2) * S;
     if (cb < 4 * (S + 1)) cb = 4 * (S + 1);
     L.av = (cb + 15) & ~15;
-    L.q = L.av + th * S * 4;
-    L.qcap = kind == kWalkAdj1 ? 256u : 512u;  // entries <= ring size <= 252
-    L.tail = L.q + (int)L.qcap * 2;
+    L.q = L.av + ((th * S * vbytes + 15) & ~15);
+    L.qcap = 256u;  // entries <= ring size <= 252 fit in one fill
+    L.tail = L.q + (int)L.qcap * 4;
     int tail = 0;
     if (kind == kWalkFwd1 || kind == kWalkAdj1) tail = (ring_size(th, tw) * 2 + 15) & ~15;
     if (kind == kWalkAdj2) tail = 64 * 8;
@@ -730,23 +783,89 @@ __host__ __device__ inline WLayout walk_layout(int th, int tw, int kind)
 }
 
 // ---------------------------------------------------------------- kernels --
-// Coalesced row transfers between a global array (row-major, `cols` wide)
-// and the tile's LDS values: lane = column, one row per step.
-template <typename T, typename F>
-__device__ inline void rows_in(const wk::WTile &Tl, const Geo &g, T *avp, F load)
+// Row transfers between a global array (row-major, `cols` wide) and the
+// tile's LDS values.  Vector path (16-byte aligned rows, width a multiple of
+// 4): lane l moves columns 4 (l % 16) .. + 3 of rows l / 16 + 4 i, and all
+// 16 loads (or LDS reads) of a lane are issued before their results are
+// used, so a wavefront keeps up to 16 KiB in flight.
+__device__ inline bool rows_vec(const wk::WTile &Tl, const Geo &g, const void *p)
+{
+    return ((g.cols & 3) == 0) && ((Tl.w & 3) == 0) && ((Tl.c0 & 3) == 0) &&
+           ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
+}
+
+template <typename T>
+__device__ inline void rows_in(const wk::WTile &Tl, const Geo &g, T *avp, const T *__restrict__ src)
+{
+    const int lane = wk::lane_id();
+    if (rows_vec(Tl, g, src)) {
+        const int c = 4 * (lane & 15), rq = lane >> 4;
+        uint4 v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
+            if (r < Tl.h && c < Tl.w)
+                v[i] = *reinterpret_cast<const uint4 *>(src + (Tl.r0 + r) * g.cols + Tl.c0 + c);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
+            if (r < Tl.h && c < Tl.w) {
+                T *d = avp + wk::cidx(Tl, r, c);
+                d[0] = __builtin_bit_cast(T, v[i].x);
+                d[1] = __builtin_bit_cast(T, v[i].y);
+                d[2] = __builtin_bit_cast(T, v[i].z);
+                d[3] = __builtin_bit_cast(T, v[i].w);
+            }
+        }
+        return;
+    }
+    const int c = lane;
+    if (c >= Tl.w) return;
+#pragma unroll 8
+    for (int r = 0; r < Tl.h; ++r) avp[wk::cidx(Tl, r, c)] = src[(Tl.r0 + r) * g.cols + Tl.c0 + c];
+}
+
+template <typename T>
+__device__ inline void rows_fill(const wk::WTile &Tl, T *avp, T v)
 {
     const int c = wk::lane_id();
     if (c >= Tl.w) return;
-#pragma unroll 8
-    for (int r = 0; r < Tl.h; ++r) avp[wk::cidx(Tl, r, c)] = load((Tl.r0 + r) * g.cols + Tl.c0 + c);
+    for (int r = 0; r < Tl.h; ++r) avp[wk::cidx(Tl, r, c)] = v;
 }
 
 // out = avp for data cells, 0 for NoData (valid: this lane's row mask)
 template <typename T>
 __device__ inline void rows_out(const wk::WTile &Tl, const Geo &g, const T *avp, uint64_t valid, T *out)
 {
-    const int c = wk::lane_id();
+    const int lane = wk::lane_id();
     const uint32_t vlo = (uint32_t)valid, vhi = (uint32_t)(valid >> 32);
+    if (rows_vec(Tl, g, out)) {
+        const int c = 4 * (lane & 15), rq = lane >> 4;
+        uint4 v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
+            const uint32_t lo = (uint32_t)__shfl((int)vlo, r & 63, 64);
+            const uint32_t hi = (uint32_t)__shfl((int)vhi, r & 63, 64);
+            const uint32_t bits = (c < 32 ? lo >> c : hi >> (c - 32)) & 15u;
+            if (r < Tl.h && c < Tl.w) {
+                const T *s = avp + wk::cidx(Tl, r, c);
+                v[i].x = (bits & 1u) ? __builtin_bit_cast(uint32_t, s[0]) : 0u;
+                v[i].y = (bits & 2u) ? __builtin_bit_cast(uint32_t, s[1]) : 0u;
+                v[i].z = (bits & 4u) ? __builtin_bit_cast(uint32_t, s[2]) : 0u;
+                v[i].w = (bits & 8u) ? __builtin_bit_cast(uint32_t, s[3]) : 0u;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
+            if (r < Tl.h && c < Tl.w)
+                *reinterpret_cast<uint4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + c) = v[i];
+        }
+        return;
+    }
+    const int c = lane;
     for (int r = 0; r < Tl.h; ++r) {
         uint32_t lo = __builtin_amdgcn_readlane(vlo, r), hi = __builtin_amdgcn_readlane(vhi, r);
         uint64_t row_valid = ((uint64_t)hi << 32) | lo;
@@ -773,36 +892,41 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
     using namespace wk;
     extern __shared__ __align__(16) uint8_t lds8[];
     const WTile Tl = wtile_of(g, blockIdx.x);
-    const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkFwd1 : kWalkFwd2);
+    using VT = FwdLds<PASS, T>;
+    const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkFwd1 : kWalkFwd2, (int)sizeof(VT));
     uint8_t *cb8 = lds8;
     uint32_t *cbw = reinterpret_cast<uint32_t *>(lds8);
-    T *avp = reinterpret_cast<T *>(lds8 + L.av) - Tl.S;
-    uint16_t *q = reinterpret_cast<uint16_t *>(lds8 + L.q);
+    VT *avp = reinterpret_cast<VT *>(lds8 + L.av) - Tl.S;
+    uint32_t *q = reinterpret_cast<uint32_t *>(lds8 + L.q);
     uint16_t *ll = reinterpret_cast<uint16_t *>(lds8 + L.tail);
     const int lane = lane_id();
 
     Setup St = setup_tile<0, PASS == 1>(dirs, g, Tl, cb8, status);
 
     // seeds: own weight (+ resolved inflow on the perimeter in pass 2)
-    if (w) rows_in(Tl, g, avp, [&](int64_t i) { return (T)w[i]; });
-    else rows_in(Tl, g, avp, [&](int64_t) { return (T)1; });
-    if (PASS == 2) {
+    if constexpr (std::is_same<VT, float>::value) {
+        if (w) rows_in(Tl, g, avp, w);
+        else rows_fill(Tl, avp, 1.0f);
+    } else {
+        rows_fill(Tl, avp, (VT)1);
+    }
+    if constexpr (PASS == 2) {
         __syncthreads();
         for (int p = lane; p < Tl.P; p += 64) {
             int qr, qc;
             ring_cell(p, Tl.h, Tl.w, qr, qc);
-            avp[cidx(Tl, qr, qc)] += (T)ext[Tl.base + p];
+            avp[cidx(Tl, qr, qc)] += (VT)ext[Tl.base + p];
         }
     } else {
-        for (int p = lane; p < Tl.P; p += 64) ll[p] = kLinkTerm;
+        for (int p = lane; p < Tl.P; p += 64) ll[p] = kLlTerm;
     }
     __syncthreads();
 
-    int visited = fwd_walks<T, PASS == 1>(Tl, cb8, cbw, avp, q, L.qcap, St.src, St.entry, ll, status);
+    int visited = fwd_walks<VT, PASS == 1>(Tl, cb8, cbw, avp, q, L.qcap, St.src, St.entry, ll);
     if (wave_sum(visited) != wave_sum(__popcll(St.valid)) && lane == 0) set_status(status, kStatusCycle);
     __syncthreads();
 
-    if (PASS == 2) {
+    if constexpr (PASS == 2) {
         rows_out(Tl, g, avp, St.valid, out);
         // an exit whose children never all arrived sits on a cycle of exits
         for (int p = lane; p < Tl.P; p += 64) {
@@ -822,10 +946,10 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
         uint16_t Lk;
         if (k >= (uint32_t)kNoData) Lk = kLinkNoData;
         else if (k < (uint32_t)kNoFlow && (cb8[idx + dir_off(k, Tl.S)] & 15u) == kFrameTile) Lk = kLinkExt;
-        else Lk = ll[p];
+        else Lk = link_of(Tl, ll[p], status);
         int64_t id = Tl.base + p;
         link[id] = Lk;
-        aloc[id] = k < (uint32_t)kNoData ? avp[idx] : (T)0;
+        aloc[id] = k < (uint32_t)kNoData ? (T)avp[idx] : (T)0;
         indeg[id] = 0;
         if (cnt) cnt[id] = 0;
         acc[id] = (V)0;
@@ -849,17 +973,17 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
     const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkAdj1 : kWalkAdj2);
     uint8_t *cb8 = lds8;
     float *avp = reinterpret_cast<float *>(lds8 + L.av) - Tl.S;
-    uint16_t *q = reinterpret_cast<uint16_t *>(lds8 + L.q);
+    uint32_t *q = reinterpret_cast<uint32_t *>(lds8 + L.q);
     const int lane = lane_id();
 
     Setup St = setup_tile<PASS == 1 ? 1 : 2, PASS == 1>(dirs, g, Tl, cb8, status);
-    rows_in(Tl, g, avp, [&](int64_t i) { return gin[i]; });
+    rows_in(Tl, g, avp, gin);
 
     if (PASS == 1) {
         uint16_t *ll = reinterpret_cast<uint16_t *>(lds8 + L.tail);
-        for (int p = lane; p < Tl.P; p += 64) ll[p] = kLinkTerm;
+        for (int p = lane; p < Tl.P; p += 64) ll[p] = kLlTerm;
         __syncthreads();
-        link_sum_walks(Tl, cb8, avp, q, L.qcap, St.entry, ll, Sg + Tl.base, status);
+        link_sum_walks(Tl, cb8, avp, q, L.qcap, St.entry, ll, Sg + Tl.base);
         __syncthreads();
         for (int p = lane; p < Tl.P; p += 64) {
             int qr, qc;
@@ -869,7 +993,7 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
             uint16_t Lk;
             if (k >= (uint32_t)kNoData) Lk = kLinkNoData;
             else if (k < (uint32_t)kNoFlow && (cb8[idx + dir_off(k, Tl.S)] & 15u) == kFrameTile) Lk = kLinkExt;
-            else Lk = ll[p];
+            else Lk = link_of(Tl, ll[p], status);
             link[Tl.base + p] = Lk;
         }
         return;
@@ -893,9 +1017,10 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
     rows_out(Tl, g, avp, St.valid, out);
 }
 
-__host__ inline size_t walk_lds_bytes(int th, int tw, int kind)
+__host__ inline size_t walk_lds_bytes(int th, int tw, int kind, int vbytes = 4)
 {
-    return (size_t)walk_layout(th, tw, kind).total;
+    return (size_t)walk_layout(th, tw, kind, vbytes).total;
 }
+
 
 }  // namespace d8
