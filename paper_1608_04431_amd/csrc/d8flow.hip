@@ -59,7 +59,7 @@ int check_common(int64_t rows, int64_t cols, int &th, int &tw, Geo &g, bool &emp
     if (tw > cols) tw = (int)cols;
     if (th > D8_MAX_TILE_SIDE || tw > D8_MAX_TILE_SIDE) return D8_EINVAL;
     g = make_geo(rows, cols, th, tw);
-    if (g.nnodes >= (int64_t)kNone || (int64_t)g.nty * g.ntx > INT_MAX) return D8_EINVAL;
+    if (g.nnodes >= (int64_t)kJumpDone || (int64_t)g.nty * g.ntx > INT_MAX) return D8_EINVAL;
     return D8_OK;
 }
 
@@ -330,11 +330,9 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     uint16_t *link = reinterpret_cast<uint16_t *>(w8 + L.link);
     uint32_t *entry = reinterpret_cast<uint32_t *>(w8 + L.entry);
     uint32_t *succ = reinterpret_cast<uint32_t *>(w8 + L.succ);
-    uint32_t *ptr[2] = {reinterpret_cast<uint32_t *>(w8 + L.indeg),
-                        reinterpret_cast<uint32_t *>(w8 + L.ptr2)};
     float *S = reinterpret_cast<float *>(w8 + L.val32);
-    double *val[2] = {reinterpret_cast<double *>(w8 + L.acc64),
-                      reinterpret_cast<double *>(w8 + L.ext64)};
+    unsigned long long *jw[2] = {reinterpret_cast<unsigned long long *>(w8 + L.acc64),
+                                 reinterpret_cast<unsigned long long *>(w8 + L.ext64)};
 
     int ntiles = g.nty * g.ntx;
     const int thr = kTileThreads;
@@ -350,18 +348,17 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr)));
     D8_LAUNCH("adj_jump_init", st,
-              (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(g, link, entry, succ, S, ptr[0], val[0])));
+              (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(g, link, entry, succ, S, jw[0], jw[1])));
     int rounds = 1;
     while (((int64_t)1 << (rounds - 1)) <= g.nnodes) ++rounds;
     for (int r = 0; r < rounds; ++r)
         D8_LAUNCH("adj_jump_round", st,
-                  (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(g, ptr[r & 1], val[r & 1],
-                                                             ptr[(r + 1) & 1], val[(r + 1) & 1],
-                                                             jstate, r)));
+                  (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(g, jw[r & 1], jw[(r + 1) & 1], jstate,
+                                                             r)));
     D8_LAUNCH("adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
     D8_LAUNCH("adj_pass2", st,
-              (adj_walk<2><<<ntiles, thr, lds2, st>>>(dirs, grad_acc, g, link, nullptr, val[0],
-                                                     val[1], jstate, grad_weights, status)));
+              (adj_walk<2><<<ntiles, thr, lds2, st>>>(dirs, grad_acc, g, link, nullptr, jw[0],
+                                                      jw[1], jstate, grad_weights, status)));
     return last_error();
 }
 

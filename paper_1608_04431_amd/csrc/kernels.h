@@ -119,17 +119,19 @@ __global__ void resolve_fwd_u32(Geo g, const uint16_t *__restrict__ link,
     if (id >= g.nnodes) return;
     if (link[id] != kLinkExt || indeg[id] != 0) return;
     uint32_t v = aloc[id];
-    uint32_t e = (uint32_t)id;
+    uint32_t n = entry[id], s = succ[id];
     for (;;) {
-        uint32_t n = entry[e];
         if (n == kNone) break;
         atomicAdd(&ext[n], v);
-        uint32_t s = succ[e];
         if (s == kNone) break;
+        // the next node's fields do not depend on the arrival: fetch them
+        // while the atomic is in flight
+        const uint32_t as = aloc[s], is = indeg[s], ns = entry[s], ss = succ[s];
         unsigned long long old = atomicAdd(&packed[s], ((unsigned long long)v << 32) | 1ull);
-        if ((uint32_t)old + 1u != indeg[s]) break;
-        v = aloc[s] + (uint32_t)(old >> 32) + v;
-        e = s;
+        if ((uint32_t)old + 1u != is) break;
+        v = as + (uint32_t)(old >> 32) + v;
+        n = ns;
+        s = ss;
     }
 }
 
@@ -145,45 +147,62 @@ __global__ void resolve_fwd_f64(Geo g, const uint16_t *__restrict__ link, const 
     if (id >= g.nnodes) return;
     if (link[id] != kLinkExt || indeg[id] != 0) return;
     double v = (double)aloc[id];
-    uint32_t e = (uint32_t)id;
+    uint32_t n = entry[id], s = succ[id];
     for (;;) {
-        uint32_t n = entry[e];
         if (n == kNone) break;
         atomicAdd(&ext[n], v);
-        uint32_t s = succ[e];
         if (s == kNone) break;
+        const double as = (double)aloc[s];
+        const uint32_t is = indeg[s], ns = entry[s], ss = succ[s];
         atomicAdd(&acc[s], v);
         uint32_t old = __hip_atomic_fetch_add(&cnt[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1u != indeg[s]) break;
-        v = (double)aloc[s] + __hip_atomic_load(&acc[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        e = s;
+        if (old + 1u != is) break;
+        v = as + __hip_atomic_load(&acc[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        n = ns;
+        s = ss;
     }
 }
 
 // -------------------------------------------------------------- adjoint ----
 // mu(e) = lambda(entry(e)) = S(entry(e)) + mu(succ(e)): a downstream path sum
-// over the exit forest.  Initial state: ptr = succ, val = S(entry) (0 without
-// an entry).  Non-exit nodes are inert (ptr = none, val = 0).
+// over the exit forest, by pointer jumping.  One 64-bit word per node:
+// pointer in the low half, float partial sum in the high half.  A pointer
+// kNone means the sum is complete; kJumpDone additionally means the word
+// holds the same complete sum in both buffers, so rounds skip the node.
+constexpr uint32_t kJumpDone = 0xFFFFFFFEu;
+
+__device__ inline unsigned long long jump_word(uint32_t ptr, float v)
+{
+    return ((unsigned long long)__float_as_uint(v) << 32) | ptr;
+}
+__device__ inline float jump_val(unsigned long long w) { return __uint_as_float((uint32_t)(w >> 32)); }
+
+// Initial state: exits point at their successor with val = S(entry); every
+// other node is inert (done, 0) in both buffers.
 __global__ void adj_jump_init(Geo g, const uint16_t *__restrict__ link,
                               const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
-                              const float *__restrict__ S, uint32_t *ptr, double *val)
+                              const float *__restrict__ S, unsigned long long *buf0,
+                              unsigned long long *buf1)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= g.nnodes) return;
-    uint32_t n = entry[id];
-    ptr[id] = (link[id] == kLinkExt) ? succ[id] : kNone;
-    val[id] = (link[id] == kLinkExt && n != kNone) ? (double)S[n] : 0.0;
+    unsigned long long w = jump_word(kJumpDone, 0.0f);
+    if (link[id] == kLinkExt) {
+        const uint32_t n = entry[id];
+        w = jump_word(succ[id], n != kNone ? S[n] : 0.0f);
+    }
+    buf0[id] = w;
+    buf1[id] = w;
 }
 
-// One synchronous pointer-jumping round r: reads buffer r&1, writes buffer
-// (r+1)&1: val' = val + val[ptr], ptr' = ptr[ptr].  live[r%3] is set when any
+// One synchronous round r: reads buffer r&1, writes buffer (r+1)&1:
+// val' = val + val[ptr], ptr' = ptr[ptr].  live[r%3] is set when any
 // pointer is still live after the round; round r reads live[(r-1)%3] and, if
 // nothing was live, records the final buffer in state[0] and does nothing.
 // live[(r+1)%3] is cleared here for the next round (its previous contents were
 // read by round r-1, which has completed).
-__global__ void adj_jump_round(Geo g, const uint32_t *__restrict__ ptr_in,
-                               const double *__restrict__ val_in, uint32_t *__restrict__ ptr_out,
-                               double *__restrict__ val_out, uint32_t *state, int round)
+__global__ void adj_jump_round(Geo g, unsigned long long *w_in, unsigned long long *__restrict__ w_out,
+                               uint32_t *state, int round)
 {
     uint32_t *live = state + 1;
     if (live[(round + 2) % 3] == 0) {
@@ -195,17 +214,25 @@ __global__ void adj_jump_round(Geo g, const uint32_t *__restrict__ ptr_in,
     }
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id == 0) live[(round + 1) % 3] = 0;
-    if (id >= g.nnodes) return;
-    uint32_t p = ptr_in[id];
-    double v = val_in[id];
-    uint32_t np = kNone;
-    if (p != kNone) {
-        v += val_in[p];
-        np = ptr_in[p];
+    bool alive = false;
+    if (id < g.nnodes) {
+        const unsigned long long w = w_in[id];
+        const uint32_t p = (uint32_t)w;
+        if (p == kNone) {
+            // complete since the last round: the same word, done, in both
+            // buffers (readers of w_in see the same sum either way)
+            const unsigned long long d = jump_word(kJumpDone, jump_val(w));
+            w_out[id] = d;
+            w_in[id] = d;
+        } else if (p != kJumpDone) {
+            const unsigned long long t = w_in[p];
+            uint32_t np = (uint32_t)t;
+            if (np == kJumpDone) np = kNone;
+            alive = np != kNone;
+            w_out[id] = jump_word(np, jump_val(w) + jump_val(t));
+        }
     }
-    ptr_out[id] = np;
-    val_out[id] = v;
-    if (__ballot(np != kNone) != 0 && (threadIdx.x & (warpSize - 1)) == 0) live[round % 3] = 1;
+    if (__ballot(alive) != 0 && (threadIdx.x & (warpSize - 1)) == 0) live[round % 3] = 1;
 }
 
 // After the last round: if no round found convergence, the final buffer is

@@ -963,8 +963,8 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
 template <int PASS>
 __global__ void __launch_bounds__(64)
 adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
-         uint16_t *__restrict__ link, float *__restrict__ Sg, const double *__restrict__ mu0,
-         const double *__restrict__ mu1, const uint32_t *__restrict__ jstate,
+         uint16_t *__restrict__ link, float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
+         const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
          float *__restrict__ out, uint32_t *status)
 {
     using namespace wk;
@@ -1001,13 +1001,14 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
 
     // pass 2: every perimeter cell gets the downstream sum of the cell its
     // flow enters in another tile (zero unless it is an exit)
-    const double *mu = jstate[0] == 1 ? mu1 : mu0;
+    // downstream sums: float in the high half of each node's jump word
+    const unsigned long long *mu = jstate[0] == 1 ? mu1 : mu0;
     uint64_t *pend = reinterpret_cast<uint64_t *>(lds8 + L.tail);
     __syncthreads();
     for (int p = lane; p < Tl.P; p += 64) {
         int qr, qc;
         ring_cell(p, Tl.h, Tl.w, qr, qc);
-        avp[cidx(Tl, qr, qc)] += (float)mu[Tl.base + p];
+        avp[cidx(Tl, qr, qc)] += __uint_as_float((uint32_t)(mu[Tl.base + p] >> 32));
     }
     __syncthreads();
     int visited = up_walks(Tl, cb8, avp, q, L.qcap, St.root, pend);
