@@ -139,8 +139,71 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                        size_t ws_bytes, void *stream);
 
 /*
+ * Batches of rasters.  Many rasters of uneven sizes go through the same
+ * three stages together: one launch per stage for the whole batch instead of
+ * one per raster.  The tile passes run persistent workers that take the
+ * next (raster, tile) pair from a work counter; rasters are ordered by
+ * decreasing cell count, so the largest rasters' tiles are handed out
+ * first, and all rasters' perimeter cells form one global flow graph (the
+ * paper hands tiles to workers in turn and resolves one graph of all
+ * perimeters, Sections "Constructing a Global Solution" and "Implementation
+ * Details").  Forward accumulation is float32 (weights, or NULL for w = 1);
+ * the results equal those of flow_accum(D8_ACC_F32) / flow_accum_adjoint per
+ * raster with the same tile shapes, bit for bit.
+ *
+ * d8_batch_item: one raster; every pointer is a device pointer owned by the
+ * caller.  rows, cols >= 0 (an empty raster is skipped); tile_rows,
+ * tile_cols as for flow_accum (0, 0 = 64 x 64), per raster.
+ *   dirs (in); weights (in, NULL = 1) and acc (out) for D8_BATCH_FWD;
+ *   grad_acc (in) and grad_weights (out) for D8_BATCH_ADJ.
+ * mode: D8_BATCH_FWD, D8_BATCH_ADJ or both (forward first, then adjoint).
+ * items: host array of n items (read during the call only).
+ * ws, ws_bytes: device workspace of at least d8_batch_workspace_bytes(items,
+ *   n) bytes (the same items; 0 means the items are invalid).  It holds the
+ *   batch's descriptor tables and perimeter-graph arrays.
+ */
+typedef struct {
+    const uint8_t *dirs;
+    const float *weights;
+    float *acc;
+    const float *grad_acc;
+    float *grad_weights;
+    int64_t rows, cols;
+    int tile_rows, tile_cols;
+} d8_batch_item;
+
+enum { D8_BATCH_FWD = 1, D8_BATCH_ADJ = 2 };
+
+size_t d8_batch_workspace_bytes(const d8_batch_item *items, int n);
+
+/*
+ * Runs a batch on `stream`.  The descriptor tables are copied into `ws`
+ * first and the call waits for that copy (one synchronisation of `stream`);
+ * the stages are then enqueued without further waits.  Returns D8_OK,
+ * D8_EINVAL (bad item, mode, or a missing pointer the mode needs),
+ * D8_EWORKSPACE or D8_EHIP; data errors via d8_check_status(ws, stream).
+ */
+int flow_accum_batched(const d8_batch_item *items, int n, int mode, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/*
+ * The same batch recorded once as a HIP graph: d8_graph_create copies the
+ * descriptor tables into `ws` (waiting on `stream`), records every stage on
+ * a private stream and returns an executable graph in *graph_exec.
+ * d8_graph_launch replays it on `stream` -- one launch for the whole batch;
+ * it reads and writes the items' arrays and `ws` as they are at replay time
+ * (the pointers are fixed at creation).  Replays on one workspace must not
+ * overlap.  d8_graph_destroy frees the graph.  The graph allocates nothing
+ * and contains no memset nodes.
+ */
+int d8_graph_create(const d8_batch_item *items, int n, int mode, void *ws, size_t ws_bytes,
+                    void *stream, void **graph_exec);
+int d8_graph_launch(void *graph_exec, void *stream);
+int d8_graph_destroy(void *graph_exec);
+
+/*
  * Waits for `stream`, then returns the data-dependent status recorded in
- * `ws` by the last flow_accum / flow_accum_adjoint call on it: D8_OK,
+ * `ws` by the last flow_accum / flow_accum_adjoint / batch call on it: D8_OK,
  * D8_EDIRCODE or D8_ECYCLE (or D8_EHIP if the wait itself fails, D8_EINVAL for
  * a NULL workspace).
  */

@@ -17,7 +17,7 @@ NOFLOW = 8
 NODATA = 9
 
 __all__ = ["d8_directions", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
-           "check_status", "FlowAccum", "D8Error"]
+           "check_status", "FlowAccum", "D8Error", "Raster", "Batch", "BatchGraph"]
 
 
 def _stream(device: torch.device) -> int:
@@ -160,3 +160,90 @@ class FlowAccum(torch.autograd.Function):
         (dirs,) = ctx.saved_tensors
         gw = flow_accum_adjoint(dirs, grad_a.contiguous(), tile=ctx.tile)
         return gw, None, None
+
+
+# ----------------------------------------------------------------- batches --
+
+class Raster:
+    """One raster of a batch: dirs (uint8) and, per direction of the batch,
+    weights (float32 or None) with the output acc, and grad_acc with the
+    output grad_weights.  Outputs are allocated when not given."""
+
+    def __init__(self, dirs, weights=None, grad_acc=None, tile=(0, 0), acc=None, grad_weights=None):
+        _check_raster(dirs, torch.uint8, "dirs")
+        for name, t in (("weights", weights), ("grad_acc", grad_acc)):
+            if t is not None:
+                _check_raster(t, torch.float32, name)
+                if t.shape != dirs.shape:
+                    raise ValueError(f"{name} and dirs differ in shape")
+        self.dirs, self.weights, self.grad_acc, self.tile = dirs, weights, grad_acc, tuple(tile)
+        self.acc = acc if acc is not None else torch.empty(dirs.shape, dtype=torch.float32,
+                                                           device=dirs.device)
+        self.grad_weights = grad_weights
+        if grad_acc is not None and grad_weights is None:
+            self.grad_weights = torch.empty(dirs.shape, dtype=torch.float32, device=dirs.device)
+
+    def item(self) -> _lib.BatchItem:
+        return _lib.BatchItem(_ptr(self.dirs), _ptr(self.weights), _ptr(self.acc),
+                              _ptr(self.grad_acc), _ptr(self.grad_weights), self.dirs.shape[0],
+                              self.dirs.shape[1], self.tile[0], self.tile[1])
+
+
+class Batch:
+    """Many rasters through one set of launches (flow_accum_batched).
+    mode: 'fwd', 'adj' or 'fwd+adj'."""
+
+    def __init__(self, rasters: list[Raster], mode: str = "fwd+adj", device=None):
+        self.rasters = list(rasters)
+        self.mode = {"fwd": _lib.D8_BATCH_FWD, "adj": _lib.D8_BATCH_ADJ,
+                     "fwd+adj": _lib.D8_BATCH_FWD | _lib.D8_BATCH_ADJ}[mode]
+        self.items = (_lib.BatchItem * max(1, len(self.rasters)))(*[r.item() for r in self.rasters])
+        self.n = len(self.rasters)
+        self.nbytes = _lib.load().d8_batch_workspace_bytes(self.items, self.n)
+        if self.nbytes == 0:
+            raise D8Error(_lib.D8_EINVAL, "batch items")
+        dev = device or (self.rasters[0].dirs.device if self.rasters else "cuda")
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+
+    def run(self) -> None:
+        rc = _lib.load().flow_accum_batched(self.items, self.n, self.mode, _ptr(self.buf),
+                                            self.nbytes, _stream(self.buf.device))
+        _lib.check(rc, "flow_accum_batched")
+
+    def check_status(self) -> None:
+        rc = _lib.load().d8_check_status(_ptr(self.buf), _stream(self.buf.device))
+        _lib.check(rc, "status")
+
+    def graph(self) -> "BatchGraph":
+        return BatchGraph(self)
+
+
+class BatchGraph:
+    """The batch recorded as one HIP graph (d8_graph_create); launch() replays
+    it on the current stream."""
+
+    def __init__(self, batch: Batch):
+        import ctypes
+        self.batch = batch
+        h = ctypes.c_void_p()
+        rc = _lib.load().d8_graph_create(batch.items, batch.n, batch.mode, _ptr(batch.buf),
+                                         batch.nbytes, _stream(batch.buf.device), ctypes.byref(h))
+        _lib.check(rc, "d8_graph_create")
+        self.handle = h
+
+    def launch(self) -> None:
+        if self.handle is None:
+            raise RuntimeError("graph destroyed")
+        rc = _lib.load().d8_graph_launch(self.handle, _stream(self.batch.buf.device))
+        _lib.check(rc, "d8_graph_launch")
+
+    def destroy(self) -> None:
+        if self.handle is not None:
+            _lib.load().d8_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

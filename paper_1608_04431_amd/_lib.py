@@ -13,11 +13,23 @@ LIB_PATH = os.path.join(HERE, "libd8flow.so")
 
 # every symbol declared in include/d8flow.h
 EXPORTS = ("d8_directions", "d8_workspace_bytes", "flow_accum", "flow_accum_adjoint",
+           "d8_batch_workspace_bytes", "flow_accum_batched", "d8_graph_create",
+           "d8_graph_launch", "d8_graph_destroy",
            "d8_check_status", "d8_strerror", "d8_version", "d8_timing_enable",
            "d8_timing_report", "d8_last_error_message")
 
 D8_OK, D8_EINVAL, D8_EWORKSPACE, D8_EHIP, D8_EDIRCODE, D8_ECYCLE = 0, -1, -2, -3, -4, -5
 D8_ACC_U32, D8_ACC_F32 = 0, 1
+D8_BATCH_FWD, D8_BATCH_ADJ = 1, 2
+
+
+class BatchItem(ctypes.Structure):
+    """d8_batch_item of include/d8flow.h (device pointers as integers)."""
+    _fields_ = [("dirs", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("acc", ctypes.c_void_p),
+                ("grad_acc", ctypes.c_void_p), ("grad_weights", ctypes.c_void_p),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("tile_rows", ctypes.c_int), ("tile_cols", ctypes.c_int)]
+
 D8_MAX_TILE_SIDE = 64
 
 _lib = None
@@ -52,6 +64,17 @@ def load() -> ctypes.CDLL:
     lib.flow_accum.restype = i32
     lib.flow_accum_adjoint.argtypes = [vp, vp, vp, i64, i64, i32, i32, vp, sz, vp]
     lib.flow_accum_adjoint.restype = i32
+    items = ctypes.POINTER(BatchItem)
+    lib.d8_batch_workspace_bytes.argtypes = [items, i32]
+    lib.d8_batch_workspace_bytes.restype = sz
+    lib.flow_accum_batched.argtypes = [items, i32, i32, vp, sz, vp]
+    lib.flow_accum_batched.restype = i32
+    lib.d8_graph_create.argtypes = [items, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.d8_graph_create.restype = i32
+    lib.d8_graph_launch.argtypes = [vp, vp]
+    lib.d8_graph_launch.restype = i32
+    lib.d8_graph_destroy.argtypes = [vp]
+    lib.d8_graph_destroy.restype = i32
     lib.d8_check_status.argtypes = [vp, vp]
     lib.d8_check_status.restype = i32
     lib.d8_strerror.argtypes = [i32]

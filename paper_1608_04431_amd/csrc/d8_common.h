@@ -110,6 +110,19 @@ inline Geo make_geo(int64_t rows, int64_t cols, int th, int tw)
     return g;
 }
 
+// One raster of a batch (device-side descriptor).  Node and tile numbers
+// of the raster are offset by node0 / tile0 in the batch's arrays.
+struct DemDesc {
+    Geo g;
+    int64_t node0;      // first perimeter node of this raster
+    int64_t tile0;      // first tile of this raster in the batch's tile order
+    const uint8_t *dirs;
+    const float *w;     // forward weights (NULL = 1)
+    float *acc;         // forward output
+    const float *gacc;  // adjoint cotangent
+    float *gw;          // adjoint output
+};
+
 // First error wins.
 __device__ inline void set_status(uint32_t *status, uint32_t code)
 {

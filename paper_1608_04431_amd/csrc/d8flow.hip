@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstring>
 #include <mutex>
@@ -88,6 +89,9 @@ hipEvent_t pooled_event()
     return e;
 }
 
+// set while this thread records a graph: no timing events go into it
+thread_local bool g_capturing = false;
+
 struct LaunchTimer {
     const char *name;
     hipStream_t st;
@@ -95,7 +99,7 @@ struct LaunchTimer {
     LaunchTimer(const char *n, hipStream_t s) : name(n), st(s)
     {
         std::lock_guard<std::mutex> lk(g_timing_mu);
-        if (g_timing_on) {
+        if (g_timing_on && !g_capturing) {
             a = pooled_event();
             (void)hipEventRecord(a, st);
         }
@@ -211,11 +215,11 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg)));
     if constexpr (kCounts) {
         D8_LAUNCH("resolve_fwd", st,
-                  (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g, link, aloc, entry, succ, indeg, acc,
+                  (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg, acc,
                                                               ext)));
     } else {
         D8_LAUNCH("resolve_fwd", st,
-                  (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(g, link, aloc, entry, succ, indeg,
+                  (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg,
                                                                  cnt, acc, ext)));
     }
     D8_LAUNCH("fwd_pass2", st,
@@ -223,6 +227,230 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
                                                                acc, ext, out, status)));
     return last_error();
 }
+
+
+// ------------------------------------------------------------------ batch --
+// A batch plan: rasters with cells, sorted by decreasing cell count (the
+// tile work queue hands out the largest rasters' tiles first), their
+// descriptors, the raster of every batch tile, and the raster where every
+// chunk of 2^kChunkShift nodes starts.
+struct BatchLayout {
+    size_t status, jstate, counters, desc, tile_dem, chunk_dem;
+    size_t link, entry, succ, indeg, cnt, val32, acc64, ext64, total;
+};
+
+struct BatchPlan {
+    std::vector<DemDesc> dems;
+    std::vector<uint32_t> tile_dem, chunk_dem;
+    int64_t ntiles = 0, nnodes = 0;
+    size_t lds[4] = {0, 0, 0, 0};  // fwd pass 1, fwd pass 2, adj pass 1, adj pass 2
+    BatchLayout L{};
+};
+
+int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
+{
+    if (n < 0 || (n > 0 && !items)) return D8_EINVAL;
+    std::vector<int> order;
+    for (int i = 0; i < n; ++i) {
+        const d8_batch_item &it = items[i];
+        if (it.rows < 0 || it.cols < 0) return D8_EINVAL;
+        if (it.rows > 0 && it.cols > 0) order.push_back(i);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return items[a].rows * items[a].cols > items[b].rows * items[b].cols;
+    });
+    for (int i : order) {
+        const d8_batch_item &it = items[i];
+        int th = it.tile_rows, tw = it.tile_cols;
+        Geo g;
+        bool empty = false;
+        int rc = check_common(it.rows, it.cols, th, tw, g, empty);
+        if (rc != D8_OK) return rc;
+        DemDesc D;
+        D.g = g;
+        D.node0 = P.nnodes;
+        D.tile0 = P.ntiles;
+        D.dirs = it.dirs;
+        D.w = it.weights;
+        D.acc = it.acc;
+        D.gacc = it.grad_acc;
+        D.gw = it.grad_weights;
+        if (!D.dirs) return D8_EINVAL;
+        const int64_t nt = (int64_t)g.nty * g.ntx;
+        for (int64_t t = 0; t < nt; ++t) P.tile_dem.push_back((uint32_t)P.dems.size());
+        P.dems.push_back(D);
+        P.ntiles += nt;
+        P.nnodes += g.nnodes;
+        if (P.nnodes >= (int64_t)kJumpDone || P.ntiles >= (int64_t)INT_MAX) return D8_EINVAL;
+        P.lds[0] = std::max(P.lds[0], walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4));
+        P.lds[1] = std::max(P.lds[1], walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4));
+        P.lds[2] = std::max(P.lds[2], walk_lds_bytes(g.th, g.tw, kWalkAdj1, 4));
+        P.lds[3] = std::max(P.lds[3], walk_lds_bytes(g.th, g.tw, kWalkAdj2, 4));
+    }
+    const int64_t nchunk = (P.nnodes >> kChunkShift) + 1;
+    P.chunk_dem.assign((size_t)nchunk, 0);
+    size_t d = 0;
+    for (int64_t k = 0; k < nchunk; ++k) {
+        const int64_t first = k << kChunkShift;
+        while (d + 1 < P.dems.size() && P.dems[d + 1].node0 <= first) ++d;
+        P.chunk_dem[(size_t)k] = (uint32_t)d;
+    }
+    const size_t N = (size_t)P.nnodes;
+    BatchLayout &L = P.L;
+    size_t off = 0;
+    L.status = off; off += 256;
+    L.jstate = off; off += 256;
+    L.counters = off; off += 256;
+    L.desc = off;      off = align256(off + P.dems.size() * sizeof(DemDesc));
+    L.tile_dem = off;  off = align256(off + P.tile_dem.size() * sizeof(uint32_t));
+    L.chunk_dem = off; off = align256(off + P.chunk_dem.size() * sizeof(uint32_t));
+    L.link = off;  off = align256(off + N * sizeof(uint16_t));
+    L.entry = off; off = align256(off + N * sizeof(uint32_t));
+    L.succ = off;  off = align256(off + N * sizeof(uint32_t));
+    L.indeg = off; off = align256(off + N * sizeof(uint32_t));
+    L.cnt = off;   off = align256(off + N * sizeof(uint32_t));
+    L.val32 = off; off = align256(off + N * sizeof(float));
+    L.acc64 = off; off = align256(off + N * sizeof(double));
+    L.ext64 = off; off = align256(off + N * sizeof(double));
+    L.total = off;
+    return D8_OK;
+}
+
+__global__ void init_batch(uint32_t *status, uint32_t *jstate, uint32_t *counters)
+{
+    status[0] = kStatusOk;
+    jstate[0] = kNone;
+    jstate[1] = 0;
+    jstate[2] = 0;
+    jstate[3] = 1;
+    for (int i = 0; i < 4; ++i) counters[i] = 0;
+}
+
+__global__ void reset_jump(uint32_t *jstate)
+{
+    jstate[0] = kNone;
+    jstate[1] = 0;
+    jstate[2] = 0;
+    jstate[3] = 1;
+}
+
+// Descriptor tables into the workspace; waits for the copies (the host
+// vectors are the plan's).
+int upload_plan(const BatchPlan &P, char *ws, hipStream_t st)
+{
+    const BatchLayout &L = P.L;
+    if (!P.dems.empty()) {
+        if (hipMemcpyAsync(ws + L.desc, P.dems.data(), P.dems.size() * sizeof(DemDesc),
+                           hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ws + L.tile_dem, P.tile_dem.data(), P.tile_dem.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ws + L.chunk_dem, P.chunk_dem.data(),
+                           P.chunk_dem.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess)
+            return D8_EHIP;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return D8_EHIP;
+    return D8_OK;
+}
+
+// Persistent grid: as many tile workers as fit on the device at once.
+unsigned workers_for(const void *kernel, size_t lds, int64_t ntiles)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, lds);
+    int64_t n = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    if (n > ntiles) n = ntiles;
+    return (unsigned)(n > 0 ? n : 1);
+}
+
+int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
+{
+    const BatchLayout &L = P.L;
+    uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.status);
+    uint32_t *jstate = reinterpret_cast<uint32_t *>(ws + L.jstate);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(ws + L.counters);
+    const DemDesc *dems = reinterpret_cast<const DemDesc *>(ws + L.desc);
+    const uint32_t *tile_dem = reinterpret_cast<const uint32_t *>(ws + L.tile_dem);
+    const uint32_t *chunk_dem = reinterpret_cast<const uint32_t *>(ws + L.chunk_dem);
+    uint16_t *link = reinterpret_cast<uint16_t *>(ws + L.link);
+    uint32_t *entry = reinterpret_cast<uint32_t *>(ws + L.entry);
+    uint32_t *succ = reinterpret_cast<uint32_t *>(ws + L.succ);
+    uint32_t *indeg = reinterpret_cast<uint32_t *>(ws + L.indeg);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + L.cnt);
+    float *val32 = reinterpret_cast<float *>(ws + L.val32);
+    double *acc = reinterpret_cast<double *>(ws + L.acc64);
+    double *ext = reinterpret_cast<double *>(ws + L.ext64);
+    unsigned long long *jw[2] = {reinterpret_cast<unsigned long long *>(ws + L.acc64),
+                                 reinterpret_cast<unsigned long long *>(ws + L.ext64)};
+    const int ndem = (int)P.dems.size();
+    const uint32_t ntiles = (uint32_t)P.ntiles;
+    const int64_t N = P.nnodes;
+    const unsigned nb = blocks_for(N, kNodeBlock);
+
+    init_batch<<<1, 1, 0, st>>>(status, jstate, counters);
+    if (ndem == 0) return last_error();
+    if (mode & D8_BATCH_FWD) {
+        if (allow_lds(fwd_walk_batch<1>, P.lds[0]) || allow_lds(fwd_walk_batch<2>, P.lds[1])) return D8_EHIP;
+        const unsigned w1 = workers_for(reinterpret_cast<const void *>(fwd_walk_batch<1>), P.lds[0], P.ntiles);
+        const unsigned w2 = workers_for(reinterpret_cast<const void *>(fwd_walk_batch<2>), P.lds[1], P.ntiles);
+        D8_LAUNCH("batch_fwd_pass1", st,
+                  (fwd_walk_batch<1><<<w1, 64, P.lds[0], st>>>(dems, tile_dem, counters + 0, ntiles, link,
+                                                              val32, indeg, cnt, acc, ext, status)));
+        D8_LAUNCH("batch_graph_build", st,
+                  (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
+                                                                succ, indeg)));
+        D8_LAUNCH("batch_resolve_fwd", st,
+                  (resolve_fwd_f64<float><<<nb, kNodeBlock, 0, st>>>(N, link, val32, entry, succ, indeg,
+                                                                     cnt, acc, ext)));
+        D8_LAUNCH("batch_fwd_pass2", st,
+                  (fwd_walk_batch<2><<<w2, 64, P.lds[1], st>>>(dems, tile_dem, counters + 1, ntiles, link,
+                                                              val32, indeg, cnt, acc, ext, status)));
+    }
+    if (mode & D8_BATCH_ADJ) {
+        if (allow_lds(adj_walk_batch<1>, P.lds[2]) || allow_lds(adj_walk_batch<2>, P.lds[3])) return D8_EHIP;
+        const unsigned w1 = workers_for(reinterpret_cast<const void *>(adj_walk_batch<1>), P.lds[2], P.ntiles);
+        const unsigned w2 = workers_for(reinterpret_cast<const void *>(adj_walk_batch<2>), P.lds[3], P.ntiles);
+        reset_jump<<<1, 1, 0, st>>>(jstate);
+        D8_LAUNCH("batch_adj_pass1", st,
+                  (adj_walk_batch<1><<<w1, 64, P.lds[2], st>>>(dems, tile_dem, counters + 2, ntiles, link,
+                                                              val32, nullptr, nullptr, jstate, status)));
+        D8_LAUNCH("batch_graph_build", st,
+                  (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
+                                                                succ, nullptr)));
+        D8_LAUNCH("batch_adj_jump_init", st,
+                  (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(N, link, entry, succ, val32, jw[0], jw[1])));
+        int rounds = 1;
+        while (((int64_t)1 << (rounds - 1)) <= N) ++rounds;
+        for (int r = 0; r < rounds; ++r)
+            D8_LAUNCH("batch_adj_jump_round", st,
+                      (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(N, jw[r & 1], jw[(r + 1) & 1], jstate, r)));
+        D8_LAUNCH("batch_adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
+        D8_LAUNCH("batch_adj_pass2", st,
+                  (adj_walk_batch<2><<<w2, 64, P.lds[3], st>>>(dems, tile_dem, counters + 3, ntiles, link,
+                                                              nullptr, jw[0], jw[1], jstate, status)));
+    }
+    return last_error();
+}
+
+// Checks shared by the batch entry points; fills P.
+int batch_prepare(const d8_batch_item *items, int n, int mode, void *ws, size_t ws_bytes, BatchPlan &P)
+{
+    if (mode <= 0 || (mode & ~(D8_BATCH_FWD | D8_BATCH_ADJ)) != 0) return D8_EINVAL;
+    int rc = make_plan(items, n, P);
+    if (rc != D8_OK) return rc;
+    for (const DemDesc &D : P.dems) {
+        if ((mode & D8_BATCH_FWD) && !D.acc) return D8_EINVAL;
+        if ((mode & D8_BATCH_ADJ) && (!D.gacc || !D.gw)) return D8_EINVAL;
+    }
+    if (!ws || ws_bytes < P.L.total) return D8_EWORKSPACE;
+    return D8_OK;
+}
+
+struct GraphHandle {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 }  // namespace
 
@@ -348,18 +576,100 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr)));
     D8_LAUNCH("adj_jump_init", st,
-              (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(g, link, entry, succ, S, jw[0], jw[1])));
+              (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, entry, succ, S, jw[0], jw[1])));
     int rounds = 1;
     while (((int64_t)1 << (rounds - 1)) <= g.nnodes) ++rounds;
     for (int r = 0; r < rounds; ++r)
         D8_LAUNCH("adj_jump_round", st,
-                  (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(g, jw[r & 1], jw[(r + 1) & 1], jstate,
+                  (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(g.nnodes, jw[r & 1], jw[(r + 1) & 1], jstate,
                                                              r)));
     D8_LAUNCH("adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
     D8_LAUNCH("adj_pass2", st,
               (adj_walk<2><<<ntiles, thr, lds2, st>>>(dirs, grad_acc, g, link, nullptr, jw[0],
                                                       jw[1], jstate, grad_weights, status)));
     return last_error();
+}
+
+// ---------------------------------------------------------------- batch --
+
+size_t d8_batch_workspace_bytes(const d8_batch_item *items, int n)
+{
+    BatchPlan P;
+    if (make_plan(items, n, P) != D8_OK) return 0;
+    return P.L.total;
+}
+
+int flow_accum_batched(const d8_batch_item *items, int n, int mode, void *ws, size_t ws_bytes,
+                       void *stream)
+{
+    BatchPlan P;
+    int rc = batch_prepare(items, n, mode, ws, ws_bytes, P);
+    if (rc != D8_OK) return rc;
+    begin_call();
+    char *w8 = reinterpret_cast<char *>(ws);
+    hipStream_t st = as_stream(stream);
+    rc = upload_plan(P, w8, st);
+    if (rc != D8_OK) return rc;
+    return enqueue_batch(P, mode, w8, st);
+}
+
+int d8_graph_create(const d8_batch_item *items, int n, int mode, void *ws, size_t ws_bytes,
+                    void *stream, void **graph_exec)
+{
+    if (!graph_exec) return D8_EINVAL;
+    *graph_exec = nullptr;
+    BatchPlan P;
+    int rc = batch_prepare(items, n, mode, ws, ws_bytes, P);
+    if (rc != D8_OK) return rc;
+    begin_call();
+    char *w8 = reinterpret_cast<char *>(ws);
+    rc = upload_plan(P, w8, as_stream(stream));
+    if (rc != D8_OK) return rc;
+    // record on a stream of our own (the caller's may be the legacy default
+    // stream, which cannot be captured)
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return D8_EHIP;
+    GraphHandle *h = new GraphHandle;
+    rc = D8_EHIP;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        g_capturing = true;
+        int erc = enqueue_batch(P, mode, w8, cap);
+        g_capturing = false;
+        hipError_t e = hipStreamEndCapture(cap, &h->graph);
+        if (erc == D8_OK && e == hipSuccess &&
+            hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) == hipSuccess)
+            rc = D8_OK;
+        else if (erc != D8_OK)
+            rc = erc;
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc != D8_OK) {
+        if (h->exec) (void)hipGraphExecDestroy(h->exec);
+        if (h->graph) (void)hipGraphDestroy(h->graph);
+        delete h;
+        (void)hipGetLastError();
+        return rc;
+    }
+    *graph_exec = h;
+    return D8_OK;
+}
+
+int d8_graph_launch(void *graph_exec, void *stream)
+{
+    if (!graph_exec) return D8_EINVAL;
+    GraphHandle *h = reinterpret_cast<GraphHandle *>(graph_exec);
+    return hipGraphLaunch(h->exec, as_stream(stream)) == hipSuccess ? D8_OK : D8_EHIP;
+}
+
+int d8_graph_destroy(void *graph_exec)
+{
+    if (!graph_exec) return D8_EINVAL;
+    GraphHandle *h = reinterpret_cast<GraphHandle *>(graph_exec);
+    int rc = D8_OK;
+    if (h->exec && hipGraphExecDestroy(h->exec) != hipSuccess) rc = D8_EHIP;
+    if (h->graph && hipGraphDestroy(h->graph) != hipSuccess) rc = D8_EHIP;
+    delete h;
+    return rc;
 }
 
 const char *d8_last_error_message(void) { return g_last_error.c_str(); }

@@ -72,14 +72,14 @@ __global__ void d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ d
 // (itself if it is FlowExternal, none if its path terminates).  indeg (when
 // given) counts each exit node's children in the exit forest; it is not
 // changed afterwards, so the resolve can tell leaves from inner nodes.
-__global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
-                            const uint16_t *__restrict__ link, uint32_t *__restrict__ entry,
-                            uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg)
+__device__ inline void graph_node(const uint8_t *__restrict__ dirs, const Geo &g, int64_t node0,
+                                  int64_t id, const uint16_t *__restrict__ link,
+                                  uint32_t *__restrict__ entry, uint32_t *__restrict__ succ,
+                                  uint32_t *__restrict__ indeg)
 {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
+    const int64_t gid = node0 + id;
     uint32_t e = kNone, s = kNone;
-    if (link[id] == kLinkExt) {
+    if (link[gid] == kLinkExt) {
         int ty, tx, p, r, c;
         node_tile(g, id, ty, tx, p);
         ring_cell(p, tile_h(g, ty), tile_w(g, tx), r, c);
@@ -88,7 +88,7 @@ __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
         int64_t nr = gr + dir_dr(k), nc = gc + dir_dc(k);
         int uty = (int)(nr / g.th), utx = (int)(nc / g.tw);
         int lr = (int)(nr - (int64_t)uty * g.th), lc = (int)(nc - (int64_t)utx * g.tw);
-        int64_t ub = node_base(g, uty, utx);
+        int64_t ub = node0 + node_base(g, uty, utx);
         int q = ring_index(lr, lc, tile_h(g, uty), tile_w(g, utx));  // >= 0: borders a tile edge
         int64_t n = ub + (q < 0 ? 0 : q);
         uint16_t L = q < 0 ? kLinkNoData : link[n];
@@ -97,9 +97,35 @@ __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
             s = (L == kLinkExt) ? (uint32_t)n : (L == kLinkTerm ? kNone : (uint32_t)(ub + L));
         }
     }
-    entry[id] = e;
-    succ[id] = s;
+    entry[gid] = e;
+    succ[gid] = s;
     if (indeg && s != kNone) atomicAdd(&indeg[s], 1u);
+}
+
+__global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
+                            const uint16_t *__restrict__ link, uint32_t *__restrict__ entry,
+                            uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    graph_node(dirs, g, 0, id, link, entry, succ, indeg);
+}
+
+// Batch: the raster of node id starts at chunk_dem[id >> kChunkShift] and is
+// found by stepping forward over the (few) rasters that start in the chunk.
+constexpr int kChunkShift = 12;
+
+__global__ void graph_build_batch(const DemDesc *__restrict__ dems, int ndem,
+                                  const uint32_t *__restrict__ chunk_dem, int64_t nnodes,
+                                  const uint16_t *__restrict__ link, uint32_t *__restrict__ entry,
+                                  uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nnodes) return;
+    int d = (int)chunk_dem[id >> kChunkShift];
+    while (d + 1 < ndem && dems[d + 1].node0 <= id) ++d;
+    const DemDesc &D = dems[d];
+    graph_node(D.dirs, D.g, D.node0, id - D.node0, link, entry, succ, indeg);
 }
 
 // Forest accumulation over exit nodes (the paper's modified Algorithm 1 on the
@@ -110,13 +136,13 @@ __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
 // Unit counts: one 64-bit atomic per step updates (inflow sum : arrivals)
 // together -- adding (v << 32) + 1 -- so the last child reads the complete
 // sum from the returned value and no fence is needed.
-__global__ void resolve_fwd_u32(Geo g, const uint16_t *__restrict__ link,
+__global__ void resolve_fwd_u32(int64_t nnodes, const uint16_t *__restrict__ link,
                                 const uint32_t *__restrict__ aloc, const uint32_t *__restrict__ entry,
                                 const uint32_t *__restrict__ succ, const uint32_t *__restrict__ indeg,
                                 unsigned long long *packed, uint32_t *ext)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
+    if (id >= nnodes) return;
     if (link[id] != kLinkExt || indeg[id] != 0) return;
     uint32_t v = aloc[id];
     uint32_t n = entry[id], s = succ[id];
@@ -138,13 +164,13 @@ __global__ void resolve_fwd_u32(Geo g, const uint16_t *__restrict__ link,
 // Float weights: inflow sums in double; arrivals are counted separately, so
 // the last child's acquire pairs with the other children's releases.
 template <typename T>
-__global__ void resolve_fwd_f64(Geo g, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
+__global__ void resolve_fwd_f64(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
                                 const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
                                 const uint32_t *__restrict__ indeg, uint32_t *cnt, double *acc,
                                 double *ext)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
+    if (id >= nnodes) return;
     if (link[id] != kLinkExt || indeg[id] != 0) return;
     double v = (double)aloc[id];
     uint32_t n = entry[id], s = succ[id];
@@ -179,13 +205,13 @@ __device__ inline float jump_val(unsigned long long w) { return __uint_as_float(
 
 // Initial state: exits point at their successor with val = S(entry); every
 // other node is inert (done, 0) in both buffers.
-__global__ void adj_jump_init(Geo g, const uint16_t *__restrict__ link,
+__global__ void adj_jump_init(int64_t nnodes, const uint16_t *__restrict__ link,
                               const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
                               const float *__restrict__ S, unsigned long long *buf0,
                               unsigned long long *buf1)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
+    if (id >= nnodes) return;
     unsigned long long w = jump_word(kJumpDone, 0.0f);
     if (link[id] == kLinkExt) {
         const uint32_t n = entry[id];
@@ -201,7 +227,7 @@ __global__ void adj_jump_init(Geo g, const uint16_t *__restrict__ link,
 // nothing was live, records the final buffer in state[0] and does nothing.
 // live[(r+1)%3] is cleared here for the next round (its previous contents were
 // read by round r-1, which has completed).
-__global__ void adj_jump_round(Geo g, unsigned long long *w_in, unsigned long long *__restrict__ w_out,
+__global__ void adj_jump_round(int64_t nnodes, unsigned long long *w_in, unsigned long long *__restrict__ w_out,
                                uint32_t *state, int round)
 {
     uint32_t *live = state + 1;
@@ -215,7 +241,7 @@ __global__ void adj_jump_round(Geo g, unsigned long long *w_in, unsigned long lo
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id == 0) live[(round + 1) % 3] = 0;
     bool alive = false;
-    if (id < g.nnodes) {
+    if (id < nnodes) {
         const unsigned long long w = w_in[id];
         const uint32_t p = (uint32_t)w;
         if (p == kNone) {

@@ -883,15 +883,15 @@ __device__ inline void rows_out(const wk::WTile &Tl, const Geo &g, const T *avp,
 // counts keep (inflow sum << 32 | arrivals) in acc; float weights keep the
 // double sum in acc and arrivals in cnt.
 template <int PASS, typename T, typename V, typename E>
-__global__ void __launch_bounds__(64)
-fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
-         uint16_t *__restrict__ link, T *__restrict__ aloc, uint32_t *__restrict__ indeg,
-         uint32_t *__restrict__ cnt, V *__restrict__ acc, E *__restrict__ ext, T *__restrict__ out,
-         uint32_t *status)
+__device__ inline void fwd_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ w,
+                                const Geo &g, int64_t node0, int t, uint16_t *__restrict__ link,
+                                T *__restrict__ aloc, uint32_t *__restrict__ indeg,
+                                uint32_t *__restrict__ cnt, V *__restrict__ acc, E *__restrict__ ext,
+                                T *__restrict__ out, uint32_t *status, uint8_t *lds8)
 {
     using namespace wk;
-    extern __shared__ __align__(16) uint8_t lds8[];
-    const WTile Tl = wtile_of(g, blockIdx.x);
+    WTile Tl = wtile_of(g, t);
+    Tl.base += node0;
     using VT = FwdLds<PASS, T>;
     const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkFwd1 : kWalkFwd2, (int)sizeof(VT));
     uint8_t *cb8 = lds8;
@@ -961,15 +961,16 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
 //   PASS 1: per perimeter cell, the link and (entries) the sum of g along its in-tile path
 //   PASS 2: lambda for every cell, exits seeded with the resolved downstream sum
 template <int PASS>
-__global__ void __launch_bounds__(64)
-adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
-         uint16_t *__restrict__ link, float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
-         const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
-         float *__restrict__ out, uint32_t *status)
+__device__ inline void adj_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ gin,
+                                const Geo &g, int64_t node0, int t, uint16_t *__restrict__ link,
+                                float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
+                                const unsigned long long *__restrict__ mu1,
+                                const uint32_t *__restrict__ jstate, float *__restrict__ out,
+                                uint32_t *status, uint8_t *lds8)
 {
     using namespace wk;
-    extern __shared__ __align__(16) uint8_t lds8[];
-    const WTile Tl = wtile_of(g, blockIdx.x);
+    WTile Tl = wtile_of(g, t);
+    Tl.base += node0;
     const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkAdj1 : kWalkAdj2);
     uint8_t *cb8 = lds8;
     float *avp = reinterpret_cast<float *>(lds8 + L.av) - Tl.S;
@@ -1016,6 +1017,78 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
         set_status(status, kStatusCycle);
     __syncthreads();
     rows_out(Tl, g, avp, St.valid, out);
+}
+
+// ---- kernels: one raster (one wavefront per tile) ------------------------
+template <int PASS, typename T, typename V, typename E>
+__global__ void __launch_bounds__(64)
+fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
+         uint16_t *__restrict__ link, T *__restrict__ aloc, uint32_t *__restrict__ indeg,
+         uint32_t *__restrict__ cnt, V *__restrict__ acc, E *__restrict__ ext, T *__restrict__ out,
+         uint32_t *status)
+{
+    extern __shared__ __align__(16) uint8_t lds8[];
+    fwd_tile<PASS, T, V, E>(dirs, w, g, 0, blockIdx.x, link, aloc, indeg, cnt, acc, ext, out, status,
+                            lds8);
+}
+
+template <int PASS>
+__global__ void __launch_bounds__(64)
+adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
+         uint16_t *__restrict__ link, float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
+         const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
+         float *__restrict__ out, uint32_t *status)
+{
+    extern __shared__ __align__(16) uint8_t lds8[];
+    adj_tile<PASS>(dirs, gin, g, 0, blockIdx.x, link, Sg, mu0, mu1, jstate, out, status, lds8);
+}
+
+// ---- kernels: a batch of rasters ----------------------------------------
+// Persistent workers: each wavefront takes the next tile of the batch's tile
+// order (rasters by decreasing cost, tiles row-major) from a counter until
+// none is left.  tile_dem[t] is the raster of batch tile t.
+__device__ inline uint32_t next_tile(uint32_t *counter)
+{
+    uint32_t t = 0;
+    if (__lane_id() == 0) t = atomicAdd(counter, 1u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)t, 0, 64));
+}
+
+template <int PASS>
+__global__ void __launch_bounds__(64)
+fwd_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
+               uint32_t *counter, uint32_t ntiles, uint16_t *__restrict__ link,
+               float *__restrict__ aloc, uint32_t *__restrict__ indeg, uint32_t *__restrict__ cnt,
+               double *__restrict__ acc, double *__restrict__ ext, uint32_t *status)
+{
+    extern __shared__ __align__(16) uint8_t lds8[];
+    for (;;) {
+        const uint32_t t = next_tile(counter);
+        if (t >= ntiles) break;
+        const DemDesc &D = dems[tile_dem[t]];
+        fwd_tile<PASS, float, double, double>(D.dirs, D.w, D.g, D.node0, (int)(t - D.tile0), link,
+                                              aloc, indeg, cnt, acc, ext, D.acc, status, lds8);
+        __syncthreads();
+    }
+}
+
+template <int PASS>
+__global__ void __launch_bounds__(64)
+adj_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
+               uint32_t *counter, uint32_t ntiles, uint16_t *__restrict__ link,
+               float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
+               const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
+               uint32_t *status)
+{
+    extern __shared__ __align__(16) uint8_t lds8[];
+    for (;;) {
+        const uint32_t t = next_tile(counter);
+        if (t >= ntiles) break;
+        const DemDesc &D = dems[tile_dem[t]];
+        adj_tile<PASS>(D.dirs, D.gacc, D.g, D.node0, (int)(t - D.tile0), link, Sg, mu0, mu1, jstate,
+                       D.gw, status, lds8);
+        __syncthreads();
+    }
 }
 
 __host__ inline size_t walk_lds_bytes(int th, int tw, int kind, int vbytes = 4)

@@ -38,7 +38,7 @@ def test_workspace_bytes():
     lib = _lib.load()
     assert lib.d8_workspace_bytes(512, 512, 64, 64) > 0
     assert lib.d8_workspace_bytes(512, 512, 0, 0) == lib.d8_workspace_bytes(512, 512, 64, 64)
-    assert lib.d8_workspace_bytes(512, 512, 200, 200) == 0        # > 8192 cells per tile
+    assert lib.d8_workspace_bytes(512, 512, 200, 200) == 0        # a side above 64
     assert lib.d8_workspace_bytes(10, 10, 200, 200) > 0           # clipped to the raster
     assert lib.d8_workspace_bytes(512, 512, 0, 5) == 0
     assert lib.d8_workspace_bytes(-1, 5, 8, 8) == 0
@@ -70,6 +70,38 @@ def test_argument_errors_return_before_launch():
     assert lib.d8_check_status(None, None) == _lib.D8_EINVAL
     # empty raster, no workspace needed for d8_directions
     assert lib.d8_directions(None, None, 0, 4, 0.0, None) == _lib.D8_OK
+
+
+def test_batch_argument_errors_return_before_launch():
+    lib = _lib.load()
+    fake = 0x1000
+    It = _lib.BatchItem
+    items = (It * 3)(It(fake, None, fake, None, None, 100, 80, 0, 0),
+                     It(fake, None, fake, fake, fake, 0, 50, 0, 0),     # empty: skipped
+                     It(fake, fake, fake, None, None, 300, 20, 32, 16))
+    nb = lib.d8_batch_workspace_bytes(items, 3)
+    assert nb > lib.d8_batch_workspace_bytes(items, 1) > lib.d8_batch_workspace_bytes(items, 0) > 0
+    bad = (It * 1)(It(fake, None, fake, None, None, -1, 8, 0, 0))
+    assert lib.d8_batch_workspace_bytes(bad, 1) == 0
+    bad = (It * 1)(It(fake, None, fake, None, None, 100, 100, 0, 5))
+    assert lib.d8_batch_workspace_bytes(bad, 1) == 0
+    bad = (It * 1)(It(None, None, fake, None, None, 10, 10, 0, 0))   # no directions
+    assert lib.d8_batch_workspace_bytes(bad, 1) == 0
+    EINVAL, EWS = _lib.D8_EINVAL, _lib.D8_EWORKSPACE
+    FWD, ADJ = _lib.D8_BATCH_FWD, _lib.D8_BATCH_ADJ
+    assert lib.flow_accum_batched(items, 3, 0, fake, nb, None) == EINVAL
+    assert lib.flow_accum_batched(items, 3, 4, fake, nb, None) == EINVAL
+    assert lib.flow_accum_batched(items, 3, ADJ, fake, nb, None) == EINVAL   # item 0 has no g
+    assert lib.flow_accum_batched(items, 3, FWD, fake, nb - 1, None) == EWS
+    assert lib.flow_accum_batched(items, 3, FWD, None, 0, None) == EWS
+    assert lib.flow_accum_batched(None, 3, FWD, fake, nb, None) == EINVAL
+    assert lib.flow_accum_batched(items, -1, FWD, fake, nb, None) == EINVAL
+    h = ctypes.c_void_p()
+    assert lib.d8_graph_create(items, 3, 0, fake, nb, None, ctypes.byref(h)) == EINVAL
+    assert h.value is None
+    assert lib.d8_graph_create(items, 3, FWD, fake, nb, None, None) == EINVAL
+    assert lib.d8_graph_launch(None, None) == EINVAL
+    assert lib.d8_graph_destroy(None) == EINVAL
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
