@@ -8,9 +8,12 @@ from __future__ import annotations
 
 import argparse
 import json
+import multiprocessing as mp
 import os
 import sys
+import tempfile
 import time
+from multiprocessing import shared_memory
 
 import numpy as np
 
@@ -72,6 +75,175 @@ def cpu_baseline(z: np.ndarray, seed_g: int, rows: int) -> dict:
                       f"adjoint in float64 ({t2 - t1:.2f}s), serial C"}
 
 
+# ------------------------------------------------------------ batched leg --
+# 2000 DEMs of uneven sizes (side log-uniform in [64, 4096], aspect uniform in
+# [0.5, 2]), float32 weights and cotangents: forward + adjoint for all of
+# them as one recorded graph launch, against a loop of per-DEM calls.
+
+_SHM = {}
+
+
+def _batch_worker_init(names):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    for k, name in names.items():
+        _SHM[k] = shared_memory.SharedMemory(name=name)
+
+
+def _batch_worker(job):
+    off, rows, cols, lam, sd, sw, sg = job
+    n = rows * cols
+    for key, arr in (("dem", synth.dem(rows, cols, seed=sd, lambda0=lam)),
+                     ("w", synth.uniform((rows, cols), sw)), ("g", synth.uniform((rows, cols), sg))):
+        dst = np.ndarray((n,), dtype=np.float32, buffer=_SHM[key].buf, offset=4 * off)
+        dst[:] = arr.ravel()
+    return n
+
+
+class BatchData:
+    """DEMs, weights and cotangents of the batch in shared memory."""
+
+    def __init__(self, n: int, workers: int):
+        self.shapes = synth.batch_shapes(n)
+        self.off = np.concatenate([[0], np.cumsum([r * c for r, c, *_ in self.shapes])]).astype(np.int64)
+        total = int(self.off[-1])
+        self.shm = {k: shared_memory.SharedMemory(create=True, size=max(4, 4 * total))
+                    for k in ("dem", "w", "g")}
+        try:
+            jobs = [(int(self.off[i]), *self.shapes[i][:3], *self.shapes[i][3:])
+                    for i in range(n)]
+            jobs.sort(key=lambda j: -(j[1] * j[2]))
+            names = {k: v.name for k, v in self.shm.items()}
+            with mp.get_context("fork").Pool(workers, _batch_worker_init, (names,)) as pool:
+                done = sum(pool.imap_unordered(_batch_worker, jobs, chunksize=4))
+            assert done == total
+        except BaseException:
+            self.close()
+            raise
+        self.cells = total
+
+    def view(self, key: str, i: int) -> np.ndarray:
+        rows, cols = self.shapes[i][:2]
+        return np.ndarray((rows, cols), dtype=np.float32, buffer=self.shm[key].buf,
+                          offset=4 * int(self.off[i]))
+
+    def close(self):
+        for v in self.shm.values():
+            try:
+                v.close()
+                v.unlink()
+            except FileNotFoundError:
+                pass
+        self.shm = {}
+
+
+def batch_leg(bd: BatchData, reps: int) -> dict:
+    import torch
+    import paper_1608_04431_amd as d8
+    from paper_1608_04431_amd.autotune import Tuner, size_class
+    dev = torch.device("cuda:0")
+    n = len(bd.shapes)
+    rs = []
+    for i in range(n):
+        dem = torch.from_numpy(bd.view("dem", i)).to(dev)
+        dirs = d8.d8_directions(dem)
+        del dem
+        rs.append(dict(dirs=dirs, w=torch.from_numpy(bd.view("w", i)).to(dev),
+                       g=torch.from_numpy(bd.view("g", i)).to(dev)))
+    torch.cuda.synchronize()
+    bd.close()
+    log(f"batch resident: {n} DEMs, {bd.cells:.3e} cells")
+
+    # tile shape per size class, tuned in batch context on the class's DEMs
+    with tempfile.TemporaryDirectory() as tmp:
+        tuner = Tuner(path=os.path.join(tmp, "tiles.json"))
+        classes = {}
+        for r in rs:
+            classes.setdefault(size_class(*r["dirs"].shape), []).append(r)
+        tuned = {}
+        for cls, members in sorted(classes.items(), key=lambda kv: int(kv[0])):
+            times = tuner.tune_batch([(r["dirs"], r["w"], r["g"]) for r in members], save=False)
+            tuned[cls] = {f"{a}x{b}": round(v, 4) for (a, b), v in times.items()}
+        for r in rs:
+            r["tile"] = tuner.tile_for(*r["dirs"].shape, batch=True)
+    choice = {cls: "x".join(map(str, tuner.tile_for(int(cls), int(cls), batch=True))) for cls in tuned}
+    log(f"tiles per size class: {choice}")
+
+    # (i) looped: two C-ABI calls per DEM on one stream, one sync at the end
+    ws_bytes = max(d8.workspace_bytes(*r["dirs"].shape, r["tile"]) for r in rs)
+    ws = d8.Workspace(1, 1, (1, 1), dev)
+    ws.buf = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ws.nbytes = ws_bytes
+    for r in rs:
+        r["acc"] = torch.empty_like(r["w"])
+        r["gw"] = torch.empty_like(r["w"])
+
+    def looped():
+        for r in rs:
+            d8.flow_accum(r["dirs"], r["w"], "f32", r["tile"], ws, r["acc"])
+            d8.flow_accum_adjoint(r["dirs"], r["g"], r["tile"], ws, r["gw"])
+
+    def timed(fn):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        out = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            start.record()
+            fn()
+            stop.record()
+            torch.cuda.synchronize()
+            out.append(start.elapsed_time(stop))
+        return float(np.median(out)), out
+
+    looped()
+    torch.cuda.synchronize()
+    d8.timing_enable(True)
+    looped()
+    torch.cuda.synchronize()
+    d8.timing_enable(False)
+    launches_looped = sum(c for _, c in d8.timing_report().values())
+    t_loop, loop_all = timed(looped)
+    d8.check_status(ws)
+    log(f"looped: {t_loop:.2f} ms (median of {reps})")
+
+    # (ii) batched: one graph launch for all DEMs, forward + adjoint
+    rasters = [d8.Raster(r["dirs"], r["w"], r["g"], tile=r["tile"]) for r in rs]
+    batch = d8.Batch(rasters, "fwd+adj", dev)
+    # per-kernel times of the same work, launched without the graph
+    batch.run()
+    torch.cuda.synchronize()
+    d8.timing_enable(True)
+    batch.run()
+    torch.cuda.synchronize()
+    d8.timing_enable(False)
+    batch_kernels = {k: round(ms, 3) for k, (ms, c) in d8.timing_report().items()}
+    graph = batch.graph()
+    try:
+        graph.launch()
+        t_graph, graph_all = timed(graph.launch)
+        batch.check_status()
+    finally:
+        graph.destroy()
+    log(f"batched graph: {t_graph:.2f} ms (median of {reps})")
+    same = all(torch.equal(rr.acc, r["acc"]) and torch.equal(rr.grad_weights, r["gw"])
+               for rr, r in zip(rasters, rs))
+    bytes_alg = 18.0 * bd.cells  # forward 1 + 4 + 4, adjoint 1 + 4 + 4 bytes per cell
+    return {
+        "workload": f"{n} DEMs, sides log-uniform in [64, 4096], aspect uniform in [0.5, 2], "
+                    "filled value-noise terrain (wavelength max side / 8), float32 weights and "
+                    "cotangents U[0,1); forward (f32) + adjoint",
+        "dems": n, "cells": int(bd.cells),
+        "looped_ms": t_loop, "batched_ms": t_graph, "speedup": t_loop / t_graph,
+        "looped_cells_per_s": bd.cells / (t_loop * 1e-3),
+        "batched_cells_per_s": bd.cells / (t_graph * 1e-3),
+        "batched_hbm_GBps_algorithmic": bytes_alg / (t_graph * 1e-3) / 1e9,
+        "batched_frac_hbm_peak": bytes_alg / (t_graph * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "launches_looped": int(launches_looped), "launches_batched": 1,
+        "reps_ms": {"looped": [round(x, 3) for x in loop_all], "batched": [round(x, 3) for x in graph_all]},
+        "tiles": choice, "tuning_ms": tuned, "outputs_identical": bool(same),
+        "kernels_ms": batch_kernels,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +254,11 @@ def main():
     ap.add_argument("--cache-dir", default=os.environ.get("D8_CACHE_DIR"))
     ap.add_argument("--cpu-rows", type=int, default=6144,
                     help="rows of the raster in the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--batch", type=int, default=2000,
+                    help="DEMs in the batched-vs-looped leg (0 = skip)")
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host processes generating the batch")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -89,6 +266,22 @@ def main():
               "(see DESIGN.md for how the method would shard).", file=sys.stderr)
         sys.exit(2)
 
+    # the batch is generated by forked workers before anything touches the GPU
+    bd = None
+    if args.batch > 0:
+        t = time.time()
+        bd = BatchData(args.batch, args.workers)
+        log(f"generated batch of {args.batch} DEMs ({bd.cells:.3e} cells) in {time.time() - t:.1f}s "
+            f"with {args.workers} workers")
+    try:
+        out = run(args, bd)
+    finally:
+        if bd is not None:
+            bd.close()
+    print(json.dumps(out), flush=True)
+
+
+def run(args, bd):
     import torch
     import paper_1608_04431_amd as d8
 
@@ -180,7 +373,11 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    if bd is not None:
+        del A, lam, ws, dirs, g
+        torch.cuda.empty_cache()
+        out["batched"] = batch_leg(bd, args.batch_reps)
+    return out
 
 
 if __name__ == "__main__":

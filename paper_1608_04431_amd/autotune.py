@@ -1,0 +1,177 @@
+"""Tile-shape autotuner.
+
+Times candidate tile shapes on a sample raster of a size class (forward in
+float32 plus the adjoint, events on the current stream) and keeps the
+fastest per (device, size class) in a JSON cache.  The paper leaves the tile
+size free (Section "The Algorithm": equal tiles are a convenience); on the GPU
+it trades LDS per tile (resident tiles per CU) against the number of
+perimeter cells in the global graph.
+
+Cache lookup order: the user cache (``$D8_TUNE_CACHE`` or
+``~/.cache/d8flow/tiles.json``), then the table shipped with the package
+(``tiles_mi355x.json``), then 64 x 64.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PACKAGED = os.path.join(HERE, "tiles_mi355x.json")
+DEFAULT_TILE = (64, 64)
+CANDIDATES = ((64, 64), (64, 32), (32, 64), (64, 48), (48, 64), (32, 32))
+
+
+def size_class(rows: int, cols: int) -> str:
+    """Rasters are grouped by their longer side, rounded up to a power of two
+    (at least 64)."""
+    s = max(int(rows), int(cols), 1)
+    k = max(6, (s - 1).bit_length())
+    return str(1 << k)
+
+
+def device_key(device=None) -> str:
+    if not torch.cuda.is_available():
+        return "cpu"
+    props = torch.cuda.get_device_properties(device or torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "") or ""
+    return f"{props.name}|{arch.split(':')[0]}"
+
+
+def user_cache_path() -> str:
+    return os.environ.get("D8_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "d8flow", "tiles.json")
+
+
+def _read(path: str) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+class Tuner:
+    """tile_for(rows, cols) -> (tile_rows, tile_cols); tune(...) measures."""
+
+    def __init__(self, path: str | None = None, device=None):
+        self.path = path or user_cache_path()
+        self.device = device
+        self.key = device_key(device)
+        self.user = _read(self.path)
+        self.packaged = _read(PACKAGED)
+
+    def _key(self, batch: bool) -> str:
+        return self.key + ("|batch" if batch else "")
+
+    def lookup(self, rows: int, cols: int, batch: bool = False):
+        cls = size_class(rows, cols)
+        for table in (self.user, self.packaged):
+            entry = table.get(self._key(batch), {}).get(cls)
+            if entry:
+                return tuple(int(v) for v in entry["tile"])
+        return None
+
+    def tile_for(self, rows: int, cols: int, batch: bool = False) -> tuple[int, int]:
+        """Tile shape for a raster run on its own, or (batch=True) as one of
+        many rasters in a batch; a batch lookup falls back to the single one."""
+        if batch:
+            t = self.lookup(rows, cols, True)
+            if t:
+                return t
+        return self.lookup(rows, cols) or DEFAULT_TILE
+
+    def tune(self, dirs: torch.Tensor, weights: torch.Tensor | None = None,
+             grad_acc: torch.Tensor | None = None, candidates=CANDIDATES, reps: int = 3,
+             save: bool = True) -> dict:
+        """Times forward (float32) + adjoint for every candidate on `dirs`
+        (a sample of its size class), records the fastest for the class and
+        returns {tile: ms}."""
+        from . import Workspace, flow_accum, flow_accum_adjoint
+        rows, cols = dirs.shape
+        if weights is None:
+            weights = torch.ones(dirs.shape, dtype=torch.float32, device=dirs.device)
+        if grad_acc is None:
+            grad_acc = torch.ones(dirs.shape, dtype=torch.float32, device=dirs.device)
+        acc = torch.empty(dirs.shape, dtype=torch.float32, device=dirs.device)
+        lam = torch.empty_like(acc)
+        times = {}
+        for tile in candidates:
+            th, tw = min(tile[0], rows), min(tile[1], cols)
+            if (th, tw) in times:
+                continue
+            ws = Workspace(rows, cols, (th, tw), dirs.device)
+
+            def step():
+                flow_accum(dirs, weights, "f32", (th, tw), ws, acc)
+                flow_accum_adjoint(dirs, grad_acc, (th, tw), ws, lam)
+
+            step()
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            best = None
+            for _ in range(reps):
+                start.record()
+                step()
+                stop.record()
+                stop.synchronize()
+                ms = start.elapsed_time(stop)
+                best = ms if best is None else min(best, ms)
+            times[(th, tw)] = best
+        tile = min(times, key=times.get)
+        cls = size_class(rows, cols)
+        self.user.setdefault(self.key, {})[cls] = {
+            "tile": list(tile), "ms": round(times[tile], 4), "sample": [rows, cols],
+            "candidates": {f"{a}x{b}": round(v, 4) for (a, b), v in times.items()}}
+        if save:
+            self.save()
+        return times
+
+    def tune_batch(self, samples, candidates=CANDIDATES, reps: int = 2, save: bool = True) -> dict:
+        """Tile shape for rasters of one size class run together: times one
+        recorded batch (forward float32 + adjoint) of all `samples` -- a
+        list of (dirs, weights, grad_acc) -- per candidate.  In a batch the
+        other rasters supply the parallelism, so this favours per-cell
+        efficiency where tune() favours one raster's latency."""
+        from . import Batch, Raster
+        if not samples:
+            return {}
+        outs = [(torch.empty_like(w), torch.empty_like(g)) for _, w, g in samples]
+        cls = size_class(*max((d.shape for d, _, _ in samples), key=lambda s: s[0] * s[1]))
+        times = {}
+        for tile in candidates:
+            rasters = [Raster(d, w, g, tile=tile, acc=a, grad_weights=l)
+                       for (d, w, g), (a, l) in zip(samples, outs)]
+            graph = Batch(rasters, "fwd+adj", samples[0][0].device).graph()
+            try:
+                graph.launch()
+                start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                best = None
+                for _ in range(reps):
+                    start.record()
+                    graph.launch()
+                    stop.record()
+                    stop.synchronize()
+                    ms = start.elapsed_time(stop)
+                    best = ms if best is None else min(best, ms)
+            finally:
+                graph.destroy()
+            times[tuple(tile)] = best
+        tile = min(times, key=times.get)
+        self.user.setdefault(self._key(True), {})[cls] = {
+            "tile": list(tile), "ms": round(times[tile], 4), "rasters": len(samples),
+            "candidates": {f"{a}x{b}": round(v, 4) for (a, b), v in times.items()}}
+        if save:
+            self.save()
+        return times
+
+    def save(self) -> None:
+        d = os.path.dirname(self.path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.user, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)

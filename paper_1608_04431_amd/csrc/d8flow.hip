@@ -239,33 +239,50 @@ struct BatchLayout {
     size_t link, entry, succ, indeg, cnt, val32, acc64, ext64, total;
 };
 
+// Rasters of one tile shape: a contiguous range of the batch's tiles, run by
+// one persistent launch per stage with that shape's LDS size.
+struct TileGroup {
+    int th, tw;
+    int64_t t_begin, t_end;
+    size_t lds[4];  // fwd pass 1, fwd pass 2, adj pass 1, adj pass 2
+};
+constexpr int kMaxGroups = 16;  // 4 stages x 16 counters in the counter block
+
 struct BatchPlan {
     std::vector<DemDesc> dems;
     std::vector<uint32_t> tile_dem, chunk_dem;
+    std::vector<TileGroup> groups;
     int64_t ntiles = 0, nnodes = 0;
-    size_t lds[4] = {0, 0, 0, 0};  // fwd pass 1, fwd pass 2, adj pass 1, adj pass 2
     BatchLayout L{};
 };
 
 int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
 {
     if (n < 0 || (n > 0 && !items)) return D8_EINVAL;
-    std::vector<int> order;
+    struct Entry { int i; Geo g; };
+    std::vector<Entry> order;
     for (int i = 0; i < n; ++i) {
         const d8_batch_item &it = items[i];
         if (it.rows < 0 || it.cols < 0) return D8_EINVAL;
-        if (it.rows > 0 && it.cols > 0) order.push_back(i);
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return items[a].rows * items[a].cols > items[b].rows * items[b].cols;
-    });
-    for (int i : order) {
-        const d8_batch_item &it = items[i];
+        if (it.rows == 0 || it.cols == 0) continue;
         int th = it.tile_rows, tw = it.tile_cols;
         Geo g;
         bool empty = false;
         int rc = check_common(it.rows, it.cols, th, tw, g, empty);
         if (rc != D8_OK) return rc;
+        order.push_back({i, g});
+    }
+    // group by the requested tile shape (LDS size of a launch), largest
+    // rasters first within a group
+    std::stable_sort(order.begin(), order.end(), [&](const Entry &a, const Entry &b) {
+        const d8_batch_item &x = items[a.i], &y = items[b.i];
+        if (x.tile_rows != y.tile_rows) return x.tile_rows > y.tile_rows;
+        if (x.tile_cols != y.tile_cols) return x.tile_cols > y.tile_cols;
+        return x.rows * x.cols > y.rows * y.cols;
+    });
+    for (const Entry &e : order) {
+        const d8_batch_item &it = items[e.i];
+        const Geo &g = e.g;
         DemDesc D;
         D.g = g;
         D.node0 = P.nnodes;
@@ -277,15 +294,22 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
         D.gw = it.grad_weights;
         if (!D.dirs) return D8_EINVAL;
         const int64_t nt = (int64_t)g.nty * g.ntx;
+        const int key_th = it.tile_rows, key_tw = it.tile_cols;
+        if (P.groups.empty() || P.groups.back().th != key_th || P.groups.back().tw != key_tw) {
+            if ((int)P.groups.size() == kMaxGroups) return D8_EINVAL;
+            P.groups.push_back({key_th, key_tw, P.ntiles, P.ntiles, {0, 0, 0, 0}});
+        }
+        TileGroup &G = P.groups.back();
         for (int64_t t = 0; t < nt; ++t) P.tile_dem.push_back((uint32_t)P.dems.size());
         P.dems.push_back(D);
         P.ntiles += nt;
         P.nnodes += g.nnodes;
+        G.t_end = P.ntiles;
         if (P.nnodes >= (int64_t)kJumpDone || P.ntiles >= (int64_t)INT_MAX) return D8_EINVAL;
-        P.lds[0] = std::max(P.lds[0], walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4));
-        P.lds[1] = std::max(P.lds[1], walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4));
-        P.lds[2] = std::max(P.lds[2], walk_lds_bytes(g.th, g.tw, kWalkAdj1, 4));
-        P.lds[3] = std::max(P.lds[3], walk_lds_bytes(g.th, g.tw, kWalkAdj2, 4));
+        G.lds[0] = std::max(G.lds[0], walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4));
+        G.lds[1] = std::max(G.lds[1], walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4));
+        G.lds[2] = std::max(G.lds[2], walk_lds_bytes(g.th, g.tw, kWalkAdj1, 4));
+        G.lds[3] = std::max(G.lds[3], walk_lds_bytes(g.th, g.tw, kWalkAdj2, 4));
     }
     const int64_t nchunk = (P.nnodes >> kChunkShift) + 1;
     P.chunk_dem.assign((size_t)nchunk, 0);
@@ -323,7 +347,7 @@ __global__ void init_batch(uint32_t *status, uint32_t *jstate, uint32_t *counter
     jstate[1] = 0;
     jstate[2] = 0;
     jstate[3] = 1;
-    for (int i = 0; i < 4; ++i) counters[i] = 0;
+    for (int i = 0; i < 4 * kMaxGroups; ++i) counters[i] = 0;
 }
 
 __global__ void reset_jump(uint32_t *jstate)
@@ -384,37 +408,42 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
     unsigned long long *jw[2] = {reinterpret_cast<unsigned long long *>(ws + L.acc64),
                                  reinterpret_cast<unsigned long long *>(ws + L.ext64)};
     const int ndem = (int)P.dems.size();
-    const uint32_t ntiles = (uint32_t)P.ntiles;
     const int64_t N = P.nnodes;
     const unsigned nb = blocks_for(N, kNodeBlock);
 
     init_batch<<<1, 1, 0, st>>>(status, jstate, counters);
     if (ndem == 0) return last_error();
+    // one persistent launch per tile group and stage; counter 16 * stage + group
+    auto tiles = [&](int stage, auto kernel, const char *name, auto &&...args) -> int {
+        for (size_t k = 0; k < P.groups.size(); ++k) {
+            const TileGroup &G = P.groups[k];
+            const size_t lds = G.lds[stage];
+            if (allow_lds(kernel, lds)) return D8_EHIP;
+            const unsigned w = workers_for(reinterpret_cast<const void *>(kernel), lds, G.t_end - G.t_begin);
+            D8_LAUNCH(name, st,
+                      (kernel<<<w, 64, lds, st>>>(dems, tile_dem, counters + kMaxGroups * stage + k,
+                                                  (uint32_t)G.t_begin, (uint32_t)G.t_end, args...)));
+        }
+        return D8_OK;
+    };
     if (mode & D8_BATCH_FWD) {
-        if (allow_lds(fwd_walk_batch<1>, P.lds[0]) || allow_lds(fwd_walk_batch<2>, P.lds[1])) return D8_EHIP;
-        const unsigned w1 = workers_for(reinterpret_cast<const void *>(fwd_walk_batch<1>), P.lds[0], P.ntiles);
-        const unsigned w2 = workers_for(reinterpret_cast<const void *>(fwd_walk_batch<2>), P.lds[1], P.ntiles);
-        D8_LAUNCH("batch_fwd_pass1", st,
-                  (fwd_walk_batch<1><<<w1, 64, P.lds[0], st>>>(dems, tile_dem, counters + 0, ntiles, link,
-                                                              val32, indeg, cnt, acc, ext, status)));
+        if (tiles(0, fwd_walk_batch<1>, "batch_fwd_pass1", link, val32, indeg, cnt, acc, ext, status))
+            return D8_EHIP;
         D8_LAUNCH("batch_graph_build", st,
                   (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
                                                                 succ, indeg)));
         D8_LAUNCH("batch_resolve_fwd", st,
                   (resolve_fwd_f64<float><<<nb, kNodeBlock, 0, st>>>(N, link, val32, entry, succ, indeg,
                                                                      cnt, acc, ext)));
-        D8_LAUNCH("batch_fwd_pass2", st,
-                  (fwd_walk_batch<2><<<w2, 64, P.lds[1], st>>>(dems, tile_dem, counters + 1, ntiles, link,
-                                                              val32, indeg, cnt, acc, ext, status)));
+        if (tiles(1, fwd_walk_batch<2>, "batch_fwd_pass2", link, val32, indeg, cnt, acc, ext, status))
+            return D8_EHIP;
     }
     if (mode & D8_BATCH_ADJ) {
-        if (allow_lds(adj_walk_batch<1>, P.lds[2]) || allow_lds(adj_walk_batch<2>, P.lds[3])) return D8_EHIP;
-        const unsigned w1 = workers_for(reinterpret_cast<const void *>(adj_walk_batch<1>), P.lds[2], P.ntiles);
-        const unsigned w2 = workers_for(reinterpret_cast<const void *>(adj_walk_batch<2>), P.lds[3], P.ntiles);
         reset_jump<<<1, 1, 0, st>>>(jstate);
-        D8_LAUNCH("batch_adj_pass1", st,
-                  (adj_walk_batch<1><<<w1, 64, P.lds[2], st>>>(dems, tile_dem, counters + 2, ntiles, link,
-                                                              val32, nullptr, nullptr, jstate, status)));
+        const unsigned long long *none = nullptr;
+        if (tiles(2, adj_walk_batch<1>, "batch_adj_pass1", link, val32, none, none,
+                  (const uint32_t *)jstate, status))
+            return D8_EHIP;
         D8_LAUNCH("batch_graph_build", st,
                   (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
                                                                 succ, nullptr)));
@@ -426,9 +455,11 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
             D8_LAUNCH("batch_adj_jump_round", st,
                       (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(N, jw[r & 1], jw[(r + 1) & 1], jstate, r)));
         D8_LAUNCH("batch_adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
-        D8_LAUNCH("batch_adj_pass2", st,
-                  (adj_walk_batch<2><<<w2, 64, P.lds[3], st>>>(dems, tile_dem, counters + 3, ntiles, link,
-                                                              nullptr, jw[0], jw[1], jstate, status)));
+        const unsigned long long *m0 = jw[0], *m1 = jw[1];
+        float *nof = nullptr;
+        if (tiles(3, adj_walk_batch<2>, "batch_adj_pass2", link, nof, m0, m1, (const uint32_t *)jstate,
+                  status))
+            return D8_EHIP;
     }
     return last_error();
 }

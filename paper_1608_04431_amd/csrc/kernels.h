@@ -161,8 +161,10 @@ __global__ void resolve_fwd_u32(int64_t nnodes, const uint16_t *__restrict__ lin
     }
 }
 
-// Float weights: inflow sums in double; arrivals are counted separately, so
-// the last child's acquire pairs with the other children's releases.
+// Float weights: inflow sums in double, arrivals counted separately.  Every
+// access to acc and cnt is an atomic (performed where all XCDs see it), and
+// a child counts its arrival only after its add has returned, so the last
+// child's atomic read of acc sees every child's sum -- no cache-wide fences.
 template <typename T>
 __global__ void resolve_fwd_f64(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
                                 const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
@@ -180,10 +182,12 @@ __global__ void resolve_fwd_f64(int64_t nnodes, const uint16_t *__restrict__ lin
         if (s == kNone) break;
         const double as = (double)aloc[s];
         const uint32_t is = indeg[s], ns = entry[s], ss = succ[s];
-        atomicAdd(&acc[s], v);
-        uint32_t old = __hip_atomic_fetch_add(&cnt[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const double before = atomicAdd(&acc[s], v);
+        uint32_t one = 1u;
+        asm volatile("" : "+v"(one) : "v"(before));  // the count waits for the add
+        const uint32_t old = atomicAdd(&cnt[s], one);
         if (old + 1u != is) break;
-        v = as + __hip_atomic_load(&acc[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        v = as + atomicAdd(&acc[s], 0.0);
         n = ns;
         s = ss;
     }

@@ -1044,9 +1044,10 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
 }
 
 // ---- kernels: a batch of rasters ----------------------------------------
-// Persistent workers: each wavefront takes the next tile of the batch's tile
-// order (rasters by decreasing cost, tiles row-major) from a counter until
-// none is left.  tile_dem[t] is the raster of batch tile t.
+// Persistent workers: each wavefront takes the next tile of its range of the
+// batch's tile order (rasters grouped by tile shape, by decreasing cost within
+// a group, tiles row-major) from a counter until none is left.  tile_dem[t]
+// is the raster of batch tile t.
 __device__ inline uint32_t next_tile(uint32_t *counter)
 {
     uint32_t t = 0;
@@ -1057,14 +1058,14 @@ __device__ inline uint32_t next_tile(uint32_t *counter)
 template <int PASS>
 __global__ void __launch_bounds__(64)
 fwd_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
-               uint32_t *counter, uint32_t ntiles, uint16_t *__restrict__ link,
+               uint32_t *counter, uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
                float *__restrict__ aloc, uint32_t *__restrict__ indeg, uint32_t *__restrict__ cnt,
                double *__restrict__ acc, double *__restrict__ ext, uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
     for (;;) {
-        const uint32_t t = next_tile(counter);
-        if (t >= ntiles) break;
+        const uint32_t t = t_begin + next_tile(counter);
+        if (t >= t_end) break;
         const DemDesc &D = dems[tile_dem[t]];
         fwd_tile<PASS, float, double, double>(D.dirs, D.w, D.g, D.node0, (int)(t - D.tile0), link,
                                               aloc, indeg, cnt, acc, ext, D.acc, status, lds8);
@@ -1075,15 +1076,15 @@ fwd_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ ti
 template <int PASS>
 __global__ void __launch_bounds__(64)
 adj_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
-               uint32_t *counter, uint32_t ntiles, uint16_t *__restrict__ link,
+               uint32_t *counter, uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
                float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
                const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
                uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
     for (;;) {
-        const uint32_t t = next_tile(counter);
-        if (t >= ntiles) break;
+        const uint32_t t = t_begin + next_tile(counter);
+        if (t >= t_end) break;
         const DemDesc &D = dems[tile_dem[t]];
         adj_tile<PASS>(D.dirs, D.gacc, D.g, D.node0, (int)(t - D.tile0), link, Sg, mu0, mu1, jstate,
                        D.gw, status, lds8);
