@@ -11,6 +11,7 @@ Functions (each follows one passage of the paper; see ``oracle.c``):
   transpose_f64 the adjoint lambda = (I-P)^-T g (reverse topological sweep)
   brute_*       path walking, independent of the Kahn order (small inputs)
   upstream_sum  one value of A from its definition (catchment search)
+  downstream_sum one value of the adjoint from its definition (path walk)
   tiled         Algorithms 1-3 literally (small inputs), with intermediates
   path_stats    critical-path statistics for a tile shape (sizing only)
 """
@@ -70,6 +71,8 @@ def _load():
     lib.orc_brute_u64.argtypes = [vp, i64, i64, vp]
     lib.orc_upstream_sum.argtypes = [vp, i64, i64, vp, i64, i64]
     lib.orc_upstream_sum.restype = ctypes.c_double
+    lib.orc_downstream_sum.argtypes = [vp, i64, i64, vp, i64, i64]
+    lib.orc_downstream_sum.restype = ctypes.c_double
     lib.orc_tiled.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp, vp]
     lib.orc_path_stats.argtypes = [vp, i64, i64, i64, i64, vp]
     for name in ("orc_d8", "orc_receivers", "orc_accum_u64", "orc_accum_f64", "orc_accum_f64d",
@@ -183,6 +186,18 @@ def upstream_sum(dirs: np.ndarray, r: int, c: int, w: np.ndarray | None = None,
         w = np.ascontiguousarray(w, dtype=np.float32)
     v = _load().orc_upstream_sum(_p(dirs), dirs.shape[0], dirs.shape[1], _p(w),
                                  r * dirs.shape[1] + c, max_cells)
+    if v < 0:
+        raise OracleError(-5)
+    return v
+
+
+def downstream_sum(dirs: np.ndarray, r: int, c: int, g: np.ndarray,
+                   max_steps: int = 1 << 40) -> float:
+    """lambda at (r, c): the sum of g along the cell's downstream path."""
+    dirs = _dirs(dirs)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    v = _load().orc_downstream_sum(_p(dirs), dirs.shape[0], dirs.shape[1], _p(g),
+                                   r * dirs.shape[1] + c, max_steps)
     if v < 0:
         raise OracleError(-5)
     return v

@@ -305,6 +305,27 @@ double orc_upstream_sum(const uint8_t *dirs, int64_t rows, int64_t cols, const f
     return s;
 }
 
+/*
+ * One value of the adjoint from its definition: lambda(x) = g(x) + lambda of
+ * x's receiver, i.e. the sum of g over x's downstream flow path (x, its
+ * receiver, that cell's receiver, ... up to a cell without one).  0 for a
+ * NoData cell; -1 for an invalid code or a path longer than max_steps (a
+ * cycle).
+ */
+double orc_downstream_sum(const uint8_t *dirs, int64_t rows, int64_t cols, const float *g,
+                          int64_t x, int64_t max_steps)
+{
+    if (dirs[x] >= OR_NODATA) return dirs[x] == OR_NODATA ? 0.0 : -1.0;
+    double s = 0.0;
+    for (int64_t steps = 0; x >= 0; ++steps) {
+        if (steps > max_steps) return -1.0;
+        s += (double)g[x];
+        x = receiver(dirs, rows, cols, x);
+        if (x == -2) return -1.0;
+    }
+    return s;
+}
+
 /* --------------------------------------------- tiled scheme, literally --- */
 /*
  * The paper's tiled method (Algorithms 1-3), written out literally, for small

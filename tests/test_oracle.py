@@ -355,6 +355,28 @@ def test_d8_tie_breaks_lowest_index():
 
 
 # ------------------------------------------------------------ spot values ----
+def test_downstream_sum_matches_transpose_and_brute_force():
+    rng = np.random.default_rng(77)
+    for seed in range(3):
+        z = rng.permutation(30 * 41).astype(np.float32).reshape(30, 41)
+        z[rng.random(z.shape) < 0.1] = -9999.0
+        d = oracle.d8(z)
+        g = rng.random(d.shape).astype(np.float32)
+        lam = oracle.transpose_f64(d, g)
+        _, lam_b = oracle.brute_f64(d, g=g)
+        for r, c in zip(rng.integers(0, 30, 40), rng.integers(0, 41, 40)):
+            v = oracle.downstream_sum(d, int(r), int(c), g)
+            assert abs(v - lam[r, c]) <= 1e-12 * max(1.0, lam[r, c])
+            assert abs(v - lam_b[r, c]) <= 1e-12 * max(1.0, lam[r, c])
+    # hand case: a row flowing east sums g from the cell to the east edge
+    d = np.full((1, 5), 4, np.uint8)
+    g = np.array([[1, 2, 4, 8, 16]], np.float32)
+    assert [oracle.downstream_sum(d, 0, c, g) for c in range(5)] == [31, 30, 28, 24, 16]
+    cyc = np.array([[4, 3]], np.uint8)   # two cells pointing at each other
+    with pytest.raises(oracle.OracleError):
+        oracle.downstream_sum(cyc, 0, 0, np.ones((1, 2), np.float32), max_steps=10)
+
+
 def test_upstream_sum_matches_kahn():
     d = random_acyclic_dirs(50, 50, 21)
     w = synth.uniform(d.shape, 22)
