@@ -37,6 +37,45 @@ KERNEL_BYTES_PER_CELL = {
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
 
 
+KERNEL_NAMES = {  # timing label -> kernel symbol prefix in profiler output
+    "fwd_pass1": "void d8::fwd_walk<1, unsigned int",
+    "fwd_pass2": "void d8::fwd_walk<2, unsigned int",
+    "adj_pass1": "void d8::adj_walk<1>",
+    "adj_pass2": "void d8::adj_walk<2>",
+}
+SOURCES = ("paper_1608_04431_amd/csrc/d8flow.hip", "paper_1608_04431_amd/csrc/kernels.h",
+           "paper_1608_04431_amd/csrc/walk.h", "paper_1608_04431_amd/csrc/d8_common.h")
+
+
+def source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<kernel>_<workload>.txt), or None when there is none or
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -259,6 +298,9 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="host processes generating the batch")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of MIB MiB before timing (a kernel of known "
+                         "traffic for scaling hardware counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -300,6 +342,15 @@ def run(args, bd):
     A = torch.empty((rows, cols), dtype=torch.int32, device=dev)
     lam = torch.empty((rows, cols), dtype=torch.float32, device=dev)
     ws = d8.Workspace(rows, cols, tile, dev)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
+        del src, dst
     torch.cuda.synchronize()
     log(f"inputs resident: {rows}x{cols}, tile {tile}, workspace {ws.nbytes / 2**30:.2f} GiB")
 
@@ -335,7 +386,7 @@ def run(args, bd):
     dom_ms = per_launch[dom][0]
     dom_bytes = KERNEL_BYTES_PER_CELL.get(dom)
     roofline = {"bound": "hbm", "kernel": dom, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "traffic": None}
+                "traffic": measured_traffic(dom, args.workload)}
     if dom_bytes is not None:
         achieved = dom_bytes * n_cells / (dom_ms * 1e-3) / 1e9
         roofline.update(achieved=achieved, frac=achieved / HBM_PEAK_GBPS,

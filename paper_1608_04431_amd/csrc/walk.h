@@ -1020,6 +1020,17 @@ __device__ inline void adj_tile(const uint8_t *__restrict__ dirs, const float *_
 }
 
 // ---- kernels: one raster (one wavefront per tile) ------------------------
+// Workgroups go to the 8 XCDs in turn (block b to XCD b % 8), and each XCD
+// has its own L2.  Block b therefore takes tile (b % 8) * n/8 + b / 8: every
+// XCD works through a contiguous eighth of the row-major tile order, so the
+// tiles beside and below a tile -- which read the same cache lines of the
+// direction raster (row segments, halo cells) -- are served by one L2.
+__device__ inline int xcd_tile(int b, int n)
+{
+    const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <int PASS, typename T, typename V, typename E>
 __global__ void __launch_bounds__(64)
 fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
@@ -1028,8 +1039,8 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
          uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
-    fwd_tile<PASS, T, V, E>(dirs, w, g, 0, blockIdx.x, link, aloc, indeg, cnt, acc, ext, out, status,
-                            lds8);
+    fwd_tile<PASS, T, V, E>(dirs, w, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, aloc, indeg, cnt, acc,
+                            ext, out, status, lds8);
 }
 
 template <int PASS>
@@ -1040,7 +1051,8 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
          float *__restrict__ out, uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
-    adj_tile<PASS>(dirs, gin, g, 0, blockIdx.x, link, Sg, mu0, mu1, jstate, out, status, lds8);
+    adj_tile<PASS>(dirs, gin, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, Sg, mu0, mu1, jstate, out,
+                   status, lds8);
 }
 
 // ---- kernels: a batch of rasters ----------------------------------------

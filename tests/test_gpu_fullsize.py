@@ -1,0 +1,104 @@
+"""The 32768 x 32768 workload in the launch configuration the benchmark
+times (64 x 64 tiles): D8 on sampled windows, then unit-count accumulation
+and the float32 adjoint checked at every cell through properties that
+determine them (local balance against the donors, the adjoint recurrence
+along receivers; both are computed here with plain tensor ops, independently
+of the library), plus sampled cells against the oracle's per-cell
+definitions."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DR = (-1, -1, -1, 0, 0, 1, 1, 1)
+DC = (-1, 0, 1, -1, 1, -1, 0, 1)
+
+
+@pytest.fixture(scope="module")
+def d8m():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    import paper_1608_04431_amd as m
+    m._lib.load()
+    return m
+
+
+def receivers(dirs: torch.Tensor) -> torch.Tensor:
+    """Flat receiver index per cell, -1 where there is none (NoFlow, NoData,
+    off the raster, or into NoData)."""
+    rows, cols = dirs.shape
+    k = dirs.long()
+    r = torch.arange(rows, device=dirs.device).view(-1, 1).expand(rows, cols)
+    c = torch.arange(cols, device=dirs.device).view(1, -1).expand(rows, cols)
+    dr = torch.tensor(DR + (0, 0), device=dirs.device)[k.clamp(max=9)]
+    dc = torch.tensor(DC + (0, 0), device=dirs.device)[k.clamp(max=9)]
+    nr, nc = r + dr, c + dc
+    ok = (k < 8) & (nr >= 0) & (nr < rows) & (nc >= 0) & (nc < cols)
+    idx = (nr.clamp(0, rows - 1) * cols + nc.clamp(0, cols - 1))
+    ok &= dirs.view(-1)[idx.view(-1)].view(rows, cols) != 9
+    return torch.where(ok, idx, torch.full_like(idx, -1)).view(-1)
+
+
+def test_dem32768_full_size(d8m):
+    wl = synth.WORKLOADS["dem32768"]
+    z = synth.workload_dem("dem32768")
+    rows, cols = z.shape
+    dirs = d8m.d8_directions(torch.from_numpy(z).cuda())
+    # D8 on sampled windows (with a one-cell halo) against the oracle
+    rng = np.random.default_rng(5)
+    d_host = dirs.cpu().numpy()
+    for r0, c0 in zip(rng.integers(1, rows - 257, 6), rng.integers(1, cols - 257, 6)):
+        want = oracle.d8(z[r0 - 1:r0 + 257, c0 - 1:c0 + 257])[1:-1, 1:-1]
+        np.testing.assert_array_equal(d_host[r0:r0 + 256, c0:c0 + 256], want)
+    np.testing.assert_array_equal(d_host[:2, :300], oracle.d8(z[:3, :301])[:2, :300])
+    del z
+
+    tile = (64, 64)
+    A = d8m.flow_accum(dirs, acc_type="u32", tile=tile)
+    g = torch.from_numpy(synth.uniform((rows, cols), wl["seed_g"])).cuda()
+    lam = d8m.flow_accum_adjoint(dirs, g, tile=tile)
+    torch.cuda.synchronize()
+
+    recv = receivers(dirs)
+    data = dirs.view(-1) != 9
+    has = recv >= 0
+    # local balance, exact in int64: A(c) = 1 + sum of A over c's donors
+    A64 = A.view(-1).long() & 0xFFFFFFFF
+    inflow = torch.zeros_like(A64)
+    inflow.index_add_(0, recv[has], A64[has])
+    assert torch.equal(A64[data], 1 + inflow[data])
+    assert (A64[~data] == 0).all()
+    # the outlets hold every data cell once
+    assert int(A64[data & ~has].sum()) == int(data.sum())
+    del inflow
+
+    # adjoint recurrence lambda(c) = g(c) + lambda(receiver), float32 tolerance
+    L = lam.view(-1).double()
+    G = g.view(-1).double()
+    down = torch.zeros_like(L)
+    down[has] = L[recv[has]]
+    res = (L - G - down)[data].abs()
+    scale = (L.abs() + down.abs())[data]
+    assert (res <= 1e-4 * scale + 1e-6).all(), float((res / (scale + 1e-30)).max())
+    assert (L[~data] == 0).all()
+
+    # sampled cells against the oracle's per-cell definitions: random data
+    # cells, two with catchments of at least 1e5 cells, and the largest
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    cand = torch.randint(0, rows * cols, (4096,), device="cuda", generator=gen)
+    rand = cand[data[cand]][:40]
+    big = torch.nonzero(A64 >= 100000).view(-1)
+    big = big[torch.randint(0, big.numel(), (2,), device="cuda", generator=gen)]
+    picks = torch.cat([rand, big, torch.argmax(A64).view(1)]).tolist()
+    A_host = A.cpu().numpy().view(np.uint32)
+    L_host = lam.cpu().numpy()
+    g_host = g.cpu().numpy()
+    for i in picks:
+        r, c = divmod(int(i), cols)
+        assert oracle.upstream_sum(d_host, r, c) == A_host[r, c], (r, c)
+        want = oracle.downstream_sum(d_host, r, c, g_host)
+        assert abs(L_host[r, c] - want) <= 1e-4 * max(want, 1.0), (r, c, L_host[r, c], want)
