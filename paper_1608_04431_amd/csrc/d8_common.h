@@ -121,6 +121,7 @@ struct DemDesc {
     float *acc;         // forward output
     const float *gacc;  // adjoint cotangent
     float *gw;          // adjoint output
+    uint8_t *root8;     // adjoint: root label per cell (batch workspace)
 };
 
 // First error wins.

@@ -22,7 +22,7 @@ constexpr int kDefaultTile = 64;
 constexpr int kNodeBlock = 256;
 
 struct Layout {
-    size_t status, jstate, link, entry, succ, indeg, val32, acc64, ext64, ptr2, total;
+    size_t status, jstate, link, entry, succ, indeg, val32, acc64, ext64, ptr2, root8, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -42,6 +42,7 @@ Layout layout_for(const Geo &g)
     L.val32 = off;  off = align256(off + N * sizeof(uint32_t));
     L.acc64 = off;  off = align256(off + N * sizeof(double));
     L.ext64 = off;  off = align256(off + N * sizeof(double));
+    L.root8 = off;  off = align256(off + (size_t)g.rows * (size_t)g.cols);  // adjoint root labels
     L.total = off;
     return L;
 }
@@ -236,7 +237,7 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
 // chunk of 2^kChunkShift nodes starts.
 struct BatchLayout {
     size_t status, jstate, counters, desc, tile_dem, chunk_dem;
-    size_t link, entry, succ, indeg, cnt, val32, acc64, ext64, total;
+    size_t link, entry, succ, indeg, cnt, val32, acc64, ext64, root8, total;
 };
 
 // Rasters of one tile shape: a contiguous range of the batch's tiles, run by
@@ -244,15 +245,16 @@ struct BatchLayout {
 struct TileGroup {
     int th, tw;
     int64_t t_begin, t_end;
-    size_t lds[4];  // fwd pass 1, fwd pass 2, adj pass 1, adj pass 2
+    size_t lds[3];  // fwd pass 1, fwd pass 2, adj pass 1
 };
 constexpr int kMaxGroups = 16;  // 4 stages x 16 counters in the counter block
 
 struct BatchPlan {
     std::vector<DemDesc> dems;
+    std::vector<int64_t> cell0;  // each raster's first cell in the root-label array
     std::vector<uint32_t> tile_dem, chunk_dem;
     std::vector<TileGroup> groups;
-    int64_t ntiles = 0, nnodes = 0;
+    int64_t ntiles = 0, nnodes = 0, ncells = 0;
     BatchLayout L{};
 };
 
@@ -297,11 +299,14 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
         const int key_th = it.tile_rows, key_tw = it.tile_cols;
         if (P.groups.empty() || P.groups.back().th != key_th || P.groups.back().tw != key_tw) {
             if ((int)P.groups.size() == kMaxGroups) return D8_EINVAL;
-            P.groups.push_back({key_th, key_tw, P.ntiles, P.ntiles, {0, 0, 0, 0}});
+            P.groups.push_back({key_th, key_tw, P.ntiles, P.ntiles, {0, 0, 0}});
         }
         TileGroup &G = P.groups.back();
         for (int64_t t = 0; t < nt; ++t) P.tile_dem.push_back((uint32_t)P.dems.size());
+        D.root8 = nullptr;  // set when the workspace is known
         P.dems.push_back(D);
+        P.cell0.push_back(P.ncells);
+        P.ncells += g.rows * g.cols;
         P.ntiles += nt;
         P.nnodes += g.nnodes;
         G.t_end = P.ntiles;
@@ -309,7 +314,6 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
         G.lds[0] = std::max(G.lds[0], walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4));
         G.lds[1] = std::max(G.lds[1], walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4));
         G.lds[2] = std::max(G.lds[2], walk_lds_bytes(g.th, g.tw, kWalkAdj1, 4));
-        G.lds[3] = std::max(G.lds[3], walk_lds_bytes(g.th, g.tw, kWalkAdj2, 4));
     }
     const int64_t nchunk = (P.nnodes >> kChunkShift) + 1;
     P.chunk_dem.assign((size_t)nchunk, 0);
@@ -336,6 +340,7 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
     L.val32 = off; off = align256(off + N * sizeof(float));
     L.acc64 = off; off = align256(off + N * sizeof(double));
     L.ext64 = off; off = align256(off + N * sizeof(double));
+    L.root8 = off; off = align256(off + (size_t)P.ncells);
     L.total = off;
     return D8_OK;
 }
@@ -363,8 +368,11 @@ __global__ void reset_jump(uint32_t *jstate)
 int upload_plan(const BatchPlan &P, char *ws, hipStream_t st)
 {
     const BatchLayout &L = P.L;
-    if (!P.dems.empty()) {
-        if (hipMemcpyAsync(ws + L.desc, P.dems.data(), P.dems.size() * sizeof(DemDesc),
+    std::vector<DemDesc> dems = P.dems;
+    for (size_t i = 0; i < dems.size(); ++i)
+        dems[i].root8 = reinterpret_cast<uint8_t *>(ws + L.root8) + P.cell0[i];
+    if (!dems.empty()) {
+        if (hipMemcpyAsync(ws + L.desc, dems.data(), dems.size() * sizeof(DemDesc),
                            hipMemcpyHostToDevice, st) != hipSuccess ||
             hipMemcpyAsync(ws + L.tile_dem, P.tile_dem.data(), P.tile_dem.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -440,10 +448,7 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
     }
     if (mode & D8_BATCH_ADJ) {
         reset_jump<<<1, 1, 0, st>>>(jstate);
-        const unsigned long long *none = nullptr;
-        if (tiles(2, adj_walk_batch<1>, "batch_adj_pass1", link, val32, none, none,
-                  (const uint32_t *)jstate, status))
-            return D8_EHIP;
+        if (tiles(2, adj_walk_batch, "batch_adj_pass1", link, val32, status)) return D8_EHIP;
         D8_LAUNCH("batch_graph_build", st,
                   (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
                                                                 succ, nullptr)));
@@ -455,11 +460,9 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
             D8_LAUNCH("batch_adj_jump_round", st,
                       (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(N, jw[r & 1], jw[(r + 1) & 1], jstate, r)));
         D8_LAUNCH("batch_adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
-        const unsigned long long *m0 = jw[0], *m1 = jw[1];
-        float *nof = nullptr;
-        if (tiles(3, adj_walk_batch<2>, "batch_adj_pass2", link, nof, m0, m1, (const uint32_t *)jstate,
-                  status))
-            return D8_EHIP;
+        D8_LAUNCH("batch_adj_pass2", st,
+                  (adj_finish_batch<<<(unsigned)P.ntiles, 64, 0, st>>>(dems, tile_dem, (uint32_t)P.ntiles,
+                                                                      jw[0], jw[1], jstate)));
     }
     return last_error();
 }
@@ -593,17 +596,18 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     unsigned long long *jw[2] = {reinterpret_cast<unsigned long long *>(w8 + L.acc64),
                                  reinterpret_cast<unsigned long long *>(w8 + L.ext64)};
 
+    uint8_t *root8 = reinterpret_cast<uint8_t *>(w8 + L.root8);
     int ntiles = g.nty * g.ntx;
     const int thr = kTileThreads;
-    size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1), lds2 = walk_lds_bytes(g.th, g.tw, kWalkAdj2);
+    size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1);
     begin_call();
-    if (allow_lds(adj_walk<1>, lds1) || allow_lds(adj_walk<2>, lds2)) return D8_EHIP;
+    if (allow_lds(adj_walk, lds1)) return D8_EHIP;
     unsigned nb = blocks_for(g.nnodes, kNodeBlock);
 
     init_state<<<1, 1, 0, st>>>(status, jstate);
     D8_LAUNCH("adj_pass1", st,
-              (adj_walk<1><<<ntiles, thr, lds1, st>>>(dirs, grad_acc, g, link, S, nullptr, nullptr,
-                                                      jstate, nullptr, status)));
+              (adj_walk<<<ntiles, thr, lds1, st>>>(dirs, grad_acc, g, link, S, grad_weights, root8,
+                                                   status)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr)));
     D8_LAUNCH("adj_jump_init", st,
@@ -616,8 +620,7 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                                                              r)));
     D8_LAUNCH("adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
     D8_LAUNCH("adj_pass2", st,
-              (adj_walk<2><<<ntiles, thr, lds2, st>>>(dirs, grad_acc, g, link, nullptr, jw[0],
-                                                      jw[1], jstate, grad_weights, status)));
+              (adj_finish<<<ntiles, thr, 0, st>>>(g, root8, jw[0], jw[1], jstate, grad_weights)));
     return last_error();
 }
 

@@ -277,7 +277,8 @@ struct Setup {
 //   MODE 0 (forward): code | pending donors of a confluence << 4;
 //   MODE 1 (links only): code;
 //   MODE 2 (upstream walks): bit j = the neighbour in direction j is a donor.
-// Entries are found when WANT_ENTRY, roots when MODE == 2.
+// Entries are found when WANT_ENTRY, roots when MODE == 2 (NoData bytes are
+// then 0xFF).
 template <int MODE, bool WANT_ENTRY>
 __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &g, const WTile &Tl,
                                    uint8_t *cb8, uint32_t *status)
@@ -327,7 +328,8 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
                 uint32_t mask = 0;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) mask |= (e[j] >> 7) << j;
-                bytes = mask & ((vm >> 7) * 0xFFu);
+                // NoData cells: 0xFF (never walked; marks them after the walks)
+                bytes = mask | (~(vm >> 7) & 0x01010101u) * 0xFFu;
                 // roots: NoFlow, or a direction whose target is outside the tile / NoData
                 uint32_t va = valid_markers(A[m]), vw = vm, vb = valid_markers(B[m]);
                 uint32_t va0 = valid_markers(a0), va2 = valid_markers(a2);
@@ -644,38 +646,105 @@ __device__ inline void link_sum_walks(const WTile &Tl, const uint8_t *cb8, const
     }
 }
 
-// Upstream walks for the adjoint: lambda(d) = g(d) + lambda(receiver).  avp
-// holds the seeds (g, plus the downstream sum at exits) and receives lambda.
-// A walk starts at a finished cell and moves to its first donor; the other
-// donors of a branching cell are finished on the spot and queued (a ring of
-// qcap entries; when full, they go to the pending bitmap pend, one 64-bit
-// row mask per tile row, which also holds the roots not yet queued).
-// Returns the number of cells this lane finished, roots excluded.
-__device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, uint32_t *q,
-                               uint32_t qcap, uint64_t roots, uint64_t *pend)
+// Upstream walks for the adjoint, local part: lambda_loc(d) = g(d) +
+// lambda_loc(receiver) inside the tile (0 beyond a root), and for every cell
+// the label of its root: the root's ring index if the root's flow leaves the
+// tile into the raster (an exit), else kLabelTerm.  The adjoint of a cell is
+// then lambda_loc plus the downstream sum of its root's exit.
+//
+// A walk starts at a root (or a queued cell) and moves to its first donor;
+// the other donors of a branching cell are finished on the spot and queued.
+// Cell bytes hold donor masks until a walk reaches the cell, then its label.
+// Queue entries: index | donor mask << 13 | label << 22.  Roots that do not
+// fit the queue wait in the lanes' masks; side donors that do not fit go to
+// the pending bitmap pend (their label already in their byte; the donor mask
+// is rebuilt from the direction raster when they are queued).
+constexpr uint32_t kLabelTerm = 254;
+constexpr uint32_t kLabelNoData = 255;
+
+__device__ inline uint32_t donor_mask_global(const uint8_t *__restrict__ dirs, const Geo &g,
+                                             const WTile &Tl, int r, int c)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int nr = r + dir_dr(j), nc = c + dir_dc(j);
+        if (nr < 0 || nr >= Tl.h || nc < 0 || nc >= Tl.w) continue;
+        if (dirs[(Tl.r0 + nr) * g.cols + Tl.c0 + nc] == (uint8_t)(7 - j)) m |= 1u << j;
+    }
+    return m;
+}
+
+// Queue fill for upstream walks from lane masks (lane = tile row).  ROOTS:
+// label from the exit bitmap, mask from the cell byte; otherwise (pending
+// side donors): label from the cell byte, mask rebuilt from dirs.
+template <bool ROOTS>
+__device__ inline uint32_t fill_up(uint32_t *q, uint32_t cap, const WTile &Tl, const Geo &g,
+                                   const uint8_t *__restrict__ dirs, const uint8_t *cb8,
+                                   const uint32_t *exitbits, uint64_t &m)
+{
+    const int lane = lane_id();
+    const uint32_t n = (uint32_t)__popcll(m);
+    uint32_t incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    uint32_t pos = incl - n;
+    const int rowbase = (lane + 1) * Tl.S + 1;
+    while (m != 0 && pos < cap) {
+        const int c = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1ull;
+        const int idx = rowbase + c;
+        uint32_t mask, label;
+        if (ROOTS) {
+            mask = cb8[idx];
+            const int p = ring_index(lane, c, Tl.h, Tl.w);
+            label = (p >= 0 && ((exitbits[p >> 5] >> (p & 31)) & 1u)) ? (uint32_t)p : kLabelTerm;
+        } else {
+            mask = donor_mask_global(dirs, g, Tl, lane, c);
+            label = cb8[idx];
+        }
+        q[pos++] = (uint32_t)idx | (mask << kQByte) | (label << kQRing);
+    }
+    return total < cap ? total : cap;
+}
+
+__device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__restrict__ dirs,
+                               uint8_t *cb8, float *avp, uint32_t *q, uint32_t qcap, uint64_t roots,
+                               uint64_t *pend, const uint32_t *exitbits)
 {
     const int S = Tl.S;
     const int lane = lane_id();
     int visited = 0;
-    uint64_t none = 0;
     uint32_t head = 0;
-    uint32_t tail = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 0xFFu, roots, none));
-    pend[lane] = roots;  // roots that did not fit
-    bool more = __ballot(roots != 0) != 0;
+    uint32_t tail = __builtin_amdgcn_readfirstlane(
+        fill_up<true>(q, qcap, Tl, g, dirs, cb8, exitbits, roots));
+    bool roots_left = __ballot(roots != 0) != 0;
+    bool pending = false;
+    pend[lane] = 0;
     int cur = -1;
-    uint32_t mask = 0;
+    uint32_t mask = 0, label = 0;
     float a = 0.0f;
     for (;;) {
         const uint64_t idle = __ballot(cur < 0);
         if (head >= tail) {
-            if (more) {
-                // queue empty: move pending cells into it
+            if (roots_left) {
+                head = 0;
+                tail = __builtin_amdgcn_readfirstlane(
+                    fill_up<true>(q, qcap, Tl, g, dirs, cb8, exitbits, roots));
+                roots_left = __ballot(roots != 0) != 0;
+            } else if (pending) {
+                // queue empty: move pending side donors into it
                 uint64_t m = pend[lane];
                 pend[lane] = 0;
                 head = 0;
-                tail = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 0xFFu, m, none));
+                tail = __builtin_amdgcn_readfirstlane(
+                    fill_up<false>(q, qcap, Tl, g, dirs, cb8, exitbits, m));
                 if (m != 0) pend[lane] = m;
-                more = __ballot(m != 0) != 0;
+                pending = __ballot(m != 0) != 0;
             } else if (idle == ~0ull) {
                 break;
             }
@@ -686,7 +755,9 @@ __device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, 
                 const uint32_t t = q[j & (qcap - 1)];
                 cur = (int)(t & kQIdx);
                 mask = (t >> kQByte) & 0xFFu;
+                label = t >> kQRing;
                 a = avp[cur];
+                cb8[cur] = (uint8_t)label;
             }
             const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (tail - head < nidle) ? tail : head + nidle;
@@ -704,6 +775,7 @@ __device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, 
                 const uint32_t nm = cb8[d];
                 float sd = avp[d];
                 keep_read(sd);
+                cb8[d] = (uint8_t)label;
                 a += sd;
                 avp[d] = a;
                 ++visited;
@@ -721,6 +793,7 @@ __device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, 
                 rest &= rest - 1u;
                 d = from + dir_off(j, S);
                 dm = cb8[d];
+                cb8[d] = (uint8_t)label;
                 avp[d] += af;
                 ++visited;
             }
@@ -729,7 +802,7 @@ __device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, 
             const uint32_t room = qcap - (tail - head);
             if (has) {
                 if (slot - tail < room) {
-                    q[slot & (qcap - 1)] = (uint32_t)d | (dm << kQByte);
+                    q[slot & (qcap - 1)] = (uint32_t)d | (dm << kQByte) | (label << kQRing);
                 } else {
                     int rr, cc;
                     idx_rc(Tl, d, rr, cc);
@@ -738,7 +811,7 @@ __device__ inline int up_walks(const WTile &Tl, const uint8_t *cb8, float *avp, 
             }
             uint32_t nb = (uint32_t)__popcll(b);
             if (nb > room) {
-                more = true;
+                pending = true;
                 nb = room;
             }
             tail += nb;
@@ -776,8 +849,8 @@ __host__ __device__ inline WLayout walk_layout(int th, int tw, int kind, int vby
     L.qcap = 256u;  // entries <= ring size <= 252 fit in one fill
     L.tail = L.q + (int)L.qcap * 4;
     int tail = 0;
-    if (kind == kWalkFwd1 || kind == kWalkAdj1) tail = (ring_size(th, tw) * 2 + 15) & ~15;
-    if (kind == kWalkAdj2) tail = 64 * 8;
+    if (kind == kWalkFwd1) tail = (ring_size(th, tw) * 2 + 15) & ~15;
+    if (kind == kWalkAdj1) tail = 64 * 8 + 32;  // pending bitmap, exit bitmap (adjoint)
     L.total = L.tail + tail;
     return L;
 }
@@ -876,6 +949,29 @@ __device__ inline void rows_out(const wk::WTile &Tl, const Geo &g, const T *avp,
     }
 }
 
+// Cell bytes of the tile to a raster-shaped byte array (4 bytes per lane
+// when the rows are 4-byte aligned).
+__device__ inline void bytes_out(const wk::WTile &Tl, const Geo &g, const uint8_t *cb8,
+                                 uint8_t *__restrict__ dst)
+{
+    const int lane = wk::lane_id();
+    if (((g.cols & 3) == 0) && ((Tl.w & 3) == 0) && ((Tl.c0 & 3) == 0) &&
+        ((reinterpret_cast<uintptr_t>(dst) & 3) == 0)) {
+        const int c = 4 * (lane & 15), rq = lane >> 4;
+        for (int r = rq; r < Tl.h; r += 4) {
+            if (c >= Tl.w) continue;
+            const uint8_t *s = cb8 + wk::cidx(Tl, r, c);
+            const uint32_t v = (uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16) |
+                               ((uint32_t)s[3] << 24);
+            *reinterpret_cast<uint32_t *>(dst + (Tl.r0 + r) * g.cols + Tl.c0 + c) = v;
+        }
+        return;
+    }
+    const int c = lane;
+    if (c >= Tl.w) return;
+    for (int r = 0; r < Tl.h; ++r) dst[(Tl.r0 + r) * g.cols + Tl.c0 + c] = cb8[wk::cidx(Tl, r, c)];
+}
+
 // One wavefront per tile (tiles up to 64 x 64).  Forward:
 //   PASS 1: A_loc and links -> one record per perimeter cell; resolve state zeroed
 //   PASS 2: seeds w + cross-tile inflow -> A for every cell
@@ -960,63 +1056,114 @@ __device__ inline void fwd_tile(const uint8_t *__restrict__ dirs, const float *_
 // Adjoint, one wavefront per tile.
 //   PASS 1: per perimeter cell, the link and (entries) the sum of g along its in-tile path
 //   PASS 2: lambda for every cell, exits seeded with the resolved downstream sum
-template <int PASS>
+// Adjoint pass 1, one wavefront per tile: upstream walks give lambda_loc
+// (written to out) and every cell's root label (written to root8, one byte
+// per cell); each perimeter cell's record is its link (from its label) and
+// S = lambda_loc, the sum of g along its in-tile path.
 __device__ inline void adj_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ gin,
                                 const Geo &g, int64_t node0, int t, uint16_t *__restrict__ link,
-                                float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
-                                const unsigned long long *__restrict__ mu1,
-                                const uint32_t *__restrict__ jstate, float *__restrict__ out,
-                                uint32_t *status, uint8_t *lds8)
+                                float *__restrict__ Sg, float *__restrict__ out,
+                                uint8_t *__restrict__ root8, uint32_t *status, uint8_t *lds8)
 {
     using namespace wk;
     WTile Tl = wtile_of(g, t);
     Tl.base += node0;
-    const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkAdj1 : kWalkAdj2);
+    const WLayout L = walk_layout(g.th, g.tw, kWalkAdj1);
     uint8_t *cb8 = lds8;
     float *avp = reinterpret_cast<float *>(lds8 + L.av) - Tl.S;
     uint32_t *q = reinterpret_cast<uint32_t *>(lds8 + L.q);
+    uint64_t *pend = reinterpret_cast<uint64_t *>(lds8 + L.tail);
+    uint32_t *exitbits = reinterpret_cast<uint32_t *>(lds8 + L.tail + 64 * 8);
     const int lane = lane_id();
 
-    Setup St = setup_tile<PASS == 1 ? 1 : 2, PASS == 1>(dirs, g, Tl, cb8, status);
+    Setup St = setup_tile<2, false>(dirs, g, Tl, cb8, status);
     rows_in(Tl, g, avp, gin);
-
-    if (PASS == 1) {
-        uint16_t *ll = reinterpret_cast<uint16_t *>(lds8 + L.tail);
-        for (int p = lane; p < Tl.P; p += 64) ll[p] = kLlTerm;
-        __syncthreads();
-        link_sum_walks(Tl, cb8, avp, q, L.qcap, St.entry, ll, Sg + Tl.base);
-        __syncthreads();
-        for (int p = lane; p < Tl.P; p += 64) {
-            int qr, qc;
-            ring_cell(p, Tl.h, Tl.w, qr, qc);
-            const int idx = cidx(Tl, qr, qc);
-            uint32_t k = cb8[idx] & 15u;
-            uint16_t Lk;
-            if (k >= (uint32_t)kNoData) Lk = kLinkNoData;
-            else if (k < (uint32_t)kNoFlow && (cb8[idx + dir_off(k, Tl.S)] & 15u) == kFrameTile) Lk = kLinkExt;
-            else Lk = link_of(Tl, ll[p], status);
-            link[Tl.base + p] = Lk;
-        }
-        return;
-    }
-
-    // pass 2: every perimeter cell gets the downstream sum of the cell its
-    // flow enters in another tile (zero unless it is an exit)
-    // downstream sums: float in the high half of each node's jump word
-    const unsigned long long *mu = jstate[0] == 1 ? mu1 : mu0;
-    uint64_t *pend = reinterpret_cast<uint64_t *>(lds8 + L.tail);
+    // exits: perimeter cells whose flow leaves the tile into the raster
+    if (lane < 8) exitbits[lane] = 0;
     __syncthreads();
     for (int p = lane; p < Tl.P; p += 64) {
         int qr, qc;
         ring_cell(p, Tl.h, Tl.w, qr, qc);
-        avp[cidx(Tl, qr, qc)] += __uint_as_float((uint32_t)(mu[Tl.base + p] >> 32));
+        const uint32_t k = dirs[(Tl.r0 + qr) * g.cols + Tl.c0 + qc];
+        if (k >= (uint32_t)kNoFlow) continue;
+        const int nr = qr + dir_dr(k), nc = qc + dir_dc(k);
+        const int64_t gr = Tl.r0 + nr, gc = Tl.c0 + nc;
+        const bool out_tile = nr < 0 || nr >= Tl.h || nc < 0 || nc >= Tl.w;
+        if (out_tile && gr >= 0 && gr < g.rows && gc >= 0 && gc < g.cols)
+            atomicOr(&exitbits[p >> 5], 1u << (p & 31));
     }
     __syncthreads();
-    int visited = up_walks(Tl, cb8, avp, q, L.qcap, St.root, pend);
+    int visited = up_walks(Tl, g, dirs, cb8, avp, q, L.qcap, St.root, pend, exitbits);
     if (wave_sum(visited + __popcll(St.root)) != wave_sum(__popcll(St.valid)) && lane == 0)
         set_status(status, kStatusCycle);
     __syncthreads();
+    for (int p = lane; p < Tl.P; p += 64) {
+        int qr, qc;
+        ring_cell(p, Tl.h, Tl.w, qr, qc);
+        const int idx = cidx(Tl, qr, qc);
+        const uint32_t lab = cb8[idx];
+        uint16_t Lk;
+        if (lab == kLabelNoData) Lk = kLinkNoData;
+        else if (lab == (uint32_t)p) Lk = kLinkExt;
+        else if (lab == kLabelTerm) Lk = kLinkTerm;
+        else Lk = (uint16_t)lab;
+        link[Tl.base + p] = Lk;
+        Sg[Tl.base + p] = lab == kLabelNoData ? 0.0f : avp[idx];
+    }
     rows_out(Tl, g, avp, St.valid, out);
+    bytes_out(Tl, g, cb8, root8);
+}
+
+// Adjoint pass 2, one wavefront per tile, no walks: lambda = lambda_loc +
+// the downstream sum of the cell's root exit (mu of that perimeter node),
+// in place in out.
+__device__ inline void adj_finish_tile(const Geo &g, int64_t node0, int t,
+                                       const uint8_t *__restrict__ root8,
+                                       const unsigned long long *__restrict__ mu,
+                                       float *__restrict__ out, float *mu_l)
+{
+    using namespace wk;
+    WTile Tl = wtile_of(g, t);
+    Tl.base += node0;
+    const int lane = lane_id();
+    for (int p = lane; p < Tl.P; p += 64) mu_l[p] = __uint_as_float((uint32_t)(mu[Tl.base + p] >> 32));
+    __syncthreads();
+    if (rows_vec(Tl, g, out) && ((reinterpret_cast<uintptr_t>(root8) & 3) == 0)) {
+        const int c = 4 * (lane & 15), rq = lane >> 4;
+        float4 v[16];
+        uint32_t lb[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
+            if (r < Tl.h && c < Tl.w) {
+                const int64_t o = (Tl.r0 + r) * g.cols + Tl.c0 + c;
+                v[i] = *reinterpret_cast<const float4 *>(out + o);
+                lb[i] = *reinterpret_cast<const uint32_t *>(root8 + o);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
+            if (r < Tl.h && c < Tl.w) {
+                const uint32_t l0 = lb[i] & 0xFFu, l1 = (lb[i] >> 8) & 0xFFu;
+                const uint32_t l2 = (lb[i] >> 16) & 0xFFu, l3 = lb[i] >> 24;
+                float4 x = v[i];
+                if (l0 < kLabelTerm) x.x += mu_l[l0];
+                if (l1 < kLabelTerm) x.y += mu_l[l1];
+                if (l2 < kLabelTerm) x.z += mu_l[l2];
+                if (l3 < kLabelTerm) x.w += mu_l[l3];
+                *reinterpret_cast<float4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + c) = x;
+            }
+        }
+        return;
+    }
+    const int c = lane;
+    if (c >= Tl.w) return;
+    for (int r = 0; r < Tl.h; ++r) {
+        const int64_t o = (Tl.r0 + r) * g.cols + Tl.c0 + c;
+        const uint32_t l = root8[o];
+        if (l < kLabelTerm) out[o] += mu_l[l];
+    }
 }
 
 // ---- kernels: one raster (one wavefront per tile) ------------------------
@@ -1043,16 +1190,23 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
                             ext, out, status, lds8);
 }
 
-template <int PASS>
 __global__ void __launch_bounds__(64)
 adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
-         uint16_t *__restrict__ link, float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
-         const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
-         float *__restrict__ out, uint32_t *status)
+         uint16_t *__restrict__ link, float *__restrict__ Sg, float *__restrict__ out,
+         uint8_t *__restrict__ root8, uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
-    adj_tile<PASS>(dirs, gin, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, Sg, mu0, mu1, jstate, out,
-                   status, lds8);
+    adj_tile(dirs, gin, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, Sg, out, root8, status, lds8);
+}
+
+__global__ void __launch_bounds__(64)
+adj_finish(Geo g, const uint8_t *__restrict__ root8, const unsigned long long *__restrict__ mu0,
+           const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
+           float *__restrict__ out)
+{
+    __shared__ float mu_l[256];
+    const unsigned long long *mu = jstate[0] == 1 ? mu1 : mu0;
+    adj_finish_tile(g, 0, xcd_tile(blockIdx.x, gridDim.x), root8, mu, out, mu_l);
 }
 
 // ---- kernels: a batch of rasters ----------------------------------------
@@ -1085,23 +1239,33 @@ fwd_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ ti
     }
 }
 
-template <int PASS>
 __global__ void __launch_bounds__(64)
 adj_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
                uint32_t *counter, uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
-               float *__restrict__ Sg, const unsigned long long *__restrict__ mu0,
-               const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
-               uint32_t *status)
+               float *__restrict__ Sg, uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
     for (;;) {
         const uint32_t t = t_begin + next_tile(counter);
         if (t >= t_end) break;
         const DemDesc &D = dems[tile_dem[t]];
-        adj_tile<PASS>(D.dirs, D.gacc, D.g, D.node0, (int)(t - D.tile0), link, Sg, mu0, mu1, jstate,
-                       D.gw, status, lds8);
+        adj_tile(D.dirs, D.gacc, D.g, D.node0, (int)(t - D.tile0), link, Sg, D.gw, D.root8, status, lds8);
         __syncthreads();
     }
+}
+
+// Batch pass 2: one wavefront per batch tile (an elementwise pass).
+__global__ void __launch_bounds__(64)
+adj_finish_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
+                 uint32_t ntiles, const unsigned long long *__restrict__ mu0,
+                 const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate)
+{
+    __shared__ float mu_l[256];
+    const uint32_t t = (uint32_t)xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const unsigned long long *mu = jstate[0] == 1 ? mu1 : mu0;
+    const DemDesc &D = dems[tile_dem[t]];
+    adj_finish_tile(D.g, D.node0, (int)(t - D.tile0), D.root8, mu, D.gw, mu_l);
 }
 
 __host__ inline size_t walk_lds_bytes(int th, int tw, int kind, int vbytes = 4)
