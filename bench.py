@@ -25,13 +25,16 @@ import synth  # noqa: E402
 METRIC = "D8 accumulation cells/s (fwd+adjoint) at 32768², % HBM peak; batched vs looped"
 HBM_PEAK_GBPS = 8000.0
 
-# Algorithmic bytes per cell of each tile kernel (what the operation must read
-# and write at minimum; records and workspace traffic are not counted).
+# Algorithmic bytes per cell of each tile kernel: its share of what the step
+# must move at minimum (forward: read codes, write A; adjoint: read codes and
+# g, write lambda).  Re-reads (the second pass reads the codes again), the
+# adjoint's retained lambda_loc and root labels, and the per-perimeter-cell
+# records are not counted.
 KERNEL_BYTES_PER_CELL = {
     "fwd_pass1": 1.0,   # directions
-    "fwd_pass2": 5.0,   # directions + uint32 A
+    "fwd_pass2": 4.0,   # uint32 A
     "adj_pass1": 5.0,   # directions + g
-    "adj_pass2": 9.0,   # directions + g + lambda
+    "adj_pass2": 4.0,   # lambda
     "d8_directions": 5.0,
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
