@@ -223,6 +223,10 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
                   (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg,
                                                                  cnt, acc, ext)));
     }
+    unsigned long long *packed = nullptr;
+    if constexpr (kCounts) packed = acc;
+    D8_LAUNCH("resolve_check", st,
+              (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, packed, cnt, status)));
     D8_LAUNCH("fwd_pass2", st,
               (fwd_walk<2, T, V, E><<<ntiles, thr, lds2, st>>>(dirs, w, g, link, aloc, indeg, cnt,
                                                                acc, ext, out, status)));
@@ -443,6 +447,8 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
         D8_LAUNCH("batch_resolve_fwd", st,
                   (resolve_fwd_f64<float><<<nb, kNodeBlock, 0, st>>>(N, link, val32, entry, succ, indeg,
                                                                      cnt, acc, ext)));
+        D8_LAUNCH("batch_resolve_check", st,
+                  (resolve_check<<<nb, kNodeBlock, 0, st>>>(N, link, indeg, nullptr, cnt, status)));
         if (tiles(1, fwd_walk_batch<2>, "batch_fwd_pass2", link, val32, indeg, cnt, acc, ext, status))
             return D8_EHIP;
     }

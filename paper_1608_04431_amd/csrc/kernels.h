@@ -193,6 +193,21 @@ __global__ void resolve_fwd_f64(int64_t nnodes, const uint16_t *__restrict__ lin
     }
 }
 
+// After the resolve: an exit whose children did not all arrive lies on, or
+// below, a cycle of exits.  Arrivals are the low word of `packed` (unit
+// counts) or `cnt` (float weights).
+__global__ void resolve_check(int64_t nnodes, const uint16_t *__restrict__ link,
+                              const uint32_t *__restrict__ indeg,
+                              const unsigned long long *__restrict__ packed,
+                              const uint32_t *__restrict__ cnt, uint32_t *status)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (id < nnodes && link[id] == kLinkExt)
+        bad = (packed ? (uint32_t)packed[id] : cnt[id]) != indeg[id];
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) set_status(status, kStatusCycle);
+}
+
 // -------------------------------------------------------------- adjoint ----
 // mu(e) = lambda(entry(e)) = S(entry(e)) + mu(succ(e)): a downstream path sum
 // over the exit forest, by pointer jumping.  One 64-bit word per node:

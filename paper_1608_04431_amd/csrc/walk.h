@@ -166,6 +166,41 @@ __device__ inline uint32_t from_below(uint32_t x, uint32_t edge)
     return lane_id() == 63 ? edge : v;
 }
 
+// w codes of one raster row into 16 words (bytes beyond w unspecified):
+// 16-byte loads when the row is 16-byte aligned, else words, else bytes.
+__device__ inline void load_codes(const uint8_t *__restrict__ row, int w, uint32_t (&W)[kWords])
+{
+    if ((((uintptr_t)row) & 15) == 0 && (w & 15) == 0) {
+        const uint4 *row16 = reinterpret_cast<const uint4 *>(row);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (16 * i < w) {
+                uint4 v = row16[i];
+                W[4 * i] = v.x;
+                W[4 * i + 1] = v.y;
+                W[4 * i + 2] = v.z;
+                W[4 * i + 3] = v.w;
+            }
+    } else if ((((uintptr_t)row) & 3) == 0 && (w & 3) == 0) {
+        const uint32_t *row4 = reinterpret_cast<const uint32_t *>(row);
+#pragma unroll
+        for (int m = 0; m < kWords; ++m)
+            if (4 * m < w) W[m] = row4[m];
+    } else {
+#pragma unroll
+        for (int m = 0; m < kWords; ++m) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                int c = 4 * m + b;
+                uint32_t k = c < w ? row[c] : 0xFFu;
+                v |= k << (8 * b);
+            }
+            W[m] = v;
+        }
+    }
+}
+
 // Codes of tile row r (lane r), padded with 0xFF outside the tile; codes
 // above 9 are reported and replaced by NoData.
 __device__ inline void load_row(const uint8_t *__restrict__ dirs, const Geo &g, const WTile &T,
@@ -175,36 +210,7 @@ __device__ inline void load_row(const uint8_t *__restrict__ dirs, const Geo &g, 
 #pragma unroll
     for (int m = 0; m < kWords; ++m) W[m] = 0xFFFFFFFFu;
     if (r >= T.h) return;
-    const uint8_t *row = dirs + (T.r0 + r) * g.cols + T.c0;
-    if ((((uintptr_t)row) & 15) == 0 && (T.w & 15) == 0) {
-        const uint4 *row16 = reinterpret_cast<const uint4 *>(row);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (16 * i < T.w) {
-                uint4 v = row16[i];
-                W[4 * i] = v.x;
-                W[4 * i + 1] = v.y;
-                W[4 * i + 2] = v.z;
-                W[4 * i + 3] = v.w;
-            }
-    } else if ((((uintptr_t)row) & 3) == 0 && (T.w & 3) == 0) {
-        const uint32_t *row4 = reinterpret_cast<const uint32_t *>(row);
-#pragma unroll
-        for (int m = 0; m < kWords; ++m)
-            if (4 * m < T.w) W[m] = row4[m];
-    } else {
-#pragma unroll
-        for (int m = 0; m < kWords; ++m) {
-            uint32_t v = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                int c = 4 * m + b;
-                uint32_t k = c < T.w ? row[c] : 0xFFu;
-                v |= k << (8 * b);
-            }
-            W[m] = v;
-        }
-    }
+    load_codes(dirs + (T.r0 + r) * g.cols + T.c0, T.w, W);
     // pad columns beyond the tile
 #pragma unroll
     for (int m = 0; m < kWords; ++m) {
@@ -250,16 +256,12 @@ __device__ inline void load_halo_row(const uint8_t *__restrict__ dirs, const Geo
     left = right = 0xFFu;
     if (gr < 0 || gr >= g.rows) return;
     const uint8_t *row = dirs + gr * g.cols + T.c0;
+    load_codes(row, T.w, H);
 #pragma unroll
     for (int m = 0; m < kWords; ++m) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int c = 4 * m + b;
-            uint32_t k = c < T.w ? row[c] : 0xFFu;
-            v |= k << (8 * b);
-        }
-        H[m] = v;
+        int valid = T.w - 4 * m;  // bytes of this word inside the tile's columns
+        if (valid <= 0) H[m] = 0xFFFFFFFFu;
+        else if (valid < 4) H[m] |= 0xFFFFFFFFu << (8 * valid);
     }
     if (T.c0 > 0) left = row[-1];
     if (T.c0 + T.w < g.cols) right = row[T.w];
@@ -1024,13 +1026,6 @@ __device__ inline void fwd_tile(const uint8_t *__restrict__ dirs, const float *_
 
     if constexpr (PASS == 2) {
         rows_out(Tl, g, avp, St.valid, out);
-        // an exit whose children never all arrived sits on a cycle of exits
-        for (int p = lane; p < Tl.P; p += 64) {
-            int64_t id = Tl.base + p;
-            if (link[id] != kLinkExt) continue;
-            uint32_t arrived = cnt ? cnt[id] : (uint32_t)(unsigned long long)acc[id];
-            if (arrived != indeg[id]) set_status(status, kStatusCycle);
-        }
         return;
     }
 
