@@ -141,11 +141,11 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
 /*
  * Batches of rasters.  Many rasters of uneven sizes go through the same
  * three stages together: a few launches per stage for the whole batch
- * instead of several per raster.  The tile passes run persistent workers
- * that take the next (raster, tile) pair from a work counter, one launch per
- * requested tile shape (its LDS size); within a shape, rasters are ordered by
- * decreasing cell count, so the largest rasters' tiles are handed out first.
- * All rasters' perimeter cells form one global flow graph (the
+ * instead of several per raster.  The tile passes launch one wavefront per
+ * (raster, tile) pair of the batch's tile list, one launch per requested tile
+ * shape (its LDS size); within a shape, rasters are ordered by decreasing
+ * cell count, so the largest rasters' tiles are dispatched first.  All
+ * rasters' perimeter cells form one global flow graph (the
  * paper hands tiles to workers in turn and resolves one graph of all
  * perimeters, Sections "Constructing a Global Solution" and "Implementation
  * Details").  Forward accumulation is float32 (weights, or NULL for w = 1);

@@ -240,7 +240,7 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
 // descriptors, the raster of every batch tile, and the raster where every
 // chunk of 2^kChunkShift nodes starts.
 struct BatchLayout {
-    size_t status, jstate, counters, desc, tile_dem, chunk_dem;
+    size_t status, jstate, desc, tile_dem, chunk_dem;
     size_t link, entry, succ, indeg, cnt, val32, acc64, ext64, root8, total;
 };
 
@@ -251,7 +251,7 @@ struct TileGroup {
     int64_t t_begin, t_end;
     size_t lds[3];  // fwd pass 1, fwd pass 2, adj pass 1
 };
-constexpr int kMaxGroups = 16;  // 4 stages x 16 counters in the counter block
+constexpr int kMaxGroups = 16;  // distinct tile shapes in one batch
 
 struct BatchPlan {
     std::vector<DemDesc> dems;
@@ -332,7 +332,6 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
     size_t off = 0;
     L.status = off; off += 256;
     L.jstate = off; off += 256;
-    L.counters = off; off += 256;
     L.desc = off;      off = align256(off + P.dems.size() * sizeof(DemDesc));
     L.tile_dem = off;  off = align256(off + P.tile_dem.size() * sizeof(uint32_t));
     L.chunk_dem = off; off = align256(off + P.chunk_dem.size() * sizeof(uint32_t));
@@ -349,14 +348,13 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
     return D8_OK;
 }
 
-__global__ void init_batch(uint32_t *status, uint32_t *jstate, uint32_t *counters)
+__global__ void init_batch(uint32_t *status, uint32_t *jstate)
 {
     status[0] = kStatusOk;
     jstate[0] = kNone;
     jstate[1] = 0;
     jstate[2] = 0;
     jstate[3] = 1;
-    for (int i = 0; i < 4 * kMaxGroups; ++i) counters[i] = 0;
 }
 
 __global__ void reset_jump(uint32_t *jstate)
@@ -388,24 +386,11 @@ int upload_plan(const BatchPlan &P, char *ws, hipStream_t st)
     return D8_OK;
 }
 
-// Persistent grid: as many tile workers as fit on the device at once.
-unsigned workers_for(const void *kernel, size_t lds, int64_t ntiles)
-{
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, lds);
-    int64_t n = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
-    if (n > ntiles) n = ntiles;
-    return (unsigned)(n > 0 ? n : 1);
-}
-
 int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
 {
     const BatchLayout &L = P.L;
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.status);
     uint32_t *jstate = reinterpret_cast<uint32_t *>(ws + L.jstate);
-    uint32_t *counters = reinterpret_cast<uint32_t *>(ws + L.counters);
     const DemDesc *dems = reinterpret_cast<const DemDesc *>(ws + L.desc);
     const uint32_t *tile_dem = reinterpret_cast<const uint32_t *>(ws + L.tile_dem);
     const uint32_t *chunk_dem = reinterpret_cast<const uint32_t *>(ws + L.chunk_dem);
@@ -423,18 +408,17 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
     const int64_t N = P.nnodes;
     const unsigned nb = blocks_for(N, kNodeBlock);
 
-    init_batch<<<1, 1, 0, st>>>(status, jstate, counters);
+    init_batch<<<1, 1, 0, st>>>(status, jstate);
     if (ndem == 0) return last_error();
-    // one persistent launch per tile group and stage; counter 16 * stage + group
+    // one launch per tile group and stage, a wavefront per tile of the group
     auto tiles = [&](int stage, auto kernel, const char *name, auto &&...args) -> int {
         for (size_t k = 0; k < P.groups.size(); ++k) {
             const TileGroup &G = P.groups[k];
             const size_t lds = G.lds[stage];
             if (allow_lds(kernel, lds)) return D8_EHIP;
-            const unsigned w = workers_for(reinterpret_cast<const void *>(kernel), lds, G.t_end - G.t_begin);
             D8_LAUNCH(name, st,
-                      (kernel<<<w, 64, lds, st>>>(dems, tile_dem, counters + kMaxGroups * stage + k,
-                                                  (uint32_t)G.t_begin, (uint32_t)G.t_end, args...)));
+                      (kernel<<<(unsigned)(G.t_end - G.t_begin), 64, lds, st>>>(
+                          dems, tile_dem, (uint32_t)G.t_begin, (uint32_t)G.t_end, args...)));
         }
         return D8_OK;
     };

@@ -99,13 +99,14 @@ __device__ inline uint32_t lanes_below(uint64_t m)
 template <typename VT> struct Acc { using type = VT; };
 template <> struct Acc<uint16_t> { using type = uint32_t; };
 
-__device__ inline void lds_add(float *p, float v) { atomicAdd(p, v); }
-__device__ inline void lds_add(uint32_t *p, uint32_t v) { atomicAdd(p, v); }
-// 16-bit slot: add to its 32-bit word (sums stay below 2^16, no carry out)
-__device__ inline void lds_add(uint16_t *p, uint32_t v)
+__device__ inline void lds_add(uint8_t *, float *p, float v) { atomicAdd(p, v); }
+__device__ inline void lds_add(uint8_t *, uint32_t *p, uint32_t v) { atomicAdd(p, v); }
+// 16-bit slot: add to its 32-bit word (sums stay below 2^16, no carry out).
+// The word is addressed from the LDS base so the add stays an LDS atomic.
+__device__ inline void lds_add(uint8_t *lds8, uint16_t *p, uint32_t v)
 {
-    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
-    atomicAdd(reinterpret_cast<uint32_t *>(a & ~(uintptr_t)3), v << ((a & 2u) * 8u));
+    const int off = (int)(reinterpret_cast<uint8_t *>(p) - lds8);
+    atomicAdd(reinterpret_cast<uint32_t *>(lds8 + (off & ~3)), v << ((off & 2) * 8));
 }
 
 // Makes the compiler produce v here: a value read next to another LDS read
@@ -510,18 +511,26 @@ __device__ inline uint16_t link_of(const WTile &Tl, uint16_t v, uint32_t *status
 // Forward walks from every source (and, when LINKS, link walks from every
 // entry, in the same loop).  avp[idx] holds each cell's seed and receives
 // its accumulation.  Returns the number of cells this lane finished.
+//
+// The claim and the plain step take no branches: an idle lane steps from
+// cell (0, 0) with code 15 (its step ends at once), and a store that does not
+// apply goes to the lane's own dummy word.  Only the rare confluence step
+// branches.
 template <typename VT, bool LINKS>
-__device__ inline int fwd_walks(const WTile &Tl, uint8_t *cb8, uint32_t *cbw, VT *avp, uint32_t *q,
-                                uint32_t qcap, uint64_t src, uint64_t ent, uint16_t *ll)
+__device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, uint32_t *cbw, VT *avp,
+                                uint32_t *dummy, uint32_t *q, uint32_t qcap, uint64_t src,
+                                uint64_t ent, uint16_t *ll, int ll_dummy)
 {
     using T = typename Acc<VT>::type;
-    const int S = Tl.S;
+    const int S = Tl.S, safe = S + 1;
+    const int lane = lane_id();
+    VT *mine = reinterpret_cast<VT *>(dummy + lane);
     int visited = 0;
     uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent));
     uint32_t head = 0;
     bool more = __ballot(src != 0 || ent != 0) != 0;
     int cur = -1, steps = 0;
-    uint32_t code = 0, info = 0;
+    uint32_t code = 15u, info = 0;
     T a = (T)0;
     const int max_steps = Tl.h * Tl.w;
     for (;;) {
@@ -538,114 +547,57 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *cb8, uint32_t *cbw, VT
         }
         if (idle != 0 && head < ntask) {
             const uint32_t j = head + lanes_below(idle);
-            if (cur < 0 && j < ntask) {
-                const uint32_t t = q[j];
-                cur = (int)(t & kQIdx);
-                code = (t >> kQByte) & 15u;
-                info = t;
-                steps = 0;
-                a = (T)avp[cur];
-                if (!(LINKS && (t & kQLink))) ++visited;
-            }
+            const bool take = cur < 0 && j < ntask;
+            const uint32_t t = q[take ? j : 0];
+            const int nc = (int)(t & kQIdx);
+            const T a0 = (T)avp[take ? nc : safe];
+            cur = take ? nc : cur;
+            code = take ? ((t >> kQByte) & 15u) : code;
+            info = take ? t : info;
+            steps = take ? 0 : steps;
+            a = take ? a0 : a;
+            visited += (take && !(LINKS && (t & kQLink))) ? 1 : 0;
             const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (ntask - head < nidle) ? ntask : head + nidle;
         }
-        if (cur >= 0) {
-            const bool link = LINKS && (info & kQLink);
-            const int ni = cur + dir_off(code, S);
-            const uint32_t nb = cb8[ni];
-            T sv = (T)avp[ni];
-            keep_read(sv);
-            const uint32_t nk = nb & 15u;
-            bool end = code >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData;
-            if (LINKS) {
-                ++steps;
-                // longer than the tile has cells: the path runs into a cycle
-                end = end || (link && steps > max_steps);
-            }
-            bool go = !end;
-            const bool fw = !end && !link;
-            if (fw && nb < 16u) {
-                a += sv;
-                avp[ni] = (VT)a;
-                ++visited;
-            }
-            if (fw && nb >= 16u) {
-                // confluence: add this donor's total, count the arrival; the
-                // last donor to arrive continues with the cell's total
-                const int sh = 8 * (ni & 3) + 4;
-                lds_add(&avp[ni], a);
-                const uint32_t old = atomicSub(&cbw[ni >> 2], 1u << sh);
-                if (((old >> sh) & 15u) == 1u) {
-                    a = (T)avp[ni];
-                    ++visited;
-                } else {
-                    go = false;
-                }
-            }
-            if (LINKS && link && end) {
-                const uint16_t v = steps > max_steps ? kLlCycle
-                                   : (code < (uint32_t)kNoFlow && nk == kFrameTile) ? (uint16_t)cur
-                                                                                    : kLlTerm;
-                ll[info >> kQRing] = v;
-            }
-            cur = go ? ni : -1;
-            code = nk;
+        const bool act = cur >= 0;
+        const uint32_t ck = act ? code : 15u;
+        const int ni = (act ? cur : safe) + dir_off(ck, S);
+        const uint32_t nb = cb8[ni];
+        T sv = (T)avp[ni];
+        keep_read(sv);
+        const uint32_t nk = nb & 15u;
+        const bool link = LINKS && (info & kQLink);
+        if (LINKS) ++steps;
+        // a link walk longer than the tile has cells runs into a cycle
+        const bool end = ck >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData ||
+                         (LINKS && link && steps > max_steps);
+        const bool fw = !end && !link;
+        const bool plain = fw && nb < 16u;
+        const T ap = a + sv;
+        *(plain ? &avp[ni] : mine) = (VT)ap;
+        bool last = false;
+        if (fw && nb >= 16u) {
+            // confluence: add this donor's total, count the arrival; the
+            // last donor to arrive continues with the cell's total
+            const int sh = 8 * (ni & 3) + 4;
+            lds_add(lds8, &avp[ni], a);
+            const uint32_t old = atomicSub(&cbw[ni >> 2], 1u << sh);
+            last = ((old >> sh) & 15u) == 1u;
+            if (last) a = (T)avp[ni];
         }
+        a = plain ? ap : a;
+        visited += (plain || last) ? 1 : 0;
+        if (LINKS) {
+            const uint16_t v = steps > max_steps ? kLlCycle
+                               : (ck < (uint32_t)kNoFlow && nk == kFrameTile) ? (uint16_t)cur
+                                                                              : kLlTerm;
+            ll[(act && link && end) ? (int)(info >> kQRing) : ll_dummy] = v;
+        }
+        cur = (act && !end && (plain || last || link)) ? ni : -1;
+        code = nk;
     }
     return visited;
-}
-
-// Link walks from every entry (at most the ring size, so one queue fill):
-// the link and the sum of avp along the in-tile path (the adjoint's pass 1).
-__device__ inline void link_sum_walks(const WTile &Tl, const uint8_t *cb8, const float *avp,
-                                      uint32_t *q, uint32_t qcap, uint64_t ent, uint16_t *ll,
-                                      float *Sg)
-{
-    const int S = Tl.S;
-    uint64_t none = 0;
-    const uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, none, ent));
-    uint32_t head = 0;
-    int cur = -1, steps = 0;
-    uint32_t code = 0, info = 0;
-    float s = 0.0f;
-    const int max_steps = Tl.h * Tl.w;
-    for (;;) {
-        const uint64_t idle = __ballot(cur < 0);
-        if (head >= ntask && idle == ~0ull) break;
-        if (idle != 0 && head < ntask) {
-            const uint32_t j = head + lanes_below(idle);
-            if (cur < 0 && j < ntask) {
-                const uint32_t t = q[j];
-                cur = (int)(t & kQIdx);
-                code = (t >> kQByte) & 15u;
-                info = t;
-                steps = 0;
-                s = avp[cur];
-            }
-            const uint32_t nidle = (uint32_t)__popcll(idle);
-            head = (ntask - head < nidle) ? ntask : head + nidle;
-        }
-        if (cur >= 0) {
-            const int ni = cur + dir_off(code, S);
-            const uint32_t nb = cb8[ni];
-            float sv = avp[ni];
-            keep_read(sv);
-            const uint32_t nk = nb & 15u;
-            ++steps;
-            const bool end = code >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData || steps > max_steps;
-            if (end) {
-                const int p = (int)(info >> kQRing);
-                ll[p] = steps > max_steps ? kLlCycle
-                        : (code < (uint32_t)kNoFlow && nk == kFrameTile) ? (uint16_t)cur
-                                                                         : kLlTerm;
-                Sg[p] = s;
-            }
-            s += sv;
-            cur = end ? -1 : ni;
-            code = nk;
-        }
-    }
 }
 
 // Upstream walks for the adjoint, local part: lambda_loc(d) = g(d) +
@@ -830,7 +782,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
 // value reads of frame rows land in the cell bytes (before) or the queue
 // (after), both at least 4 (S + 1) bytes long.
 struct WLayout {
-    int av, q, tail, total;
+    int av, q, dummy, tail, total;
     uint32_t qcap;
 };
 
@@ -849,9 +801,10 @@ __host__ __device__ inline WLayout walk_layout(int th, int tw, int kind, int vby
     L.av = (cb + 15) & ~15;
     L.q = L.av + ((th * S * vbytes + 15) & ~15);
     L.qcap = 256u;  // entries <= ring size <= 252 fit in one fill
-    L.tail = L.q + (int)L.qcap * 4;
+    L.dummy = L.q + (int)L.qcap * 4;  // one word per lane for stores that do not apply
+    L.tail = L.dummy + (kind == kWalkAdj1 ? 0 : 64 * 4);
     int tail = 0;
-    if (kind == kWalkFwd1) tail = (ring_size(th, tw) * 2 + 15) & ~15;
+    if (kind == kWalkFwd1) tail = (ring_size(th, tw) * 2 + 2 + 15) & ~15;  // links + a spare slot
     if (kind == kWalkAdj1) tail = 64 * 8 + 32;  // pending bitmap, exit bitmap (adjoint)
     L.total = L.tail + tail;
     return L;
@@ -869,29 +822,33 @@ __device__ inline bool rows_vec(const wk::WTile &Tl, const Geo &g, const void *p
            ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
 }
 
-template <typename T>
+template <typename T, int HALVES = 1>
 __device__ inline void rows_in(const wk::WTile &Tl, const Geo &g, T *avp, const T *__restrict__ src)
 {
     const int lane = wk::lane_id();
     if (rows_vec(Tl, g, src)) {
         const int c = 4 * (lane & 15), rq = lane >> 4;
-        uint4 v[16];
+        constexpr int K = 16 / HALVES;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = rq + 4 * i;
+        for (int half = 0; half < HALVES; ++half) {
+        uint4 v[K];
+#pragma unroll
+        for (int i0 = 0; i0 < K; ++i0) {
+            const int r = rq + 4 * (half * K + i0);
             if (r < Tl.h && c < Tl.w)
-                v[i] = *reinterpret_cast<const uint4 *>(src + (Tl.r0 + r) * g.cols + Tl.c0 + c);
+                v[i0] = *reinterpret_cast<const uint4 *>(src + (Tl.r0 + r) * g.cols + Tl.c0 + c);
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = rq + 4 * i;
+        for (int i0 = 0; i0 < K; ++i0) {
+            const int r = rq + 4 * (half * K + i0);
             if (r < Tl.h && c < Tl.w) {
                 T *d = avp + wk::cidx(Tl, r, c);
-                d[0] = __builtin_bit_cast(T, v[i].x);
-                d[1] = __builtin_bit_cast(T, v[i].y);
-                d[2] = __builtin_bit_cast(T, v[i].z);
-                d[3] = __builtin_bit_cast(T, v[i].w);
+                d[0] = __builtin_bit_cast(T, v[i0].x);
+                d[1] = __builtin_bit_cast(T, v[i0].y);
+                d[2] = __builtin_bit_cast(T, v[i0].z);
+                d[3] = __builtin_bit_cast(T, v[i0].w);
             }
+        }
         }
         return;
     }
@@ -910,33 +867,38 @@ __device__ inline void rows_fill(const wk::WTile &Tl, T *avp, T v)
 }
 
 // out = avp for data cells, 0 for NoData (valid: this lane's row mask)
-template <typename T>
+template <typename T, int HALVES = 1>
 __device__ inline void rows_out(const wk::WTile &Tl, const Geo &g, const T *avp, uint64_t valid, T *out)
 {
     const int lane = wk::lane_id();
     const uint32_t vlo = (uint32_t)valid, vhi = (uint32_t)(valid >> 32);
     if (rows_vec(Tl, g, out)) {
         const int c = 4 * (lane & 15), rq = lane >> 4;
-        uint4 v[16];
+        constexpr int K = 16 / HALVES;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int half = 0; half < HALVES; ++half) {
+        uint4 v[K];
+#pragma unroll
+        for (int i0 = 0; i0 < K; ++i0) {
+            const int i = half * K + i0;
             const int r = rq + 4 * i;
             const uint32_t lo = (uint32_t)__shfl((int)vlo, r & 63, 64);
             const uint32_t hi = (uint32_t)__shfl((int)vhi, r & 63, 64);
             const uint32_t bits = (c < 32 ? lo >> c : hi >> (c - 32)) & 15u;
             if (r < Tl.h && c < Tl.w) {
                 const T *s = avp + wk::cidx(Tl, r, c);
-                v[i].x = (bits & 1u) ? __builtin_bit_cast(uint32_t, s[0]) : 0u;
-                v[i].y = (bits & 2u) ? __builtin_bit_cast(uint32_t, s[1]) : 0u;
-                v[i].z = (bits & 4u) ? __builtin_bit_cast(uint32_t, s[2]) : 0u;
-                v[i].w = (bits & 8u) ? __builtin_bit_cast(uint32_t, s[3]) : 0u;
+                v[i0].x = (bits & 1u) ? __builtin_bit_cast(uint32_t, s[0]) : 0u;
+                v[i0].y = (bits & 2u) ? __builtin_bit_cast(uint32_t, s[1]) : 0u;
+                v[i0].z = (bits & 4u) ? __builtin_bit_cast(uint32_t, s[2]) : 0u;
+                v[i0].w = (bits & 8u) ? __builtin_bit_cast(uint32_t, s[3]) : 0u;
             }
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = rq + 4 * i;
+        for (int i0 = 0; i0 < K; ++i0) {
+            const int r = rq + 4 * (half * K + i0);
             if (r < Tl.h && c < Tl.w)
-                *reinterpret_cast<uint4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + c) = v[i];
+                *reinterpret_cast<uint4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + c) = v[i0];
+        }
         }
         return;
     }
@@ -981,7 +943,7 @@ __device__ inline void bytes_out(const wk::WTile &Tl, const Geo &g, const uint8_
 // counts keep (inflow sum << 32 | arrivals) in acc; float weights keep the
 // double sum in acc and arrivals in cnt.
 template <int PASS, typename T, typename V, typename E>
-__device__ inline void fwd_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ w,
+__device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ w,
                                 const Geo &g, int64_t node0, int t, uint16_t *__restrict__ link,
                                 T *__restrict__ aloc, uint32_t *__restrict__ indeg,
                                 uint32_t *__restrict__ cnt, V *__restrict__ acc, E *__restrict__ ext,
@@ -1020,7 +982,9 @@ __device__ inline void fwd_tile(const uint8_t *__restrict__ dirs, const float *_
     }
     __syncthreads();
 
-    int visited = fwd_walks<VT, PASS == 1>(Tl, cb8, cbw, avp, q, L.qcap, St.src, St.entry, ll);
+    uint32_t *dummy = reinterpret_cast<uint32_t *>(lds8 + L.dummy);
+    int visited = fwd_walks<VT, PASS == 1>(Tl, lds8, cb8, cbw, avp, dummy, q, L.qcap, St.src, St.entry,
+                                           ll, Tl.P);
     if (wave_sum(visited) != wave_sum(__popcll(St.valid)) && lane == 0) set_status(status, kStatusCycle);
     __syncthreads();
 
@@ -1055,7 +1019,7 @@ __device__ inline void fwd_tile(const uint8_t *__restrict__ dirs, const float *_
 // (written to out) and every cell's root label (written to root8, one byte
 // per cell); each perimeter cell's record is its link (from its label) and
 // S = lambda_loc, the sum of g along its in-tile path.
-__device__ inline void adj_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ gin,
+__device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ gin,
                                 const Geo &g, int64_t node0, int t, uint16_t *__restrict__ link,
                                 float *__restrict__ Sg, float *__restrict__ out,
                                 uint8_t *__restrict__ root8, uint32_t *status, uint8_t *lds8)
@@ -1112,7 +1076,7 @@ __device__ inline void adj_tile(const uint8_t *__restrict__ dirs, const float *_
 // Adjoint pass 2, one wavefront per tile, no walks: lambda = lambda_loc +
 // the downstream sum of the cell's root exit (mu of that perimeter node),
 // in place in out.
-__device__ inline void adj_finish_tile(const Geo &g, int64_t node0, int t,
+__device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int t,
                                        const uint8_t *__restrict__ root8,
                                        const unsigned long long *__restrict__ mu,
                                        float *__restrict__ out, float *mu_l)
@@ -1205,48 +1169,36 @@ adj_finish(Geo g, const uint8_t *__restrict__ root8, const unsigned long long *_
 }
 
 // ---- kernels: a batch of rasters ----------------------------------------
-// Persistent workers: each wavefront takes the next tile of its range of the
-// batch's tile order (rasters grouped by tile shape, by decreasing cost within
-// a group, tiles row-major) from a counter until none is left.  tile_dem[t]
-// is the raster of batch tile t.
-__device__ inline uint32_t next_tile(uint32_t *counter)
-{
-    uint32_t t = 0;
-    if (__lane_id() == 0) t = atomicAdd(counter, 1u);
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)t, 0, 64));
-}
-
+// One wavefront per tile of a range [t_begin, t_end) of the batch's tile
+// list (rasters grouped by tile shape, by decreasing cost within a group,
+// tiles row-major); the block-to-tile map is the XCD-aware one above, so
+// each XCD works through a contiguous part of the list.  tile_dem[t] is the
+// raster of batch tile t.
 template <int PASS>
 __global__ void __launch_bounds__(64)
 fwd_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
-               uint32_t *counter, uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
+               uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
                float *__restrict__ aloc, uint32_t *__restrict__ indeg, uint32_t *__restrict__ cnt,
                double *__restrict__ acc, double *__restrict__ ext, uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
-    for (;;) {
-        const uint32_t t = t_begin + next_tile(counter);
-        if (t >= t_end) break;
-        const DemDesc &D = dems[tile_dem[t]];
-        fwd_tile<PASS, float, double, double>(D.dirs, D.w, D.g, D.node0, (int)(t - D.tile0), link,
-                                              aloc, indeg, cnt, acc, ext, D.acc, status, lds8);
-        __syncthreads();
-    }
+    const uint32_t t = t_begin + (uint32_t)xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= t_end) return;
+    const DemDesc D = dems[tile_dem[t]];
+    fwd_tile<PASS, float, double, double>(D.dirs, D.w, D.g, D.node0, (int)(t - D.tile0), link, aloc,
+                                          indeg, cnt, acc, ext, D.acc, status, lds8);
 }
 
 __global__ void __launch_bounds__(64)
 adj_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
-               uint32_t *counter, uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
+               uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
                float *__restrict__ Sg, uint32_t *status)
 {
     extern __shared__ __align__(16) uint8_t lds8[];
-    for (;;) {
-        const uint32_t t = t_begin + next_tile(counter);
-        if (t >= t_end) break;
-        const DemDesc &D = dems[tile_dem[t]];
-        adj_tile(D.dirs, D.gacc, D.g, D.node0, (int)(t - D.tile0), link, Sg, D.gw, D.root8, status, lds8);
-        __syncthreads();
-    }
+    const uint32_t t = t_begin + (uint32_t)xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= t_end) return;
+    const DemDesc D = dems[tile_dem[t]];
+    adj_tile(D.dirs, D.gacc, D.g, D.node0, (int)(t - D.tile0), link, Sg, D.gw, D.root8, status, lds8);
 }
 
 // Batch pass 2: one wavefront per batch tile (an elementwise pass).
@@ -1259,7 +1211,7 @@ adj_finish_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ 
     const uint32_t t = (uint32_t)xcd_tile(blockIdx.x, gridDim.x);
     if (t >= ntiles) return;
     const unsigned long long *mu = jstate[0] == 1 ? mu1 : mu0;
-    const DemDesc &D = dems[tile_dem[t]];
+    const DemDesc D = dems[tile_dem[t]];
     adj_finish_tile(D.g, D.node0, (int)(t - D.tile0), D.root8, mu, D.gw, mu_l);
 }
 
