@@ -38,6 +38,7 @@ KERNEL_BYTES_PER_CELL = {
     "d8_directions": 5.0,
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
+SWEEP_TILES = ((64, 64), (64, 56), (56, 64), (64, 48), (48, 64), (32, 64))
 
 
 KERNEL_NAMES = {  # timing label -> kernel symbol prefix in profiler output
@@ -205,13 +206,21 @@ def batch_leg(bd: BatchData, reps: int) -> dict:
         for cls, members in sorted(classes.items(), key=lambda kv: int(kv[0])):
             times = tuner.tune_batch([(r["dirs"], r["w"], r["g"]) for r in members], save=False)
             tuned[cls] = {f"{a}x{b}": round(v, 4) for (a, b), v in times.items()}
+        tuned_single = {}
+        for cls, members in sorted(classes.items(), key=lambda kv: int(kv[0])):
+            big = max(members, key=lambda r: r["dirs"].numel())
+            times = tuner.tune(big["dirs"], big["w"], big["g"], reps=2, save=False)
+            tuned_single[cls] = {f"{a}x{b}": round(v, 4) for (a, b), v in times.items()}
         for r in rs:
             r["tile"] = tuner.tile_for(*r["dirs"].shape, batch=True)
+            r["tile1"] = tuner.tile_for(*r["dirs"].shape)
     choice = {cls: "x".join(map(str, tuner.tile_for(int(cls), int(cls), batch=True))) for cls in tuned}
-    log(f"tiles per size class: {choice}")
+    choice1 = {cls: "x".join(map(str, tuner.tile_for(int(cls), int(cls)))) for cls in tuned}
+    log(f"tiles per size class: batch {choice}, single {choice1}")
 
     # (i) looped: two C-ABI calls per DEM on one stream, one sync at the end
-    ws_bytes = max(d8.workspace_bytes(*r["dirs"].shape, r["tile"]) for r in rs)
+    ws_bytes = max(max(d8.workspace_bytes(*r["dirs"].shape, r["tile"]),
+                       d8.workspace_bytes(*r["dirs"].shape, r["tile1"])) for r in rs)
     ws = d8.Workspace(1, 1, (1, 1), dev)
     ws.buf = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     ws.nbytes = ws_bytes
@@ -219,10 +228,10 @@ def batch_leg(bd: BatchData, reps: int) -> dict:
         r["acc"] = torch.empty_like(r["w"])
         r["gw"] = torch.empty_like(r["w"])
 
-    def looped():
+    def looped(key="tile"):
         for r in rs:
-            d8.flow_accum(r["dirs"], r["w"], "f32", r["tile"], ws, r["acc"])
-            d8.flow_accum_adjoint(r["dirs"], r["g"], r["tile"], ws, r["gw"])
+            d8.flow_accum(r["dirs"], r["w"], "f32", r[key], ws, r["acc"])
+            d8.flow_accum_adjoint(r["dirs"], r["g"], r[key], ws, r["gw"])
 
     def timed(fn):
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -243,9 +252,12 @@ def batch_leg(bd: BatchData, reps: int) -> dict:
     torch.cuda.synchronize()
     d8.timing_enable(False)
     launches_looped = sum(c for _, c in d8.timing_report().values())
+    looped("tile1")
+    t_loop1, _ = timed(lambda: looped("tile1"))
     t_loop, loop_all = timed(looped)
     d8.check_status(ws)
-    log(f"looped: {t_loop:.2f} ms (median of {reps})")
+    log(f"looped: {t_loop:.2f} ms with the batch tiles, {t_loop1:.2f} ms with per-raster tiles "
+        f"(medians of {reps})")
 
     # (ii) batched: one graph launch for all DEMs, forward + adjoint
     rasters = [d8.Raster(r["dirs"], r["w"], r["g"], tile=r["tile"]) for r in rs]
@@ -275,13 +287,15 @@ def batch_leg(bd: BatchData, reps: int) -> dict:
                     "cotangents U[0,1); forward (f32) + adjoint",
         "dems": n, "cells": int(bd.cells),
         "looped_ms": t_loop, "batched_ms": t_graph, "speedup": t_loop / t_graph,
+        "looped_per_raster_tiles_ms": t_loop1, "speedup_vs_per_raster_tiles": t_loop1 / t_graph,
         "looped_cells_per_s": bd.cells / (t_loop * 1e-3),
         "batched_cells_per_s": bd.cells / (t_graph * 1e-3),
         "batched_hbm_GBps_algorithmic": bytes_alg / (t_graph * 1e-3) / 1e9,
         "batched_frac_hbm_peak": bytes_alg / (t_graph * 1e-3) / 1e9 / HBM_PEAK_GBPS,
         "launches_looped": int(launches_looped), "launches_batched": 1,
         "reps_ms": {"looped": [round(x, 3) for x in loop_all], "batched": [round(x, 3) for x in graph_all]},
-        "tiles": choice, "tuning_ms": tuned, "outputs_identical": bool(same),
+        "tiles": choice, "tiles_per_raster": choice1, "tuning_ms": tuned,
+        "tuning_single_ms": tuned_single, "outputs_identical": bool(same),
         "kernels_ms": batch_kernels,
     }
 
@@ -292,7 +306,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dem32768")
-    ap.add_argument("--tile", type=int, nargs=2, default=(64, 64))
+    ap.add_argument("--tile", type=int, nargs=2, default=None,
+                    help="tile shape of the timed run (default: the autotuner's table)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the tile-shape sweep")
     ap.add_argument("--cache-dir", default=os.environ.get("D8_CACHE_DIR"))
     ap.add_argument("--cpu-rows", type=int, default=6144,
                     help="rows of the raster in the CPU-oracle sample (0 = skip)")
@@ -335,7 +351,8 @@ def run(args, bd):
     rows, cols = z.shape
     n_cells = rows * cols
     dev = torch.device("cuda:0")
-    tile = tuple(args.tile)
+    from paper_1608_04431_amd.autotune import Tuner
+    tile = tuple(args.tile) if args.tile else Tuner().tile_for(rows, cols)
 
     # inputs resident in HBM before timing
     dem = torch.from_numpy(z).to(dev)
@@ -344,6 +361,27 @@ def run(args, bd):
     g = torch.from_numpy(synth.uniform((rows, cols), wl.get("seed_g", 31))).to(dev)
     A = torch.empty((rows, cols), dtype=torch.int32, device=dev)
     lam = torch.empty((rows, cols), dtype=torch.float32, device=dev)
+
+    # tile-shape sweep: a few steps per candidate (the timed run below uses
+    # the autotuner's choice, or --tile)
+    sweep = {}
+    if not args.no_sweep:
+        for cand in SWEEP_TILES:
+            wsc = d8.Workspace(rows, cols, cand, dev)
+            d8.flow_accum(dirs, acc_type="u32", tile=cand, ws=wsc, out=A)
+            d8.flow_accum_adjoint(dirs, g, tile=cand, ws=wsc, out=lam)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                d8.flow_accum(dirs, acc_type="u32", tile=cand, ws=wsc, out=A)
+                d8.flow_accum_adjoint(dirs, g, tile=cand, ws=wsc, out=lam)
+            e1.record()
+            torch.cuda.synchronize()
+            d8.check_status(wsc)
+            sweep[f"{cand[0]}x{cand[1]}"] = round(e0.elapsed_time(e1) / 3, 3)
+            del wsc
+        log(f"tile sweep (ms/step): {sweep}")
     ws = d8.Workspace(rows, cols, tile, dev)
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -389,7 +427,7 @@ def run(args, bd):
     dom_ms = per_launch[dom][0]
     dom_bytes = KERNEL_BYTES_PER_CELL.get(dom)
     roofline = {"bound": "hbm", "kernel": dom, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "traffic": measured_traffic(dom, args.workload)}
+                "traffic": measured_traffic(dom, f"{args.workload}_{tile[0]}x{tile[1]}")}
     if dom_bytes is not None:
         achieved = dom_bytes * n_cells / (dom_ms * 1e-3) / 1e9
         roofline.update(achieved=achieved, frac=achieved / HBM_PEAK_GBPS,
@@ -420,10 +458,13 @@ def run(args, bd):
         "config": {"workload": f"{args.workload}: {rows}x{cols} uint8 D8 directions of a filled "
                                f"6-octave value-noise DEM (wavelength {wl['lambda0']}), unit "
                                f"weights uint32 forward + dense U[0,1) float32 adjoint",
-                   "cells": n_cells, "tile": list(tile), "parallelism": "single GPU"},
+                   "cells": n_cells, "rows": rows, "cols": cols, "tile": list(tile),
+                   "parallelism": "single GPU"},
         "step_hbm_GBps_algorithmic": step_gbps,
         "step_frac_hbm_peak": step_gbps / HBM_PEAK_GBPS,
         "kernels_ms_per_step": {k: round(ms / args.steps, 4) for k, (ms, n) in kernels.items()},
+        "tile_sweep_ms_per_step": sweep,
+        "tuner_device_key": __import__("paper_1608_04431_amd.autotune", fromlist=["x"]).device_key(),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

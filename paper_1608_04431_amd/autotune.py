@@ -68,11 +68,16 @@ class Tuner:
         return self.key + ("|batch" if batch else "")
 
     def lookup(self, rows: int, cols: int, batch: bool = False):
+        """The cached tile for the size class: this device's entry, else one
+        for its architecture (the packaged table is keyed by architecture)."""
         cls = size_class(rows, cols)
+        arch = self.key.split("|")[-1]
+        keys = (self._key(batch), arch + ("|batch" if batch else ""))
         for table in (self.user, self.packaged):
-            entry = table.get(self._key(batch), {}).get(cls)
-            if entry:
-                return tuple(int(v) for v in entry["tile"])
+            for key in keys:
+                entry = table.get(key, {}).get(cls)
+                if entry:
+                    return tuple(int(v) for v in entry["tile"])
         return None
 
     def tile_for(self, rows: int, cols: int, batch: bool = False) -> tuple[int, int]:
@@ -175,3 +180,39 @@ class Tuner:
         with open(tmp, "w") as f:
             json.dump(self.user, f, indent=1, sort_keys=True)
         os.replace(tmp, self.path)
+
+
+def table_from_bench(bench: dict, arch: str) -> dict:
+    """A packaged table from one bench.py JSON line: the batch leg's tunings
+    (per size class, one raster and batch context) and the main workload's
+    tile sweep (its size class, one raster)."""
+    b = bench.get("batched") or {}
+    single, batch = {}, {}
+    for src, dst in ((b.get("tuning_single_ms", {}), single), (b.get("tuning_ms", {}), batch)):
+        for cls, cands in src.items():
+            best = min(cands, key=cands.get)
+            dst[cls] = {"tile": [int(v) for v in best.split("x")], "ms": cands[best],
+                        "candidates": cands}
+    sweep = bench.get("tile_sweep_ms_per_step") or {}
+    if sweep:
+        rows, cols = bench["config"]["rows"], bench["config"]["cols"]
+        best = min(sweep, key=sweep.get)
+        single[size_class(rows, cols)] = {"tile": [int(v) for v in best.split("x")],
+                                          "ms": sweep[best], "candidates": sweep}
+    return {arch: single, arch + "|batch": batch}
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="write a tile table from a bench.py JSON line")
+    ap.add_argument("bench_json")
+    ap.add_argument("--arch", default="gfx950")
+    ap.add_argument("--out", default=PACKAGED)
+    a = ap.parse_args()
+    with open(a.bench_json) as f:
+        line = [ln for ln in f if ln.strip().startswith("{")][-1]
+    table = table_from_bench(json.loads(line), a.arch)
+    table["source"] = f"bench.py tuning legs ({os.path.basename(a.bench_json)})"
+    with open(a.out, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    print(a.out)

@@ -1,0 +1,82 @@
+"""Tile-shape autotuner: size classes, cache lookup order (user cache, then
+the packaged table, then 64 x 64), the architecture fallback, and the table
+written from a benchmark line.  The GPU test times real candidates."""
+import json
+
+import pytest
+import torch
+
+from paper_1608_04431_amd import autotune
+
+
+def test_size_class():
+    assert autotune.size_class(1, 1) == "64"
+    assert autotune.size_class(64, 10) == "64"
+    assert autotune.size_class(65, 10) == "128"
+    assert autotune.size_class(100, 4096) == "4096"
+    assert autotune.size_class(4097, 3) == "8192"
+    assert autotune.size_class(32768, 32768) == "32768"
+
+
+def test_lookup_order_and_fallback(tmp_path, monkeypatch):
+    packaged = tmp_path / "packaged.json"
+    packaged.write_text(json.dumps({"gfx950": {"512": {"tile": [32, 64]}},
+                                    "gfx950|batch": {"512": {"tile": [48, 64]}}}))
+    monkeypatch.setattr(autotune, "PACKAGED", str(packaged))
+    user = tmp_path / "user.json"
+    t = autotune.Tuner(path=str(user))
+    t.key = "Some GPU|gfx950"
+    assert t.tile_for(300, 500) == (32, 64)                # packaged, by architecture
+    assert t.tile_for(300, 500, batch=True) == (48, 64)
+    assert t.tile_for(3000, 10) == autotune.DEFAULT_TILE   # no entry for the class
+    assert t.tile_for(3000, 10, batch=True) == autotune.DEFAULT_TILE
+    t.user = {"Some GPU|gfx950": {"512": {"tile": [64, 32]}}}
+    assert t.tile_for(300, 500) == (64, 32)                # user cache first
+    assert t.tile_for(300, 500, batch=True) == (48, 64)    # batch keeps its own entry
+    t.save()
+    assert json.loads(user.read_text()) == t.user
+    t.key = "Other|gfx942"
+    assert t.tile_for(300, 500) == autotune.DEFAULT_TILE
+
+
+def test_table_from_bench():
+    bench = {"config": {"rows": 32768, "cols": 32768},
+             "tile_sweep_ms_per_step": {"64x64": 30.0, "64x48": 29.0},
+             "batched": {"tuning_ms": {"256": {"64x64": 2.0, "32x32": 1.5}},
+                         "tuning_single_ms": {"256": {"64x64": 0.5, "32x32": 0.4}}}}
+    t = autotune.table_from_bench(bench, "gfx950")
+    assert t["gfx950"]["32768"]["tile"] == [64, 48]
+    assert t["gfx950"]["256"]["tile"] == [32, 32]
+    assert t["gfx950|batch"]["256"]["tile"] == [32, 32]
+
+
+def test_packaged_table_is_valid():
+    data = json.load(open(autotune.PACKAGED))
+    for key, table in data.items():
+        if key == "source":
+            continue
+        for cls, entry in table.items():
+            th, tw = entry["tile"]
+            assert 1 <= th <= 64 and 1 <= tw <= 64, (key, cls)
+
+
+@pytest.mark.gpu
+def test_tune_on_device(tmp_path):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    import oracle
+    import synth
+    import paper_1608_04431_amd as d8
+    d8._lib.load()
+    z = synth.dem(300, 200, seed=12, lambda0=64)
+    dirs = torch.from_numpy(oracle.d8(z)).cuda()
+    w = torch.from_numpy(synth.uniform(z.shape, 13)).cuda()
+    t = autotune.Tuner(path=str(tmp_path / "tiles.json"))
+    times = t.tune(dirs, w, w, candidates=((64, 64), (32, 32)), reps=1)
+    assert set(times) == {(64, 64), (32, 32)} and all(v > 0 for v in times.values())
+    assert t.tile_for(300, 200) == min(times, key=times.get)
+    assert json.load(open(tmp_path / "tiles.json"))[t.key]["512"]["tile"]
+    samples = [(dirs, w, w), (dirs[:100].contiguous(), w[:100].contiguous(), w[:100].contiguous())]
+    bt = t.tune_batch(samples, candidates=((64, 64), (32, 32)), reps=1)
+    assert set(bt) == {(64, 64), (32, 32)}
+    assert t.tile_for(300, 200, batch=True) == min(bt, key=bt.get)
