@@ -44,8 +44,8 @@ SWEEP_TILES = ((64, 64), (64, 56), (56, 64), (64, 48), (48, 64), (32, 64))
 KERNEL_NAMES = {  # timing label -> kernel symbol prefix in profiler output
     "fwd_pass1": "void d8::fwd_walk<1, unsigned int",
     "fwd_pass2": "void d8::fwd_walk<2, unsigned int",
-    "adj_pass1": "void d8::adj_walk<1>",
-    "adj_pass2": "void d8::adj_walk<2>",
+    "adj_pass1": "d8::adj_walk",
+    "adj_pass2": "d8::adj_finish",
 }
 SOURCES = ("paper_1608_04431_amd/csrc/d8flow.hip", "paper_1608_04431_amd/csrc/kernels.h",
            "paper_1608_04431_amd/csrc/walk.h", "paper_1608_04431_amd/csrc/d8_common.h")
