@@ -357,6 +357,17 @@ def run(args, bd):
     # inputs resident in HBM before timing
     dem = torch.from_numpy(z).to(dev)
     dirs = d8.d8_directions(dem)
+    # D8 directions on their own (not part of the step): events around 5 runs
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        d8.d8_directions(dem, out=dirs)
+    e1.record()
+    torch.cuda.synchronize()
+    d8_ms = e0.elapsed_time(e1) / 5
+    d8_gbps = KERNEL_BYTES_PER_CELL["d8_directions"] * n_cells / (d8_ms * 1e-3) / 1e9
+    log(f"d8_directions: {d8_ms:.3f} ms, {d8_gbps:.0f} GB/s algorithmic")
     del dem
     g = torch.from_numpy(synth.uniform((rows, cols), wl.get("seed_g", 31))).to(dev)
     A = torch.empty((rows, cols), dtype=torch.int32, device=dev)
@@ -466,6 +477,8 @@ def run(args, bd):
         "tile_sweep_ms_per_step": sweep,
         "tuner_device_key": __import__("paper_1608_04431_amd.autotune", fromlist=["x"]).device_key(),
         "roofline": roofline,
+        "d8_directions": {"ms": round(d8_ms, 4), "bytes_per_cell": KERNEL_BYTES_PER_CELL["d8_directions"],
+                          "achieved_GBps": d8_gbps, "frac_hbm_peak": d8_gbps / HBM_PEAK_GBPS},
         "cpu_baseline": cpu,
     }
     if bd is not None:

@@ -502,21 +502,23 @@ int d8_directions(const float *dem, uint8_t *dirs, int64_t rows, int64_t cols, f
     if (rows == 0 || cols == 0) return D8_OK;
     if (!dem || !dirs) return D8_EINVAL;
     begin_call();
-    dim3 block(64, 4);
-    int64_t gx = (cols + 63) / 64, gy = (rows + 3) / 4;
-    if (gx > INT_MAX || gy > 65535) {
-        // very tall rasters: one launch per band of rows
-        for (int64_t r0 = 0; r0 < rows; r0 += 65535 * 4) {
-            int64_t nr = rows - r0 < 65535 * 4 ? rows - r0 : 65535 * 4;
-            dim3 grid((unsigned)gx, (unsigned)((nr + 3) / 4));
-            d8_kernel<<<grid, block, 0, as_stream(stream)>>>(dem + r0 * cols, dirs + r0 * cols, nr,
-                                                             cols, nodata);
-        }
-        return last_error();
+    const int64_t ncb = (cols + kD8Cols - 1) / kD8Cols, nstrips = (rows + kD8Rows - 1) / kD8Rows;
+    const bool vec = cols % 4 == 0 && (reinterpret_cast<uintptr_t>(dem) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(dirs) & 3) == 0;
+    // at most 2^22 blocks per launch (grid size in lanes stays below 2^32)
+    const int64_t per = std::max<int64_t>(1, ((int64_t)1 << 22) / ncb);
+    for (int64_t s0 = 0; s0 < nstrips; s0 += per) {
+        const int64_t ns = nstrips - s0 < per ? nstrips - s0 : per;
+        const unsigned nb = (unsigned)(ns * ncb);
+        if (vec)
+            D8_LAUNCH("d8_directions", as_stream(stream),
+                      (d8_kernel<true><<<nb, kD8Threads, 0, as_stream(stream)>>>(
+                          dem, dirs, rows, cols, nodata, ncb, s0)));
+        else
+            D8_LAUNCH("d8_directions", as_stream(stream),
+                      (d8_kernel<false><<<nb, kD8Threads, 0, as_stream(stream)>>>(
+                          dem, dirs, rows, cols, nodata, ncb, s0)));
     }
-    D8_LAUNCH("d8_directions", as_stream(stream),
-              (d8_kernel<<<dim3((unsigned)gx, (unsigned)gy), block, 0, as_stream(stream)>>>(
-                  dem, dirs, rows, cols, nodata)));
     return last_error();
 }
 

@@ -32,38 +32,150 @@ __global__ void fill_u32(uint32_t *p, uint32_t v, int64_t n)
 }
 
 // ------------------------------------------------------------------- D8 ----
-// One thread per cell; neighbours come through L1/L2.  The drop is a single
-// float32 subtraction and the slope compare is exact in double (a float32
-// squared fits a double): cardinal key 2 d^2, diagonal key d^2.
-__global__ void d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t rows,
-                          int64_t cols, float nodata)
+// Steepest descent (O'Callaghan and Mark, the rule the paper takes as given):
+// among the in-grid data neighbours strictly lower than the cell, the one with
+// the largest drop per unit distance, the lowest code on ties; none -> NoFlow.
+// The drop is one float32 subtraction; distances 1 and sqrt 2 are compared
+// exactly in double as 2 d_card^2 against d_diag^2 (a float32 squared fits a
+// double).  The best cardinal and the best diagonal are found by float
+// compares of the drops (the key is monotone in the drop), then one double
+// compare picks between them.
+//
+// Layout: a block of 256 lanes covers 1024 columns (4 consecutive cells per
+// lane) and walks a strip of kD8Rows rows top to bottom, keeping the rows
+// above, at and below the current one in registers, so every elevation is read
+// from HBM once (plus one halo row per strip edge).  Column neighbours come
+// from the adjacent lane (shuffle) or, at a wavefront's edge, one extra load
+// of a uniform address.  NoData and off-grid neighbours are NaN, which no
+// compare selects.  VEC: rows start 16-byte aligned (cols % 4 == 0 and an
+// aligned dem), so a lane moves its 4 cells with one 16-byte load and one
+// 4-byte store; otherwise per element.  Blocks are mapped XCD-contiguously so
+// vertically and horizontally adjacent blocks share an L2.
+constexpr int kD8Threads = 256;
+constexpr int kD8Cols = 4 * kD8Threads;
+constexpr int kD8Rows = 64;
+
+struct D8Row {
+    float v[4];  // cells c0 .. c0+3
+    float l, r;  // cells c0-1 and c0+4
+};
+
+__device__ inline float d8_z(float z, float nodata)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t r = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
-    if (r >= rows || c >= cols) return;
-    float zc = dem[r * cols + c];
-    if (zc == nodata || zc != zc) {
-        dirs[r * cols + c] = kNoData;
-        return;
+    return z == nodata ? __builtin_nanf("") : z;
+}
+
+template <bool VEC>
+__device__ inline void d8_row_load(const float *__restrict__ dem, int64_t rows, int64_t cols,
+                                   int64_t r, int64_t c0, float4 &q, float &hl, float &hr)
+{
+    const float nan = __builtin_nanf("");
+    q = make_float4(nan, nan, nan, nan);
+    hl = hr = nan;
+    if (r < 0 || r >= rows) return;
+    const float *p = dem + r * cols;
+    if constexpr (VEC) {
+        if (c0 < cols) q = *reinterpret_cast<const float4 *>(p + c0);
+    } else {
+        if (c0 < cols) q.x = p[c0];
+        if (c0 + 1 < cols) q.y = p[c0 + 1];
+        if (c0 + 2 < cols) q.z = p[c0 + 2];
+        if (c0 + 3 < cols) q.w = p[c0 + 3];
     }
-    int best = kNoFlow;
-    double best_key = 0.0;
+    // halo of the wavefront: the same address in every lane
+    const int64_t cw = c0 - 4 * (threadIdx.x & 63);
+    if (cw > 0 && cw <= cols) hl = p[cw - 1];
+    if (cw + 256 < cols) hr = p[cw + 256];
+}
+
+__device__ inline D8Row d8_row_finish(float4 q, float hl, float hr, float nodata)
+{
+    D8Row o;
+    o.v[0] = d8_z(q.x, nodata);
+    o.v[1] = d8_z(q.y, nodata);
+    o.v[2] = d8_z(q.z, nodata);
+    o.v[3] = d8_z(q.w, nodata);
+    const int lane = threadIdx.x & 63;
+    const float l = __shfl_up(o.v[3], 1, 64), r = __shfl_down(o.v[0], 1, 64);
+    o.l = lane == 0 ? d8_z(hl, nodata) : l;
+    o.r = lane == 63 ? d8_z(hr, nodata) : r;
+    return o;
+}
+
+__device__ inline float d8_at(const D8Row &row, int i)  // i in -1 .. 4
+{
+    return i < 0 ? row.l : (i > 3 ? row.r : row.v[i]);
+}
+
+__device__ inline void d8_consider(float zc, float zn, int k, float &best, int &code)
+{
+    const float d = __fsub_rn(zc, zn);
+    if (d > best) {
+        best = d;
+        code = k;
+    }
+}
+
+__device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8Row &dn)
+{
+    uint32_t out = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        int64_t rr = r + dir_dr(k), cc = c + dir_dc(k);
-        if (rr < 0 || rr >= rows || cc < 0 || cc >= cols) continue;
-        float zn = dem[rr * cols + cc];
-        if (zn == nodata || zn != zn) continue;
-        float d = __fsub_rn(zc, zn);
-        if (!(d > 0.0f)) continue;
-        double dd = (double)d;
-        double key = (dir_dr(k) == 0 || dir_dc(k) == 0) ? 2.0 * dd * dd : dd * dd;
-        if (key > best_key) {
-            best_key = key;
-            best = k;
+    for (int i = 0; i < 4; ++i) {
+        const float zc = mid.v[i];
+        int code = kNoData;
+        if (zc == zc) {
+            float bc = 0.0f, bd = 0.0f;
+            int kc = kNoFlow, kd = kNoFlow;
+            d8_consider(zc, d8_at(up, i - 1), 0, bd, kd);
+            d8_consider(zc, d8_at(up, i), 1, bc, kc);
+            d8_consider(zc, d8_at(up, i + 1), 2, bd, kd);
+            d8_consider(zc, d8_at(mid, i - 1), 3, bc, kc);
+            d8_consider(zc, d8_at(mid, i + 1), 4, bc, kc);
+            d8_consider(zc, d8_at(dn, i - 1), 5, bd, kd);
+            d8_consider(zc, d8_at(dn, i), 6, bc, kc);
+            d8_consider(zc, d8_at(dn, i + 1), 7, bd, kd);
+            const double dc = bc, dd = bd;
+            const double keyc = 2.0 * (dc * dc), keyd = dd * dd;
+            code = keyd > keyc ? kd : (keyc > keyd ? kc : (kc < kd ? kc : kd));
         }
+        out |= (uint32_t)code << (8 * i);
     }
-    dirs[r * cols + c] = (uint8_t)best;
+    return out;
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(kD8Threads)
+d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t rows, int64_t cols,
+          float nodata, int64_t ncb, int64_t strip0)
+{
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t strip = strip0 + t / ncb, cb = t - (t / ncb) * ncb;
+    const int64_t c0 = cb * kD8Cols + 4 * (int64_t)threadIdx.x;
+    const int64_t r0 = strip * kD8Rows;
+    const int64_t r1 = rows - r0 < kD8Rows ? rows : r0 + kD8Rows;
+    const float nodata_ = nodata;
+    float4 q;
+    float hl, hr;
+    d8_row_load<VEC>(dem, rows, cols, r0 - 1, c0, q, hl, hr);
+    D8Row up = d8_row_finish(q, hl, hr, nodata_);
+    d8_row_load<VEC>(dem, rows, cols, r0, c0, q, hl, hr);
+    D8Row mid = d8_row_finish(q, hl, hr, nodata_);
+    d8_row_load<VEC>(dem, rows, cols, r0 + 1, c0, q, hl, hr);
+    for (int64_t r = r0; r < r1; ++r) {
+        const D8Row dn = d8_row_finish(q, hl, hr, nodata_);
+        d8_row_load<VEC>(dem, rows, cols, r + 2, c0, q, hl, hr);  // in flight during the compare
+        const uint32_t codes = d8_codes4(up, mid, dn);
+        uint8_t *o = dirs + r * cols + c0;
+        if constexpr (VEC) {
+            if (c0 < cols) *reinterpret_cast<uint32_t *>(o) = codes;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (c0 + i < cols) o[i] = (uint8_t)(codes >> (8 * i));
+        }
+        up = mid;
+        mid = dn;
+    }
 }
 
 // ------------------------------------------------------------ perimeter graph

@@ -86,6 +86,29 @@ def test_d8_directions_match_oracle(d8m):
         np.testing.assert_array_equal(got, oracle.d8(z))
 
 
+def test_d8_directions_strips_blocks_and_alignment(d8m):
+    """Shapes that cross the kernel's 64-row strips and 1024-column blocks,
+    with and without 4-aligned rows, ties, NoData, NaN and infinities; then the
+    same inputs through misaligned input and output pointers (the per-element
+    path)."""
+    rng = np.random.default_rng(5)
+    for shape in [(130, 2052), (129, 2051), (65, 1024), (64, 1025), (3, 4), (200, 8), (1, 1)]:
+        z = rng.integers(0, 6, shape).astype(np.float32)
+        z[rng.random(shape) < 0.05] = -9999.0
+        z[rng.random(shape) < 0.02] = np.nan
+        z[rng.random(shape) < 0.01] = np.inf
+        z[rng.random(shape) < 0.01] = -np.inf
+        want = oracle.d8(z)
+        np.testing.assert_array_equal(d8m.d8_directions(dev(z)).cpu().numpy(), want)
+        flat = torch.empty(z.size + 1, dtype=torch.float32, device="cuda")
+        flat[1:] = dev(z).flatten()
+        obuf = torch.zeros(z.size + 3, dtype=torch.uint8, device="cuda")
+        out = obuf[1:1 + z.size].view(shape)
+        d8m.d8_directions(flat[1:].view(shape), out=out)
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+        assert int(obuf[0]) == 0 and (obuf[1 + z.size:] == 0).all()
+
+
 # ------------------------------------------------------------ hand fixtures --
 def test_golden_fixtures_u32(d8m):
     from conftest import GOLDEN_FILES, load_golden
