@@ -50,7 +50,7 @@ enum d8_code {
 enum d8_status {
     D8_OK = 0,
     D8_EINVAL = -1,     /* bad argument: null pointer, size, tile shape, type   */
-    D8_EWORKSPACE = -2, /* workspace missing or smaller than required            */
+    D8_EWORKSPACE = -2, /* workspace missing, not 256-byte aligned, or too small */
     D8_EHIP = -3,       /* a HIP launch or runtime call failed                   */
     D8_EDIRCODE = -4,   /* (data) a direction code above 9 was found             */
     D8_ECYCLE = -5      /* (data) the directions contain a cycle                 */
@@ -109,7 +109,8 @@ size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_co
  * tile_rows, tile_cols: tile shape (0, 0 = default 64 x 64); each >= 1; a
  *           side longer than the raster is cut to the raster; after that
  *           each side <= D8_MAX_TILE_SIDE.
- * ws, ws_bytes: workspace (device), at least d8_workspace_bytes(...).
+ * ws, ws_bytes: workspace (device, 256-byte aligned as every torch or hipMalloc
+ *     allocation is), at least d8_workspace_bytes(...).
  * U32 counts are exact while every true count is below 2^32.
  * F32: each tile sums in float32, the cross-tile resolve in float64.
  * Returns D8_OK, D8_EINVAL, D8_EWORKSPACE or D8_EHIP (asynchronous data errors
@@ -159,7 +160,7 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
  *   grad_acc (in) and grad_weights (out) for D8_BATCH_ADJ.
  * mode: D8_BATCH_FWD, D8_BATCH_ADJ or both (forward first, then adjoint).
  * items: host array of n items (read during the call only).
- * ws, ws_bytes: device workspace of at least d8_batch_workspace_bytes(items,
+ * ws, ws_bytes: device workspace (256-byte aligned) of at least d8_batch_workspace_bytes(items,
  *   n) bytes (the same items; 0 means the items are invalid).  It holds the
  *   batch's descriptor tables and perimeter-graph arrays.
  */

@@ -134,6 +134,39 @@ thread_local int g_launch_rc = D8_OK;
 
 inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Downstream sums over the exit forest: dense numbering of the exits (count,
+// scan, map), initial words, then ceil(log2 N) + 1 pointer-jumping rounds and
+// the convergence check.  bsum takes one word per 4096 nodes, cmap one per
+// node; the sums end in jw[jstate[0]] at the exits' dense numbers.  Returns
+// the number of rounds.
+int jump_exits(hipStream_t st, int64_t N, const uint16_t *link, const uint32_t *entry,
+               const uint32_t *succ, const float *S, uint32_t *bsum, uint32_t *cmap,
+               unsigned long long *const jw[2], uint32_t *jstate, uint32_t *status, bool batch)
+{
+    // timing labels are kept by pointer: literals only
+#define JNAME(s) (batch ? "batch_" s : s)
+    uint32_t *nexit = jstate + 4;
+    const int64_t ncb = (N + kCompactNodes - 1) / kCompactNodes;
+    D8_LAUNCH(JNAME("adj_compact"), st,
+              (adj_compact_count<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum)));
+    D8_LAUNCH(JNAME("adj_compact"), st, (adj_compact_scan<<<1, 1024, 0, st>>>(ncb, bsum, nexit)));
+    D8_LAUNCH(JNAME("adj_compact"), st,
+              (adj_compact_map<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum, cmap)));
+    D8_LAUNCH(JNAME("adj_jump_init"), st,
+              (adj_jump_init<<<blocks_for(N, kNodeBlock), kNodeBlock, 0, st>>>(N, link, entry, succ, S,
+                                                                               cmap, jw[0])));
+    int rounds = 1;
+    while (((int64_t)1 << (rounds - 1)) <= N) ++rounds;
+    const unsigned jb = std::min<unsigned>(blocks_for(N, 2 * kNodeBlock), 4096u);
+    for (int r = 0; r < rounds; ++r)
+        D8_LAUNCH(JNAME("adj_jump_round"), st,
+                  (adj_jump_round<<<jb, kNodeBlock, 0, st>>>(nexit, jw[r & 1], jw[(r + 1) & 1], jstate, r)));
+    D8_LAUNCH(JNAME("adj_jump_finish"), st,
+              (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
+#undef JNAME
+    return rounds;
+}
+
 // one wavefront per tile
 constexpr int kTileThreads = 64;
 
@@ -442,17 +475,10 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
         D8_LAUNCH("batch_graph_build", st,
                   (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
                                                                 succ, nullptr)));
-        D8_LAUNCH("batch_adj_jump_init", st,
-                  (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(N, link, entry, succ, val32, jw[0], jw[1])));
-        int rounds = 1;
-        while (((int64_t)1 << (rounds - 1)) <= N) ++rounds;
-        for (int r = 0; r < rounds; ++r)
-            D8_LAUNCH("batch_adj_jump_round", st,
-                      (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(N, jw[r & 1], jw[(r + 1) & 1], jstate, r)));
-        D8_LAUNCH("batch_adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
+        jump_exits(st, N, link, entry, succ, val32, indeg, cnt, jw, jstate, status, true);
         D8_LAUNCH("batch_adj_pass2", st,
                   (adj_finish_batch<<<(unsigned)P.ntiles, 64, 0, st>>>(dems, tile_dem, (uint32_t)P.ntiles,
-                                                                      jw[0], jw[1], jstate)));
+                                                                      cnt, jw[0], jw[1], jstate)));
     }
     return last_error();
 }
@@ -467,7 +493,7 @@ int batch_prepare(const d8_batch_item *items, int n, int mode, void *ws, size_t 
         if ((mode & D8_BATCH_FWD) && !D.acc) return D8_EINVAL;
         if ((mode & D8_BATCH_ADJ) && (!D.gacc || !D.gw)) return D8_EINVAL;
     }
-    if (!ws || ws_bytes < P.L.total) return D8_EWORKSPACE;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) || ws_bytes < P.L.total) return D8_EWORKSPACE;
     return D8_OK;
 }
 
@@ -540,7 +566,7 @@ int flow_accum(const uint8_t *dirs, const float *weights, void *acc, int acc_typ
     bool empty;
     int rc = check_common(rows, cols, tile_rows, tile_cols, g, empty);
     if (rc != D8_OK) return rc;
-    if (!ws) return D8_EWORKSPACE;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;
     if (empty) {
         if (ws_bytes < 512) return D8_EWORKSPACE;
         init_state<<<1, 1, 0, as_stream(stream)>>>(reinterpret_cast<uint32_t *>(ws),
@@ -567,7 +593,7 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     bool empty;
     int rc = check_common(rows, cols, tile_rows, tile_cols, g, empty);
     if (rc != D8_OK) return rc;
-    if (!ws) return D8_EWORKSPACE;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;
     hipStream_t st = as_stream(stream);
     if (empty) {
         if (ws_bytes < 512) return D8_EWORKSPACE;
@@ -589,6 +615,7 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                                  reinterpret_cast<unsigned long long *>(w8 + L.ext64)};
 
     uint8_t *root8 = reinterpret_cast<uint8_t *>(w8 + L.root8);
+    uint32_t *cmap = reinterpret_cast<uint32_t *>(w8 + L.ptr2);
     int ntiles = g.nty * g.ntx;
     const int thr = kTileThreads;
     size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1);
@@ -602,17 +629,12 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                                                    status)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr)));
-    D8_LAUNCH("adj_jump_init", st,
-              (adj_jump_init<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, entry, succ, S, jw[0], jw[1])));
-    int rounds = 1;
-    while (((int64_t)1 << (rounds - 1)) <= g.nnodes) ++rounds;
-    for (int r = 0; r < rounds; ++r)
-        D8_LAUNCH("adj_jump_round", st,
-                  (adj_jump_round<<<nb, kNodeBlock, 0, st>>>(g.nnodes, jw[r & 1], jw[(r + 1) & 1], jstate,
-                                                             r)));
-    D8_LAUNCH("adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
+    const int rounds = jump_exits(st, g.nnodes, link, entry, succ, S,
+                                  reinterpret_cast<uint32_t *>(w8 + L.indeg), cmap, jw, jstate, status,
+                                  false);
     D8_LAUNCH("adj_pass2", st,
-              (adj_finish<<<ntiles, thr, 0, st>>>(g, root8, jw[0], jw[1], jstate, grad_weights)));
+              (adj_finish<<<ntiles, thr, 0, st>>>(g, root8, cmap, jw[0], jw[1], jstate, grad_weights)));
+    (void)rounds;
     return last_error();
 }
 

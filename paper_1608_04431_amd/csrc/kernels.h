@@ -334,32 +334,166 @@ __device__ inline unsigned long long jump_word(uint32_t ptr, float v)
 }
 __device__ inline float jump_val(unsigned long long w) { return __uint_as_float((uint32_t)(w >> 32)); }
 
-// Initial state: exits point at their successor with val = S(entry); every
-// other node is inert (done, 0) in both buffers.
-__global__ void adj_jump_init(int64_t nnodes, const uint16_t *__restrict__ link,
-                              const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
-                              const float *__restrict__ S, unsigned long long *buf0,
-                              unsigned long long *buf1)
+// Only exits take part: they are numbered densely in node order (a stream
+// compaction of the link array), so the rounds run over the exit forest
+// alone (about a third of the perimeter nodes), in contiguous memory.
+// Blocks of 256 lanes take 4096 consecutive nodes, 16 per lane.
+constexpr int kCompactBlock = 256;
+constexpr int kCompactPer = 16;
+constexpr int64_t kCompactNodes = (int64_t)kCompactBlock * kCompactPer;
+
+// Bit j: node n0 + j is an exit (n0 is a multiple of 16).
+__device__ inline uint32_t exit_bits16(const uint16_t *__restrict__ link, int64_t nnodes, int64_t n0)
 {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nnodes) return;
-    unsigned long long w = jump_word(kJumpDone, 0.0f);
-    if (link[id] == kLinkExt) {
-        const uint32_t n = entry[id];
-        w = jump_word(succ[id], n != kNone ? S[n] : 0.0f);
+    uint32_t m = 0;
+    if (n0 + kCompactPer <= nnodes && (reinterpret_cast<uintptr_t>(link + n0) & 15) == 0) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(link + n0);
+        const uint4 a = p[0], b = p[1];
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            m |= (uint32_t)((w[i] & 0xFFFFu) == kLinkExt) << (2 * i);
+            m |= (uint32_t)((w[i] >> 16) == kLinkExt) << (2 * i + 1);
+        }
+    } else {
+        for (int j = 0; j < kCompactPer; ++j)
+            if (n0 + j < nnodes && link[n0 + j] == kLinkExt) m |= 1u << j;
     }
-    buf0[id] = w;
-    buf1[id] = w;
+    return m;
 }
 
-// One synchronous round r: reads buffer r&1, writes buffer (r+1)&1:
-// val' = val + val[ptr], ptr' = ptr[ptr].  live[r%3] is set when any
-// pointer is still live after the round; round r reads live[(r-1)%3] and, if
-// nothing was live, records the final buffer in state[0] and does nothing.
-// live[(r+1)%3] is cleared here for the next round (its previous contents were
-// read by round r-1, which has completed).
-__global__ void adj_jump_round(int64_t nnodes, unsigned long long *w_in, unsigned long long *__restrict__ w_out,
-                               uint32_t *state, int round)
+// Exclusive prefix of v over the block's lanes; *total gets the block sum.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kCompactBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kCompactBlock / 64; ++i) {
+        before += i < wv ? wsum[i] : 0u;
+        all += wsum[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}
+
+// Exits per block of 4096 nodes.
+__global__ void __launch_bounds__(kCompactBlock)
+adj_compact_count(int64_t nnodes, const uint16_t *__restrict__ link, uint32_t *__restrict__ bsum)
+{
+    const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
+    const uint32_t c = __popc(exit_bits16(link, nnodes, n0));
+    uint32_t total;
+    block_excl_scan(c, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block counts in place (one block); the number of
+// exits goes to *nexit.
+__global__ void __launch_bounds__(1024)
+adj_compact_scan(int64_t nblocks, uint32_t *bsum, uint32_t *nexit)
+{
+    __shared__ uint32_t part[16];
+    __shared__ uint32_t carry_s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    // chunks of 8192 counts: 8 consecutive per lane
+    for (int64_t c0 = 0; c0 < nblocks; c0 += 8192) {
+        const int64_t i0 = c0 + 8 * (int64_t)threadIdx.x;
+        uint32_t v[8], s = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v[k] = i0 + k < nblocks ? bsum[i0 + k] : 0u;
+            s += v[k];
+        }
+        uint32_t x = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) part[wv] = x;
+        __syncthreads();
+        uint32_t before = carry_s, all = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            before += i < wv ? part[i] : 0u;
+            all += part[i];
+        }
+        uint32_t run = before + x - s;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (i0 + k < nblocks) bsum[i0 + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *nexit = carry_s;
+}
+
+// cmap[n] = the dense index of exit n, kNone for other nodes.
+__global__ void __launch_bounds__(kCompactBlock)
+adj_compact_map(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_t *__restrict__ bsum,
+                uint32_t *__restrict__ cmap)
+{
+    const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
+    const uint32_t m = exit_bits16(link, nnodes, n0);
+    uint32_t total;
+    uint32_t idx = bsum[blockIdx.x] + block_excl_scan(__popc(m), &total);
+    uint32_t out[kCompactPer];
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+        out[j] = (m >> j) & 1u ? idx : kNone;
+        idx += (m >> j) & 1u;
+    }
+    if (n0 + kCompactPer <= nnodes && (reinterpret_cast<uintptr_t>(cmap + n0) & 15) == 0) {
+        uint4 *p = reinterpret_cast<uint4 *>(cmap + n0);
+#pragma unroll
+        for (int i = 0; i < kCompactPer / 4; ++i)
+            p[i] = make_uint4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    } else {
+        for (int j = 0; j < kCompactPer; ++j)
+            if (n0 + j < nnodes) cmap[n0 + j] = out[j];
+    }
+}
+
+// Initial words of the exits: pointer = the dense index of the successor
+// (kNone at a root), val = S(entry).  Round 0 writes every word of the other
+// buffer, so only one is initialised.
+__global__ void adj_jump_init(int64_t nnodes, const uint16_t *__restrict__ link,
+                              const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
+                              const float *__restrict__ S, const uint32_t *__restrict__ cmap,
+                              unsigned long long *__restrict__ buf0)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nnodes || link[id] != kLinkExt) return;
+    const uint32_t n = entry[id], s = succ[id];
+    buf0[cmap[id]] = jump_word(s != kNone ? cmap[s] : kNone, n != kNone ? S[n] : 0.0f);
+}
+
+// One synchronous round r over the exits (their count is *nexit): reads
+// buffer r&1, writes buffer (r+1)&1: val' = val + val[ptr], ptr' = ptr[ptr].
+// live[r%3] is set when any pointer is still live after the round; round r
+// reads live[(r-1)%3] and, if nothing was live, records the final buffer in
+// state[0] and does nothing.  live[(r+1)%3] is cleared here for the next
+// round (its previous contents were read by round r-1, which has completed).
+// A fixed grid strides over the exits, so rounds after convergence cost one
+// small launch.
+__global__ void __launch_bounds__(256)
+adj_jump_round(const uint32_t *__restrict__ nexit, unsigned long long *w_in,
+               unsigned long long *__restrict__ w_out, uint32_t *state, int round)
 {
     uint32_t *live = state + 1;
     if (live[(round + 2) % 3] == 0) {
@@ -369,27 +503,47 @@ __global__ void adj_jump_round(int64_t nnodes, unsigned long long *w_in, unsigne
         }
         return;
     }
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id == 0) live[(round + 1) % 3] = 0;
+    const int64_t E = *nexit;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t id0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id0 == 0) live[(round + 1) % 3] = 0;
     bool alive = false;
-    if (id < nnodes) {
-        const unsigned long long w = w_in[id];
-        const uint32_t p = (uint32_t)w;
+    for (int64_t i = id0; i < E; i += 2 * stride) {
+        // two words per lane in flight
+        const int64_t j = i + stride;
+        const unsigned long long w = w_in[i];
+        const unsigned long long w2 = j < E ? w_in[j] : jump_word(kJumpDone, 0.0f);
+        const uint32_t p = (uint32_t)w, p2 = (uint32_t)w2;
+        const bool go = p != kNone && p != kJumpDone, go2 = p2 != kNone && p2 != kJumpDone;
+        unsigned long long t = 0, t2 = 0;
+        if (go) t = w_in[p];
+        if (go2) t2 = w_in[p2];
         if (p == kNone) {
             // complete since the last round: the same word, done, in both
             // buffers (readers of w_in see the same sum either way)
             const unsigned long long d = jump_word(kJumpDone, jump_val(w));
-            w_out[id] = d;
-            w_in[id] = d;
-        } else if (p != kJumpDone) {
-            const unsigned long long t = w_in[p];
+            w_out[i] = d;
+            w_in[i] = d;
+        } else if (go) {
             uint32_t np = (uint32_t)t;
             if (np == kJumpDone) np = kNone;
-            alive = np != kNone;
-            w_out[id] = jump_word(np, jump_val(w) + jump_val(t));
+            alive |= np != kNone;
+            w_out[i] = jump_word(np, jump_val(w) + jump_val(t));
+        }
+        if (j < E) {
+            if (p2 == kNone) {
+                const unsigned long long d = jump_word(kJumpDone, jump_val(w2));
+                w_out[j] = d;
+                w_in[j] = d;
+            } else if (go2) {
+                uint32_t np = (uint32_t)t2;
+                if (np == kJumpDone) np = kNone;
+                alive |= np != kNone;
+                w_out[j] = jump_word(np, jump_val(w2) + jump_val(t2));
+            }
         }
     }
-    if (__ballot(alive) != 0 && (threadIdx.x & (warpSize - 1)) == 0) live[round % 3] = 1;
+    if (__ballot(alive) != 0 && (threadIdx.x & 63) == 0) live[round % 3] = 1;
 }
 
 // After the last round: if no round found convergence, the final buffer is

@@ -1078,6 +1078,7 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
 // in place in out.
 __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int t,
                                        const uint8_t *__restrict__ root8,
+                                       const uint32_t *__restrict__ cmap,
                                        const unsigned long long *__restrict__ mu,
                                        float *__restrict__ out, float *mu_l)
 {
@@ -1085,7 +1086,11 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
     WTile Tl = wtile_of(g, t);
     Tl.base += node0;
     const int lane = lane_id();
-    for (int p = lane; p < Tl.P; p += 64) mu_l[p] = __uint_as_float((uint32_t)(mu[Tl.base + p] >> 32));
+    // mu is indexed by the exits' dense numbers; labels name exits only
+    for (int p = lane; p < Tl.P; p += 64) {
+        const uint32_t c = cmap[Tl.base + p];
+        mu_l[p] = c != kNone ? __uint_as_float((uint32_t)(mu[c] >> 32)) : 0.0f;
+    }
     __syncthreads();
     if (rows_vec(Tl, g, out) && ((reinterpret_cast<uintptr_t>(root8) & 3) == 0)) {
         const int c = 4 * (lane & 15), rq = lane >> 4;
@@ -1159,13 +1164,13 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
 }
 
 __global__ void __launch_bounds__(64)
-adj_finish(Geo g, const uint8_t *__restrict__ root8, const unsigned long long *__restrict__ mu0,
-           const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate,
-           float *__restrict__ out)
+adj_finish(Geo g, const uint8_t *__restrict__ root8, const uint32_t *__restrict__ cmap,
+           const unsigned long long *__restrict__ mu0, const unsigned long long *__restrict__ mu1,
+           const uint32_t *__restrict__ jstate, float *__restrict__ out)
 {
     __shared__ float mu_l[256];
     const unsigned long long *mu = jstate[0] == 1 ? mu1 : mu0;
-    adj_finish_tile(g, 0, xcd_tile(blockIdx.x, gridDim.x), root8, mu, out, mu_l);
+    adj_finish_tile(g, 0, xcd_tile(blockIdx.x, gridDim.x), root8, cmap, mu, out, mu_l);
 }
 
 // ---- kernels: a batch of rasters ----------------------------------------
@@ -1204,7 +1209,8 @@ adj_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ ti
 // Batch pass 2: one wavefront per batch tile (an elementwise pass).
 __global__ void __launch_bounds__(64)
 adj_finish_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
-                 uint32_t ntiles, const unsigned long long *__restrict__ mu0,
+                 uint32_t ntiles, const uint32_t *__restrict__ cmap,
+                 const unsigned long long *__restrict__ mu0,
                  const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate)
 {
     __shared__ float mu_l[256];
@@ -1212,7 +1218,7 @@ adj_finish_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ 
     if (t >= ntiles) return;
     const unsigned long long *mu = jstate[0] == 1 ? mu1 : mu0;
     const DemDesc D = dems[tile_dem[t]];
-    adj_finish_tile(D.g, D.node0, (int)(t - D.tile0), D.root8, mu, D.gw, mu_l);
+    adj_finish_tile(D.g, D.node0, (int)(t - D.tile0), D.root8, cmap, mu, D.gw, mu_l);
 }
 
 __host__ inline size_t walk_lds_bytes(int th, int tw, int kind, int vbytes = 4)

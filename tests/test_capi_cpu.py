@@ -56,7 +56,11 @@ def test_argument_errors_return_before_launch():
                           None) == _lib.D8_EINVAL
     assert lib.flow_accum(fake, None, fake, 0, 4, 4, 0, 3, fake, 1 << 20, None) == _lib.D8_EINVAL
     assert lib.flow_accum(fake, None, fake, 0, -4, 4, 0, 0, fake, 1 << 20, None) == _lib.D8_EINVAL
-    # missing / small workspace
+    # missing / misaligned / small workspace
+    odd = ctypes.c_void_p(0x1000 + 16)
+    assert lib.flow_accum(fake, None, fake, 0, 4, 4, 0, 0, odd, 1 << 20, None) == _lib.D8_EWORKSPACE
+    assert lib.flow_accum_adjoint(fake, fake, fake, 4, 4, 0, 0, odd, 1 << 20,
+                                  None) == _lib.D8_EWORKSPACE
     assert lib.flow_accum(fake, None, fake, 0, 4, 4, 0, 0, None, 0, None) == _lib.D8_EWORKSPACE
     assert lib.flow_accum(fake, None, fake, 0, 64, 64, 0, 0, fake, 100, None) == _lib.D8_EWORKSPACE
     assert lib.flow_accum_adjoint(fake, fake, fake, 64, 64, 0, 0, fake, 100,
@@ -94,6 +98,7 @@ def test_batch_argument_errors_return_before_launch():
     assert lib.flow_accum_batched(items, 3, ADJ, fake, nb, None) == EINVAL   # item 0 has no g
     assert lib.flow_accum_batched(items, 3, FWD, fake, nb - 1, None) == EWS
     assert lib.flow_accum_batched(items, 3, FWD, None, 0, None) == EWS
+    assert lib.flow_accum_batched(items, 3, FWD, fake + 64, nb + 64, None) == EWS  # misaligned
     assert lib.flow_accum_batched(None, 3, FWD, fake, nb, None) == EINVAL
     assert lib.flow_accum_batched(items, -1, FWD, fake, nb, None) == EINVAL
     h = ctypes.c_void_p()
