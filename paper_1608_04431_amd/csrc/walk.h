@@ -270,6 +270,7 @@ __device__ inline void load_halo_row(const uint8_t *__restrict__ dirs, const Geo
 
 // Per-lane setup result (bit c = column c of this lane's row).
 struct Setup {
+    uint64_t noflow; // forward: NoFlow cells
     uint64_t src;    // forward: data cells without in-tile donors
     uint64_t entry;  // data cells with a donor in another tile
     uint64_t root;   // adjoint: data cells without an in-tile receiver
@@ -295,7 +296,7 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
         B[m] = from_below(W[m], 0xFFFFFFFFu);
     }
     Setup St;
-    St.src = St.entry = St.root = St.valid = 0;
+    St.noflow = St.src = St.entry = St.root = St.valid = 0;
     const uint32_t G = 0xFFFFFFFFu;  // guard word outside the tile
     const bool own = r < Tl.h;
     uint8_t *rowb = cb8 + (r + 1) * Tl.S + 1;
@@ -327,6 +328,7 @@ __device__ inline Setup setup_tile(const uint8_t *__restrict__ dirs, const Geo &
                 uint32_t single = (eq_bytes(cnt, 1) >> 7) * 0xFFu;
                 bytes = W[m] | ((cnt & ~single) << 4);
                 St.src |= (uint64_t)marker_bits(zero_bytes(cnt) & vm) << (4 * m);
+                St.noflow |= (uint64_t)marker_bits(eq_bytes(W[m], kNoFlow)) << (4 * m);
             } else {
                 uint32_t mask = 0;
 #pragma unroll
@@ -460,7 +462,8 @@ constexpr uint16_t kLlCycle = 0xFFFE;
 // 0.. of the queue, at most `cap`, and clears the bits it wrote; returns how
 // many it wrote (wave-uniform).
 __device__ inline uint32_t fill_queue(uint32_t *q, uint32_t cap, const WTile &Tl, const uint8_t *cb8,
-                                      uint32_t byte_mask, uint64_t &m0, uint64_t &m1)
+                                      uint32_t byte_mask, uint64_t &m0, uint64_t &m1,
+                                      bool ring_flag = false)
 {
     const int lane = lane_id();
     uint32_t n = (uint32_t)(__popcll(m0) + __popcll(m1));
@@ -473,11 +476,16 @@ __device__ inline uint32_t fill_queue(uint32_t *q, uint32_t cap, const WTile &Tl
     uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     uint32_t pos = incl - n;
     const int rowbase = (lane + 1) * Tl.S + 1;
+    // ring_flag: plain walks from a perimeter cell carry kQLink (their seed
+    // may hold a cross-tile inflow)
+    const uint64_t ring = !ring_flag ? 0ull
+                          : (lane == 0 || lane == Tl.h - 1) ? ~0ull
+                                                           : (1ull | (1ull << (Tl.w - 1)));
     while (m0 != 0 && pos < cap) {
         int c = __ffsll((unsigned long long)m0) - 1;
         m0 &= m0 - 1ull;
         const int idx = rowbase + c;
-        q[pos++] = (uint32_t)idx | ((cb8[idx] & byte_mask) << kQByte);
+        q[pos++] = (uint32_t)idx | ((cb8[idx] & byte_mask) << kQByte) | (((ring >> c) & 1ull) ? kQLink : 0u);
     }
     while (m1 != 0 && pos < cap) {
         int c = __ffsll((unsigned long long)m1) - 1;
@@ -512,25 +520,40 @@ __device__ inline uint16_t link_of(const WTile &Tl, uint16_t v, uint32_t *status
 // entry, in the same loop).  avp[idx] holds each cell's seed and receives
 // its accumulation.  Returns the number of cells this lane finished.
 //
-// The claim and the plain step take no branches: an idle lane steps from
-// cell (0, 0) with code 15 (its step ends at once), and a store that does not
-// apply goes to the lane's own dummy word.  Only the rare confluence step
-// branches.
-template <typename VT, bool LINKS>
+// A walk ends on reaching a cell whose flow goes nowhere further inside the
+// tile (NoFlow, NoData, the frame), so a walker's cell always has a code
+// 0..7: its neighbour's index offset comes from a per-tile byte table with
+// one v_perm (offset + 128 per code), and NoFlow sources are finished without
+// a walk.  The claim and the plain step take no branches: an idle lane steps
+// with selector 12 (byte 0) from index 128, i.e. to cell 0 of the frame (its
+// step ends at once), and a store that does not apply goes to the lane's own
+// dummy word.  Only the rare confluence step branches.  Unit seeds (16-bit
+// values) are known to be 1, so a claim reads only its queue entry.
+// SEED: 0 = seeds are read from avp, 1 = every seed is 1, 2 = seeds are 1
+// except on the perimeter (queue entries of perimeter cells carry kQLink).
+template <typename VT, bool LINKS, int SEED>
 __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, uint32_t *cbw, VT *avp,
                                 uint32_t *dummy, uint32_t *q, uint32_t qcap, uint64_t src,
-                                uint64_t ent, uint16_t *ll, int ll_dummy)
+                                uint64_t ent, uint64_t noflow, uint16_t *ll, int ll_dummy)
 {
     using T = typename Acc<VT>::type;
-    const int S = Tl.S, safe = S + 1;
+    static_assert(SEED != 2 || !LINKS, "perimeter seed flags use the link bit");
+    const int S = Tl.S;
     const int lane = lane_id();
     VT *mine = reinterpret_cast<VT *>(dummy + lane);
-    int visited = 0;
-    uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent));
+    // offset + 128 of directions 0..7: (dr, dc) = NW N NE W E SW S SE
+    const uint32_t s8 = (uint32_t)S;
+    const uint32_t lut_lo = (128u - s8 - 1u) | ((128u - s8) << 8) | ((128u - s8 + 1u) << 16) | (127u << 24);
+    const uint32_t lut_hi = 129u | ((128u + s8 - 1u) << 8) | ((128u + s8) << 16) | ((128u + s8 + 1u) << 24);
+    // NoFlow sources are complete as they are; NoFlow entries keep link TERM
+    int visited = __popcll(src & noflow);
+    src &= ~noflow;
+    ent &= ~noflow;
+    uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent, SEED == 2));
     uint32_t head = 0;
     bool more = __ballot(src != 0 || ent != 0) != 0;
     int cur = -1, steps = 0;
-    uint32_t code = 15u, info = 0;
+    uint32_t code = 12u, info = 0;
     T a = (T)0;
     const int max_steps = Tl.h * Tl.w;
     for (;;) {
@@ -538,41 +561,50 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
         if (head >= ntask) {
             if (more) {
                 // the queue has been handed out completely: refill it
-                ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent));
+                ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent, SEED == 2));
                 head = 0;
                 more = __ballot(src != 0 || ent != 0) != 0;
             } else if (idle == ~0ull) {
                 break;
             }
         }
+        bool took = false;
+        T a0 = (T)1;
         if (idle != 0 && head < ntask) {
             const uint32_t j = head + lanes_below(idle);
             const bool take = cur < 0 && j < ntask;
             const uint32_t t = q[take ? j : 0];
             const int nc = (int)(t & kQIdx);
-            const T a0 = (T)avp[take ? nc : safe];
+            if constexpr (SEED == 0) a0 = (T)avp[take ? nc : S + 1];
+            if constexpr (SEED == 2) {
+                const bool rd = take && (t & kQLink);
+                if (__ballot(rd) != 0) a0 = rd ? (T)avp[nc] : (T)1;
+            }
             cur = take ? nc : cur;
             code = take ? ((t >> kQByte) & 15u) : code;
             info = take ? t : info;
             steps = take ? 0 : steps;
-            a = take ? a0 : a;
+            took = take;
             visited += (take && !(LINKS && (t & kQLink))) ? 1 : 0;
             const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (ntask - head < nidle) ? ntask : head + nidle;
         }
         const bool act = cur >= 0;
-        const uint32_t ck = act ? code : 15u;
-        const int ni = (act ? cur : safe) + dir_off(ck, S);
+        const uint32_t sel = act ? code : 12u;
+        const int base = act ? cur : 128;
+        const int ni = base + (int)__builtin_amdgcn_perm(lut_hi, lut_lo, 0x0C0C0C00u | sel) - 128;
         const uint32_t nb = cb8[ni];
         T sv = (T)avp[ni];
         keep_read(sv);
+        // a new walk's seed: its read completes with the step's reads
+        keep_read(a0);
+        a = took ? a0 : a;
         const uint32_t nk = nb & 15u;
         const bool link = LINKS && (info & kQLink);
         if (LINKS) ++steps;
         // a link walk longer than the tile has cells runs into a cycle
-        const bool end = ck >= (uint32_t)kNoFlow || nk >= (uint32_t)kNoData ||
-                         (LINKS && link && steps > max_steps);
-        const bool fw = !end && !link;
+        const bool end = nk >= (uint32_t)kNoData || (LINKS && link && steps > max_steps);
+        const bool fw = act && !end && !link;
         const bool plain = fw && nb < 16u;
         const T ap = a + sv;
         *(plain ? &avp[ni] : mine) = (VT)ap;
@@ -588,16 +620,71 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
         }
         a = plain ? ap : a;
         visited += (plain || last) ? 1 : 0;
+        // the walk goes on from the next cell only if its flow stays in the tile
+        const bool stop = end || nk >= (uint32_t)kNoFlow;
         if (LINKS) {
-            const uint16_t v = steps > max_steps ? kLlCycle
-                               : (ck < (uint32_t)kNoFlow && nk == kFrameTile) ? (uint16_t)cur
-                                                                              : kLlTerm;
-            ll[(act && link && end) ? (int)(info >> kQRing) : ll_dummy] = v;
+            const uint16_t v = steps > max_steps ? kLlCycle : (nk == kFrameTile ? (uint16_t)cur : kLlTerm);
+            ll[(act && link && stop) ? (int)(info >> kQRing) : ll_dummy] = v;
         }
-        cur = (act && !end && (plain || last || link)) ? ni : -1;
+        cur = (act && !stop && (plain || last || link)) ? ni : -1;
         code = nk;
     }
     return visited;
+}
+
+// Algorithm 2 (FollowPath) for the entries of a tile, after the forward
+// walks: one walk per entry along its flow path to the cell whose flow leaves
+// the tile (its exit: the cell index goes to ll[ring index of the entry]),
+// or to the end of its flow inside the tile (kLlTerm), or kLlCycle after more
+// steps than the tile has cells.  Only the low nibble (the code) of each
+// cell byte is read.  Offsets as in fwd_walks; an idle lane steps to frame
+// cell 0 and writes ll[ll_dummy].
+__device__ inline void link_walks(const WTile &Tl, const uint8_t *cb8, uint32_t *q, uint32_t qcap,
+                                  uint64_t ent, uint16_t *ll, int ll_dummy)
+{
+    const uint32_t s8 = (uint32_t)Tl.S;
+    const uint32_t lut_lo = (128u - s8 - 1u) | ((128u - s8) << 8) | ((128u - s8 + 1u) << 16) | (127u << 24);
+    const uint32_t lut_hi = 129u | ((128u + s8 - 1u) << 8) | ((128u + s8) << 16) | ((128u + s8 + 1u) << 24);
+    uint64_t none = 0;
+    uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, none, ent));
+    uint32_t head = 0;
+    bool more = __ballot(ent != 0) != 0;
+    int cur = -1, steps = 0, ring = ll_dummy;
+    uint32_t code = 12u;
+    const int max_steps = Tl.h * Tl.w;
+    for (;;) {
+        const uint64_t idle = __ballot(cur < 0);
+        if (head >= ntask) {
+            if (more) {
+                ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, none, ent));
+                head = 0;
+                more = __ballot(ent != 0) != 0;
+            } else if (idle == ~0ull) {
+                break;
+            }
+        }
+        if (idle != 0 && head < ntask) {
+            const uint32_t j = head + lanes_below(idle);
+            const bool take = cur < 0 && j < ntask;
+            const uint32_t t = q[take ? j : 0];
+            cur = take ? (int)(t & kQIdx) : cur;
+            code = take ? ((t >> kQByte) & 15u) : code;
+            ring = take ? (int)(t >> kQRing) : ring;
+            steps = take ? 0 : steps;
+            const uint32_t nidle = (uint32_t)__popcll(idle);
+            head = (ntask - head < nidle) ? ntask : head + nidle;
+        }
+        const bool act = cur >= 0;
+        const uint32_t sel = act ? code : 12u;
+        const int ni = (act ? cur : 128) + (int)__builtin_amdgcn_perm(lut_hi, lut_lo, 0x0C0C0C00u | sel) - 128;
+        const uint32_t nk = cb8[ni] & 15u;
+        ++steps;
+        const bool stop = nk >= (uint32_t)kNoFlow || steps > max_steps;
+        const uint16_t v = steps > max_steps ? kLlCycle : (nk == kFrameTile ? (uint16_t)cur : kLlTerm);
+        ll[(act && stop) ? ring : ll_dummy] = v;
+        cur = (act && !stop) ? ni : -1;
+        code = nk;
+    }
 }
 
 // Upstream walks for the adjoint, local part: lambda_loc(d) = g(d) +
@@ -983,10 +1070,18 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
     __syncthreads();
 
     uint32_t *dummy = reinterpret_cast<uint32_t *>(lds8 + L.dummy);
-    int visited = fwd_walks<VT, PASS == 1>(Tl, lds8, cb8, cbw, avp, dummy, q, L.qcap, St.src, St.entry,
-                                           ll, Tl.P);
+    // unit weights (uint32 counts): every seed is 1 in pass 1, and 1 plus the
+    // resolved inflow on the perimeter in pass 2
+    constexpr int kSeed = (std::is_same<T, uint32_t>::value && PASS == 1) ? 1 : 0;
+    int visited = fwd_walks<VT, false, kSeed>(Tl, lds8, cb8, cbw, avp, dummy, q, L.qcap, St.src, 0ull,
+                                              St.noflow, ll, Tl.P);
     if (wave_sum(visited) != wave_sum(__popcll(St.valid)) && lane == 0) set_status(status, kStatusCycle);
     __syncthreads();
+    // Algorithm 2's links of the entries (NoFlow entries keep kLlTerm)
+    if constexpr (PASS == 1) {
+        link_walks(Tl, cb8, q, L.qcap, St.entry & ~St.noflow, ll, Tl.P);
+        __syncthreads();
+    }
 
     if constexpr (PASS == 2) {
         rows_out(Tl, g, avp, St.valid, out);
@@ -1154,7 +1249,7 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
                             ext, out, status, lds8);
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 3)
 adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
          uint16_t *__restrict__ link, float *__restrict__ Sg, float *__restrict__ out,
          uint8_t *__restrict__ root8, uint32_t *status)
@@ -1194,7 +1289,7 @@ fwd_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ ti
                                           indeg, cnt, acc, ext, D.acc, status, lds8);
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 3)
 adj_walk_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ tile_dem,
                uint32_t t_begin, uint32_t t_end, uint16_t *__restrict__ link,
                float *__restrict__ Sg, uint32_t *status)
