@@ -39,6 +39,8 @@ constexpr int kW = 64;          // max tile width (columns)
 constexpr int kH = 64;          // max tile height (rows) = lanes
 constexpr int kWords = kW / 4;  // code words per row
 
+constexpr int kRingPerLane = 4;  // ring cells per lane: 2 (64 + 64) - 4 <= 4 x 64
+
 constexpr uint32_t kFrameTile = 0x0Eu;  // frame cell inside the raster (another tile)
 constexpr uint32_t kFrameOut = 0x0Fu;   // frame cell outside the raster
 
@@ -1059,10 +1061,21 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
     }
     if constexpr (PASS == 2) {
         __syncthreads();
-        for (int p = lane; p < Tl.P; p += 64) {
-            int qr, qc;
-            ring_cell(p, Tl.h, Tl.w, qr, qc);
-            avp[cidx(Tl, qr, qc)] += (VT)ext[Tl.base + p];
+        // all of a lane's loads first (a ring has at most 4 x 64 cells)
+        E e[kRingPerLane];
+#pragma unroll
+        for (int k = 0; k < kRingPerLane; ++k) {
+            const int p = lane + 64 * k;
+            e[k] = p < Tl.P ? ext[Tl.base + p] : (E)0;
+        }
+#pragma unroll
+        for (int k = 0; k < kRingPerLane; ++k) {
+            const int p = lane + 64 * k;
+            if (p < Tl.P) {
+                int qr, qc;
+                ring_cell(p, Tl.h, Tl.w, qr, qc);
+                avp[cidx(Tl, qr, qc)] += (VT)e[k];
+            }
         }
     } else {
         for (int p = lane; p < Tl.P; p += 64) ll[p] = kLlTerm;
@@ -1135,12 +1148,25 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
     // exits: perimeter cells whose flow leaves the tile into the raster
     if (lane < 8) exitbits[lane] = 0;
     __syncthreads();
-    for (int p = lane; p < Tl.P; p += 64) {
+    uint32_t codes[kRingPerLane];
+#pragma unroll
+    for (int k = 0; k < kRingPerLane; ++k) {
+        const int p = lane + 64 * k;
+        codes[k] = kNoFlow;
+        if (p < Tl.P) {
+            int qr, qc;
+            ring_cell(p, Tl.h, Tl.w, qr, qc);
+            codes[k] = dirs[(Tl.r0 + qr) * g.cols + Tl.c0 + qc];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kRingPerLane; ++k) {
+        const int p = lane + 64 * k;
+        const uint32_t kc = codes[k];
+        if (p >= Tl.P || kc >= (uint32_t)kNoFlow) continue;
         int qr, qc;
         ring_cell(p, Tl.h, Tl.w, qr, qc);
-        const uint32_t k = dirs[(Tl.r0 + qr) * g.cols + Tl.c0 + qc];
-        if (k >= (uint32_t)kNoFlow) continue;
-        const int nr = qr + dir_dr(k), nc = qc + dir_dc(k);
+        const int nr = qr + dir_dr(kc), nc = qc + dir_dc(kc);
         const int64_t gr = Tl.r0 + nr, gc = Tl.c0 + nc;
         const bool out_tile = nr < 0 || nr >= Tl.h || nc < 0 || nc >= Tl.w;
         if (out_tile && gr >= 0 && gr < g.rows && gc >= 0 && gc < g.cols)
@@ -1182,9 +1208,20 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
     Tl.base += node0;
     const int lane = lane_id();
     // mu is indexed by the exits' dense numbers; labels name exits only
-    for (int p = lane; p < Tl.P; p += 64) {
-        const uint32_t c = cmap[Tl.base + p];
-        mu_l[p] = c != kNone ? __uint_as_float((uint32_t)(mu[c] >> 32)) : 0.0f;
+    uint32_t cm[kRingPerLane];
+#pragma unroll
+    for (int k = 0; k < kRingPerLane; ++k) {
+        const int p = lane + 64 * k;
+        cm[k] = p < Tl.P ? cmap[Tl.base + p] : kNone;
+    }
+    float m[kRingPerLane];
+#pragma unroll
+    for (int k = 0; k < kRingPerLane; ++k)
+        m[k] = cm[k] != kNone ? __uint_as_float((uint32_t)(mu[cm[k]] >> 32)) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kRingPerLane; ++k) {
+        const int p = lane + 64 * k;
+        if (p < Tl.P) mu_l[p] = m[k];
     }
     __syncthreads();
     if (rows_vec(Tl, g, out) && ((reinterpret_cast<uintptr_t>(root8) & 3) == 0)) {
