@@ -911,33 +911,55 @@ __device__ inline bool rows_vec(const wk::WTile &Tl, const Geo &g, const void *p
            ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
 }
 
-template <typename T, int HALVES = 1>
+// Vector path: the tile as h x w/4 groups of 4 cells; group k of a lane is
+// lane + 64 k (row gi / (w/4) by a scaled reciprocal, exact for h <= 64 and
+// w/4 <= 16), so no lane idles when w < 64.
+struct RowGroups {
+    int ncg, ngr;
+    uint32_t inv;
+};
+
+__device__ inline RowGroups row_groups(const wk::WTile &Tl)
+{
+    RowGroups G;
+    G.ncg = Tl.w >> 2;
+    G.ngr = Tl.h * G.ncg;
+    G.inv = (65536u + (uint32_t)G.ncg - 1u) / (uint32_t)(G.ncg > 0 ? G.ncg : 1);
+    return G;
+}
+
+__device__ inline void group_rc(const RowGroups &G, int gi, int &r, int &c)
+{
+    r = (int)(((uint32_t)gi * G.inv) >> 16);
+    c = 4 * (gi - r * G.ncg);
+}
+
+// (Loads by 16-column quarters of 4 rows: lane l takes columns 4 (l % 16)
+// .. + 3 of rows l / 16 + 4 i, which keeps fewer addresses live than the
+// group order.)
+template <typename T>
 __device__ inline void rows_in(const wk::WTile &Tl, const Geo &g, T *avp, const T *__restrict__ src)
 {
     const int lane = wk::lane_id();
     if (rows_vec(Tl, g, src)) {
         const int c = 4 * (lane & 15), rq = lane >> 4;
-        constexpr int K = 16 / HALVES;
+        uint4 v[16];
 #pragma unroll
-        for (int half = 0; half < HALVES; ++half) {
-        uint4 v[K];
-#pragma unroll
-        for (int i0 = 0; i0 < K; ++i0) {
-            const int r = rq + 4 * (half * K + i0);
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
             if (r < Tl.h && c < Tl.w)
-                v[i0] = *reinterpret_cast<const uint4 *>(src + (Tl.r0 + r) * g.cols + Tl.c0 + c);
+                v[i] = *reinterpret_cast<const uint4 *>(src + (Tl.r0 + r) * g.cols + Tl.c0 + c);
         }
 #pragma unroll
-        for (int i0 = 0; i0 < K; ++i0) {
-            const int r = rq + 4 * (half * K + i0);
+        for (int i = 0; i < 16; ++i) {
+            const int r = rq + 4 * i;
             if (r < Tl.h && c < Tl.w) {
                 T *d = avp + wk::cidx(Tl, r, c);
-                d[0] = __builtin_bit_cast(T, v[i0].x);
-                d[1] = __builtin_bit_cast(T, v[i0].y);
-                d[2] = __builtin_bit_cast(T, v[i0].z);
-                d[3] = __builtin_bit_cast(T, v[i0].w);
+                d[0] = __builtin_bit_cast(T, v[i].x);
+                d[1] = __builtin_bit_cast(T, v[i].y);
+                d[2] = __builtin_bit_cast(T, v[i].z);
+                d[3] = __builtin_bit_cast(T, v[i].w);
             }
-        }
         }
         return;
     }
@@ -947,47 +969,52 @@ __device__ inline void rows_in(const wk::WTile &Tl, const Geo &g, T *avp, const 
     for (int r = 0; r < Tl.h; ++r) avp[wk::cidx(Tl, r, c)] = src[(Tl.r0 + r) * g.cols + Tl.c0 + c];
 }
 
+// Every value slot of the tile's rows (frame columns included) to v, with
+// 16-byte LDS stores over the whole value area.
 template <typename T>
 __device__ inline void rows_fill(const wk::WTile &Tl, T *avp, T v)
 {
-    const int c = wk::lane_id();
-    if (c >= Tl.w) return;
-    for (int r = 0; r < Tl.h; ++r) avp[wk::cidx(Tl, r, c)] = v;
+    uint32_t w;
+    if constexpr (sizeof(T) == 2) w = (uint32_t)__builtin_bit_cast(uint16_t, v) * 0x00010001u;
+    else w = __builtin_bit_cast(uint32_t, v);
+    uint4 *p = reinterpret_cast<uint4 *>(avp + Tl.S);  // 16-byte aligned (layout)
+    const int n16 = (Tl.h * Tl.S * (int)sizeof(T) + 15) >> 4;
+    for (int i = wk::lane_id(); i < n16; i += 64) p[i] = make_uint4(w, w, w, w);
 }
 
 // out = avp for data cells, 0 for NoData (valid: this lane's row mask)
-template <typename T, int HALVES = 1>
+template <typename T>
 __device__ inline void rows_out(const wk::WTile &Tl, const Geo &g, const T *avp, uint64_t valid, T *out)
 {
     const int lane = wk::lane_id();
     const uint32_t vlo = (uint32_t)valid, vhi = (uint32_t)(valid >> 32);
     if (rows_vec(Tl, g, out)) {
-        const int c = 4 * (lane & 15), rq = lane >> 4;
-        constexpr int K = 16 / HALVES;
+        const RowGroups G = row_groups(Tl);
+        uint4 v[16];
 #pragma unroll
-        for (int half = 0; half < HALVES; ++half) {
-        uint4 v[K];
-#pragma unroll
-        for (int i0 = 0; i0 < K; ++i0) {
-            const int i = half * K + i0;
-            const int r = rq + 4 * i;
+        for (int k = 0; k < 16; ++k) {
+            const int gi = lane + 64 * k;
+            int r, c;
+            group_rc(G, gi, r, c);
             const uint32_t lo = (uint32_t)__shfl((int)vlo, r & 63, 64);
             const uint32_t hi = (uint32_t)__shfl((int)vhi, r & 63, 64);
             const uint32_t bits = (c < 32 ? lo >> c : hi >> (c - 32)) & 15u;
-            if (r < Tl.h && c < Tl.w) {
+            if (gi < G.ngr) {
                 const T *s = avp + wk::cidx(Tl, r, c);
-                v[i0].x = (bits & 1u) ? __builtin_bit_cast(uint32_t, s[0]) : 0u;
-                v[i0].y = (bits & 2u) ? __builtin_bit_cast(uint32_t, s[1]) : 0u;
-                v[i0].z = (bits & 4u) ? __builtin_bit_cast(uint32_t, s[2]) : 0u;
-                v[i0].w = (bits & 8u) ? __builtin_bit_cast(uint32_t, s[3]) : 0u;
+                v[k].x = (bits & 1u) ? __builtin_bit_cast(uint32_t, s[0]) : 0u;
+                v[k].y = (bits & 2u) ? __builtin_bit_cast(uint32_t, s[1]) : 0u;
+                v[k].z = (bits & 4u) ? __builtin_bit_cast(uint32_t, s[2]) : 0u;
+                v[k].w = (bits & 8u) ? __builtin_bit_cast(uint32_t, s[3]) : 0u;
             }
         }
 #pragma unroll
-        for (int i0 = 0; i0 < K; ++i0) {
-            const int r = rq + 4 * (half * K + i0);
-            if (r < Tl.h && c < Tl.w)
-                *reinterpret_cast<uint4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + c) = v[i0];
-        }
+        for (int k = 0; k < 16; ++k) {
+            const int gi = lane + 64 * k;
+            if (gi < G.ngr) {
+                int r, c;
+                group_rc(G, gi, r, c);
+                *reinterpret_cast<uint4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + c) = v[k];
+            }
         }
         return;
     }
@@ -1207,6 +1234,25 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
     WTile Tl = wtile_of(g, t);
     Tl.base += node0;
     const int lane = lane_id();
+    const bool vec = rows_vec(Tl, g, out) && ((reinterpret_cast<uintptr_t>(root8) & 3) == 0);
+    // vector path: the tile as h x w/4 groups of 4 cells, group k of a lane
+    // = lane + 64 k; every load is issued before the exit sums are fetched
+    const int ncg = Tl.w >> 2, ngr = Tl.h * ncg;
+    const uint32_t inv = (65536u + (uint32_t)ncg - 1u) / (uint32_t)(ncg > 0 ? ncg : 1);
+    float4 v[16];
+    uint32_t lb[16];
+    if (vec) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int gi = lane + 64 * k;
+            if (gi < ngr) {
+                const int r = (int)(((uint32_t)gi * inv) >> 16), cg = gi - r * ncg;
+                const int64_t o = (Tl.r0 + r) * g.cols + Tl.c0 + 4 * cg;
+                v[k] = *reinterpret_cast<const float4 *>(out + o);
+                lb[k] = *reinterpret_cast<const uint32_t *>(root8 + o);
+            }
+        }
+    }
     // mu is indexed by the exits' dense numbers; labels name exits only
     uint32_t cm[kRingPerLane];
 #pragma unroll
@@ -1224,31 +1270,20 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
         if (p < Tl.P) mu_l[p] = m[k];
     }
     __syncthreads();
-    if (rows_vec(Tl, g, out) && ((reinterpret_cast<uintptr_t>(root8) & 3) == 0)) {
-        const int c = 4 * (lane & 15), rq = lane >> 4;
-        float4 v[16];
-        uint32_t lb[16];
+    if (vec) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = rq + 4 * i;
-            if (r < Tl.h && c < Tl.w) {
-                const int64_t o = (Tl.r0 + r) * g.cols + Tl.c0 + c;
-                v[i] = *reinterpret_cast<const float4 *>(out + o);
-                lb[i] = *reinterpret_cast<const uint32_t *>(root8 + o);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = rq + 4 * i;
-            if (r < Tl.h && c < Tl.w) {
-                const uint32_t l0 = lb[i] & 0xFFu, l1 = (lb[i] >> 8) & 0xFFu;
-                const uint32_t l2 = (lb[i] >> 16) & 0xFFu, l3 = lb[i] >> 24;
-                float4 x = v[i];
+        for (int k = 0; k < 16; ++k) {
+            const int gi = lane + 64 * k;
+            if (gi < ngr) {
+                const int r = (int)(((uint32_t)gi * inv) >> 16), cg = gi - r * ncg;
+                const uint32_t l0 = lb[k] & 0xFFu, l1 = (lb[k] >> 8) & 0xFFu;
+                const uint32_t l2 = (lb[k] >> 16) & 0xFFu, l3 = lb[k] >> 24;
+                float4 x = v[k];
                 if (l0 < kLabelTerm) x.x += mu_l[l0];
                 if (l1 < kLabelTerm) x.y += mu_l[l1];
                 if (l2 < kLabelTerm) x.z += mu_l[l2];
                 if (l3 < kLabelTerm) x.w += mu_l[l3];
-                *reinterpret_cast<float4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + c) = x;
+                *reinterpret_cast<float4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + 4 * cg) = x;
             }
         }
         return;
