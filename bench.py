@@ -38,7 +38,7 @@ KERNEL_BYTES_PER_CELL = {
     "d8_directions": 5.0,
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
-SWEEP_TILES = ((64, 64), (64, 56), (56, 64), (64, 48), (48, 64), (32, 64))
+SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (56, 48), (48, 64), (48, 48), (32, 64))
 
 
 KERNEL_NAMES = {  # timing label -> kernel symbol prefix in profiler output

@@ -464,8 +464,7 @@ constexpr uint16_t kLlCycle = 0xFFFE;
 // 0.. of the queue, at most `cap`, and clears the bits it wrote; returns how
 // many it wrote (wave-uniform).
 __device__ inline uint32_t fill_queue(uint32_t *q, uint32_t cap, const WTile &Tl, const uint8_t *cb8,
-                                      uint32_t byte_mask, uint64_t &m0, uint64_t &m1,
-                                      bool ring_flag = false)
+                                      uint32_t byte_mask, uint64_t &m0, uint64_t &m1)
 {
     const int lane = lane_id();
     uint32_t n = (uint32_t)(__popcll(m0) + __popcll(m1));
@@ -478,16 +477,11 @@ __device__ inline uint32_t fill_queue(uint32_t *q, uint32_t cap, const WTile &Tl
     uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     uint32_t pos = incl - n;
     const int rowbase = (lane + 1) * Tl.S + 1;
-    // ring_flag: plain walks from a perimeter cell carry kQLink (their seed
-    // may hold a cross-tile inflow)
-    const uint64_t ring = !ring_flag ? 0ull
-                          : (lane == 0 || lane == Tl.h - 1) ? ~0ull
-                                                           : (1ull | (1ull << (Tl.w - 1)));
     while (m0 != 0 && pos < cap) {
         int c = __ffsll((unsigned long long)m0) - 1;
         m0 &= m0 - 1ull;
         const int idx = rowbase + c;
-        q[pos++] = (uint32_t)idx | ((cb8[idx] & byte_mask) << kQByte) | (((ring >> c) & 1ull) ? kQLink : 0u);
+        q[pos++] = (uint32_t)idx | ((cb8[idx] & byte_mask) << kQByte);
     }
     while (m1 != 0 && pos < cap) {
         int c = __ffsll((unsigned long long)m1) - 1;
@@ -518,9 +512,9 @@ __device__ inline uint16_t link_of(const WTile &Tl, uint16_t v, uint32_t *status
 
 // ---------------------------------------------------------------- walks ---
 
-// Forward walks from every source (and, when LINKS, link walks from every
-// entry, in the same loop).  avp[idx] holds each cell's seed and receives
-// its accumulation.  Returns the number of cells this lane finished.
+// Forward walks (Algorithm 1's accumulation in Kahn order) from every
+// source.  avp[idx] holds each cell's seed and receives its accumulation.
+// Returns the number of cells this lane finished.
 //
 // A walk ends on reaching a cell whose flow goes nowhere further inside the
 // tile (NoFlow, NoData, the frame), so a walker's cell always has a code
@@ -528,44 +522,40 @@ __device__ inline uint16_t link_of(const WTile &Tl, uint16_t v, uint32_t *status
 // one v_perm (offset + 128 per code), and NoFlow sources are finished without
 // a walk.  The claim and the plain step take no branches: an idle lane steps
 // with selector 12 (byte 0) from index 128, i.e. to cell 0 of the frame (its
-// step ends at once), and a store that does not apply goes to the lane's own
-// dummy word.  Only the rare confluence step branches.  Unit seeds (16-bit
-// values) are known to be 1, so a claim reads only its queue entry.
-// SEED: 0 = seeds are read from avp, 1 = every seed is 1, 2 = seeds are 1
-// except on the perimeter (queue entries of perimeter cells carry kQLink).
-template <typename VT, bool LINKS, int SEED>
+// step ends at once), and a store that does not apply goes to the value slot
+// of a frame column (row lane % h, column -1), which nothing reads.  Only the
+// confluence step branches.  SEED: 0 = seeds are read from avp at a claim
+// (the read completes with the step's reads), 1 = every seed is 1.
+template <typename VT, int SEED>
 __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, uint32_t *cbw, VT *avp,
-                                uint32_t *dummy, uint32_t *q, uint32_t qcap, uint64_t src,
-                                uint64_t ent, uint64_t noflow, uint16_t *ll, int ll_dummy)
+                                uint32_t *q, uint32_t qcap, uint64_t src, uint64_t noflow)
 {
     using T = typename Acc<VT>::type;
-    static_assert(SEED != 2 || !LINKS, "perimeter seed flags use the link bit");
     const int S = Tl.S;
     const int lane = lane_id();
-    VT *mine = reinterpret_cast<VT *>(dummy + lane);
+    VT *mine = avp + (lane % Tl.h + 1) * S;
     // offset + 128 of directions 0..7: (dr, dc) = NW N NE W E SW S SE
     const uint32_t s8 = (uint32_t)S;
     const uint32_t lut_lo = (128u - s8 - 1u) | ((128u - s8) << 8) | ((128u - s8 + 1u) << 16) | (127u << 24);
     const uint32_t lut_hi = 129u | ((128u + s8 - 1u) << 8) | ((128u + s8) << 16) | ((128u + s8 + 1u) << 24);
-    // NoFlow sources are complete as they are; NoFlow entries keep link TERM
+    // NoFlow sources are complete as they are
     int visited = __popcll(src & noflow);
     src &= ~noflow;
-    ent &= ~noflow;
-    uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent, SEED == 2));
+    uint64_t none = 0;
+    uint32_t ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, none));
     uint32_t head = 0;
-    bool more = __ballot(src != 0 || ent != 0) != 0;
-    int cur = -1, steps = 0;
-    uint32_t code = 12u, info = 0;
+    bool more = __ballot(src != 0) != 0;
+    int cur = -1;
+    uint32_t code = 12u;
     T a = (T)0;
-    const int max_steps = Tl.h * Tl.w;
     for (;;) {
         const uint64_t idle = __ballot(cur < 0);
         if (head >= ntask) {
             if (more) {
                 // the queue has been handed out completely: refill it
-                ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, ent, SEED == 2));
+                ntask = __builtin_amdgcn_readfirstlane(fill_queue(q, qcap, Tl, cb8, 15u, src, none));
                 head = 0;
-                more = __ballot(src != 0 || ent != 0) != 0;
+                more = __ballot(src != 0) != 0;
             } else if (idle == ~0ull) {
                 break;
             }
@@ -578,16 +568,10 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
             const uint32_t t = q[take ? j : 0];
             const int nc = (int)(t & kQIdx);
             if constexpr (SEED == 0) a0 = (T)avp[take ? nc : S + 1];
-            if constexpr (SEED == 2) {
-                const bool rd = take && (t & kQLink);
-                if (__ballot(rd) != 0) a0 = rd ? (T)avp[nc] : (T)1;
-            }
             cur = take ? nc : cur;
             code = take ? ((t >> kQByte) & 15u) : code;
-            info = take ? t : info;
-            steps = take ? 0 : steps;
             took = take;
-            visited += (take && !(LINKS && (t & kQLink))) ? 1 : 0;
+            visited += take ? 1 : 0;
             const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (ntask - head < nidle) ? ntask : head + nidle;
         }
@@ -598,15 +582,10 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
         const uint32_t nb = cb8[ni];
         T sv = (T)avp[ni];
         keep_read(sv);
-        // a new walk's seed: its read completes with the step's reads
         keep_read(a0);
         a = took ? a0 : a;
         const uint32_t nk = nb & 15u;
-        const bool link = LINKS && (info & kQLink);
-        if (LINKS) ++steps;
-        // a link walk longer than the tile has cells runs into a cycle
-        const bool end = nk >= (uint32_t)kNoData || (LINKS && link && steps > max_steps);
-        const bool fw = act && !end && !link;
+        const bool fw = act && nk < (uint32_t)kNoData;
         const bool plain = fw && nb < 16u;
         const T ap = a + sv;
         *(plain ? &avp[ni] : mine) = (VT)ap;
@@ -623,12 +602,7 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
         a = plain ? ap : a;
         visited += (plain || last) ? 1 : 0;
         // the walk goes on from the next cell only if its flow stays in the tile
-        const bool stop = end || nk >= (uint32_t)kNoFlow;
-        if (LINKS) {
-            const uint16_t v = steps > max_steps ? kLlCycle : (nk == kFrameTile ? (uint16_t)cur : kLlTerm);
-            ll[(act && link && stop) ? (int)(info >> kQRing) : ll_dummy] = v;
-        }
-        cur = (act && !stop && (plain || last || link)) ? ni : -1;
+        cur = ((plain || last) && nk < (uint32_t)kNoFlow) ? ni : -1;
         code = nk;
     }
     return visited;
@@ -871,7 +845,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
 // value reads of frame rows land in the cell bytes (before) or the queue
 // (after), both at least 4 (S + 1) bytes long.
 struct WLayout {
-    int av, q, dummy, tail, total;
+    int av, q, tail, total;
     uint32_t qcap;
 };
 
@@ -889,9 +863,11 @@ __host__ __device__ inline WLayout walk_layout(int th, int tw, int kind, int vby
     if (cb < 4 * (S + 1)) cb = 4 * (S + 1);
     L.av = (cb + 15) & ~15;
     L.q = L.av + ((th * S * vbytes + 15) & ~15);
-    L.qcap = 256u;  // entries <= ring size <= 252 fit in one fill
-    L.dummy = L.q + (int)L.qcap * 4;  // one word per lane for stores that do not apply
-    L.tail = L.dummy + (kind == kWalkAdj1 ? 0 : 64 * 4);
+    // queue entries: the adjoint's queue also takes side donors as walks
+    // branch (256 keep overflow rare); forward queues hold start cells and
+    // are refilled from the lanes' masks when empty
+    L.qcap = kind == kWalkAdj1 ? 256u : 128u;
+    L.tail = L.q + (int)L.qcap * 4;
     int tail = 0;
     if (kind == kWalkFwd1) tail = (ring_size(th, tw) * 2 + 2 + 15) & ~15;  // links + a spare slot
     if (kind == kWalkAdj1) tail = 64 * 8 + 32;  // pending bitmap, exit bitmap (adjoint)
@@ -1109,12 +1085,10 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
     }
     __syncthreads();
 
-    uint32_t *dummy = reinterpret_cast<uint32_t *>(lds8 + L.dummy);
     // unit weights (uint32 counts): every seed is 1 in pass 1, and 1 plus the
     // resolved inflow on the perimeter in pass 2
     constexpr int kSeed = (std::is_same<T, uint32_t>::value && PASS == 1) ? 1 : 0;
-    int visited = fwd_walks<VT, false, kSeed>(Tl, lds8, cb8, cbw, avp, dummy, q, L.qcap, St.src, 0ull,
-                                              St.noflow, ll, Tl.P);
+    int visited = fwd_walks<VT, kSeed>(Tl, lds8, cb8, cbw, avp, q, L.qcap, St.src, St.noflow);
     if (wave_sum(visited) != wave_sum(__popcll(St.valid)) && lane == 0) set_status(status, kStatusCycle);
     __syncthreads();
     // Algorithm 2's links of the entries (NoFlow entries keep kLlTerm)
