@@ -150,14 +150,15 @@ int jump_exits(hipStream_t st, int64_t N, const uint16_t *link, const uint32_t *
     D8_LAUNCH(JNAME("adj_compact"), st,
               (adj_compact_count<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum)));
     D8_LAUNCH(JNAME("adj_compact"), st, (adj_compact_scan<<<1, 1024, 0, st>>>(ncb, bsum, nexit)));
+    // inv (dense index -> node) lives in jw[1] until round 0 overwrites it
+    uint32_t *inv = reinterpret_cast<uint32_t *>(jw[1]);
+    const unsigned jb = std::min<unsigned>(blocks_for(N, 2 * kNodeBlock), 4096u);
     D8_LAUNCH(JNAME("adj_compact"), st,
-              (adj_compact_map<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum, cmap)));
+              (adj_compact_map<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum, cmap, inv)));
     D8_LAUNCH(JNAME("adj_jump_init"), st,
-              (adj_jump_init<<<blocks_for(N, kNodeBlock), kNodeBlock, 0, st>>>(N, link, entry, succ, S,
-                                                                               cmap, jw[0])));
+              (adj_jump_init<<<jb, kNodeBlock, 0, st>>>(nexit, inv, entry, succ, S, cmap, jw[0])));
     int rounds = 1;
     while (((int64_t)1 << (rounds - 1)) <= N) ++rounds;
-    const unsigned jb = std::min<unsigned>(blocks_for(N, 2 * kNodeBlock), 4096u);
     for (int r = 0; r < rounds; ++r)
         D8_LAUNCH(JNAME("adj_jump_round"), st,
                   (adj_jump_round<<<jb, kNodeBlock, 0, st>>>(nexit, jw[r & 1], jw[(r + 1) & 1], jstate, r)));

@@ -443,10 +443,11 @@ adj_compact_scan(int64_t nblocks, uint32_t *bsum, uint32_t *nexit)
     if (threadIdx.x == 0) *nexit = carry_s;
 }
 
-// cmap[n] = the dense index of exit n, kNone for other nodes.
+// cmap[n] = the dense index of exit n, kNone for other nodes; inv[c] = the
+// node of dense index c.
 __global__ void __launch_bounds__(kCompactBlock)
 adj_compact_map(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_t *__restrict__ bsum,
-                uint32_t *__restrict__ cmap)
+                uint32_t *__restrict__ cmap, uint32_t *__restrict__ inv)
 {
     const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
     const uint32_t m = exit_bits16(link, nnodes, n0);
@@ -455,8 +456,10 @@ adj_compact_map(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_
     uint32_t out[kCompactPer];
 #pragma unroll
     for (int j = 0; j < kCompactPer; ++j) {
-        out[j] = (m >> j) & 1u ? idx : kNone;
-        idx += (m >> j) & 1u;
+        const bool ex = (m >> j) & 1u;
+        out[j] = ex ? idx : kNone;
+        if (ex) inv[idx] = (uint32_t)(n0 + j);
+        idx += ex ? 1u : 0u;
     }
     if (n0 + kCompactPer <= nnodes && (reinterpret_cast<uintptr_t>(cmap + n0) & 15) == 0) {
         uint4 *p = reinterpret_cast<uint4 *>(cmap + n0);
@@ -469,18 +472,22 @@ adj_compact_map(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_
     }
 }
 
-// Initial words of the exits: pointer = the dense index of the successor
-// (kNone at a root), val = S(entry).  Round 0 writes every word of the other
-// buffer, so only one is initialised.
-__global__ void adj_jump_init(int64_t nnodes, const uint16_t *__restrict__ link,
-                              const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
-                              const float *__restrict__ S, const uint32_t *__restrict__ cmap,
-                              unsigned long long *__restrict__ buf0)
+// Initial words of the exits (a fixed grid strides over them): pointer = the
+// dense index of the successor (kNone at a root), val = S(entry).  Round 0
+// writes every word of the other buffer, which holds inv until then.
+__global__ void __launch_bounds__(256)
+adj_jump_init(const uint32_t *__restrict__ nexit, const uint32_t *__restrict__ inv,
+              const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
+              const float *__restrict__ S, const uint32_t *__restrict__ cmap,
+              unsigned long long *__restrict__ buf0)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nnodes || link[id] != kLinkExt) return;
-    const uint32_t n = entry[id], s = succ[id];
-    buf0[cmap[id]] = jump_word(s != kNone ? cmap[s] : kNone, n != kNone ? S[n] : 0.0f);
+    const int64_t E = *nexit;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += stride) {
+        const uint32_t id = inv[i];
+        const uint32_t n = entry[id], s = succ[id];
+        buf0[i] = jump_word(s != kNone ? cmap[s] : kNone, n != kNone ? S[n] : 0.0f);
+    }
 }
 
 // One synchronous round r over the exits (their count is *nexit): reads
