@@ -154,16 +154,21 @@ d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t row
     const int64_t r0 = strip * kD8Rows;
     const int64_t r1 = rows - r0 < kD8Rows ? rows : r0 + kD8Rows;
     const float nodata_ = nodata;
-    float4 q;
-    float hl, hr;
+    float4 q, q2;
+    float hl, hr, hl2, hr2;
     d8_row_load<VEC>(dem, rows, cols, r0 - 1, c0, q, hl, hr);
     D8Row up = d8_row_finish(q, hl, hr, nodata_);
     d8_row_load<VEC>(dem, rows, cols, r0, c0, q, hl, hr);
     D8Row mid = d8_row_finish(q, hl, hr, nodata_);
+    // two rows in flight: q (row r + 1) and q2 (row r + 2)
     d8_row_load<VEC>(dem, rows, cols, r0 + 1, c0, q, hl, hr);
+    d8_row_load<VEC>(dem, rows, cols, r0 + 2, c0, q2, hl2, hr2);
     for (int64_t r = r0; r < r1; ++r) {
         const D8Row dn = d8_row_finish(q, hl, hr, nodata_);
-        d8_row_load<VEC>(dem, rows, cols, r + 2, c0, q, hl, hr);  // in flight during the compare
+        q = q2;
+        hl = hl2;
+        hr = hr2;
+        d8_row_load<VEC>(dem, rows, cols, r + 3, c0, q2, hl2, hr2);  // in flight during two compares
         const uint32_t codes = d8_codes4(up, mid, dn);
         uint8_t *o = dirs + r * cols + c0;
         if constexpr (VEC) {
