@@ -139,9 +139,9 @@ inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block 
 // the convergence check.  bsum takes one word per 4096 nodes, cmap one per
 // node; the sums end in jw[jstate[0]] at the exits' dense numbers.  Returns
 // the number of rounds.
-int jump_exits(hipStream_t st, int64_t N, const uint16_t *link, const uint32_t *entry,
-               const uint32_t *succ, const float *S, uint32_t *bsum, uint32_t *cmap,
-               unsigned long long *const jw[2], uint32_t *jstate, uint32_t *status, bool batch)
+int jump_exits(hipStream_t st, int64_t N, const JumpGraph &G, const uint16_t *link, const float *S,
+               uint32_t *bsum, uint32_t *cmap, unsigned long long *const jw[2], uint32_t *jstate,
+               uint32_t *status, bool batch)
 {
     // timing labels are kept by pointer: literals only
 #define JNAME(s) (batch ? "batch_" s : s)
@@ -156,7 +156,7 @@ int jump_exits(hipStream_t st, int64_t N, const uint16_t *link, const uint32_t *
     D8_LAUNCH(JNAME("adj_compact"), st,
               (adj_compact_map<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum, cmap, inv)));
     D8_LAUNCH(JNAME("adj_jump_init"), st,
-              (adj_jump_init<<<jb, kNodeBlock, 0, st>>>(nexit, inv, entry, succ, S, cmap, jw[0])));
+              (adj_jump_init<<<jb, kNodeBlock, 0, st>>>(nexit, inv, G, link, S, cmap, jw[0])));
     int rounds = 1;
     while (((int64_t)1 << (rounds - 1)) <= N) ++rounds;
     for (int r = 0; r < rounds; ++r)
@@ -473,10 +473,9 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
     if (mode & D8_BATCH_ADJ) {
         reset_jump<<<1, 1, 0, st>>>(jstate);
         if (tiles(2, adj_walk_batch, "batch_adj_pass1", link, val32, status)) return D8_EHIP;
-        D8_LAUNCH("batch_graph_build", st,
-                  (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
-                                                                succ, nullptr)));
-        jump_exits(st, N, link, entry, succ, val32, indeg, cnt, jw, jstate, status, true);
+        // the exits' edges are found as their jump words are initialised
+        const JumpGraph G{nullptr, Geo{}, dems, ndem, chunk_dem};
+        jump_exits(st, N, G, link, val32, indeg, cnt, jw, jstate, status, true);
         D8_LAUNCH("batch_adj_pass2", st,
                   (adj_finish_batch<<<(unsigned)P.ntiles, 64, 0, st>>>(dems, tile_dem, (uint32_t)P.ntiles,
                                                                       cnt, jw[0], jw[1], jstate)));
@@ -609,8 +608,6 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     uint32_t *status = reinterpret_cast<uint32_t *>(w8 + L.status);
     uint32_t *jstate = reinterpret_cast<uint32_t *>(w8 + L.jstate);
     uint16_t *link = reinterpret_cast<uint16_t *>(w8 + L.link);
-    uint32_t *entry = reinterpret_cast<uint32_t *>(w8 + L.entry);
-    uint32_t *succ = reinterpret_cast<uint32_t *>(w8 + L.succ);
     float *S = reinterpret_cast<float *>(w8 + L.val32);
     unsigned long long *jw[2] = {reinterpret_cast<unsigned long long *>(w8 + L.acc64),
                                  reinterpret_cast<unsigned long long *>(w8 + L.ext64)};
@@ -622,17 +619,14 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1);
     begin_call();
     if (allow_lds(adj_walk, lds1)) return D8_EHIP;
-    unsigned nb = blocks_for(g.nnodes, kNodeBlock);
-
     init_state<<<1, 1, 0, st>>>(status, jstate);
     D8_LAUNCH("adj_pass1", st,
               (adj_walk<<<ntiles, thr, lds1, st>>>(dirs, grad_acc, g, link, S, grad_weights, root8,
                                                    status)));
-    D8_LAUNCH("graph_build", st,
-              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, nullptr)));
-    const int rounds = jump_exits(st, g.nnodes, link, entry, succ, S,
-                                  reinterpret_cast<uint32_t *>(w8 + L.indeg), cmap, jw, jstate, status,
-                                  false);
+    // the exits' edges are found as their jump words are initialised
+    const JumpGraph G{dirs, g, nullptr, 0, nullptr};
+    const int rounds = jump_exits(st, g.nnodes, G, link, S, reinterpret_cast<uint32_t *>(w8 + L.indeg),
+                                  cmap, jw, jstate, status, false);
     D8_LAUNCH("adj_pass2", st,
               (adj_finish<<<ntiles, thr, 0, st>>>(g, root8, cmap, jw[0], jw[1], jstate, grad_weights)));
     (void)rounds;

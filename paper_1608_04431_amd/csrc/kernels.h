@@ -2,21 +2,26 @@
 //
 // Forward (Eq. (1), alpha in {0,1}), the paper's three stages on one GPU:
 //   fwd_walk<1>       one wavefront per tile (walk.h): Algorithm 1's
-//                     accumulation and Algorithm 2's perimeter links; writes
-//                     one record (link, A_loc) per perimeter cell.
+//                     accumulation, then Algorithm 2's links of the entry
+//                     cells; one record (link, A_loc) per perimeter cell.
 //   graph_build       joins every FlowExternal perimeter cell to the perimeter
 //                     cell it flows into in the neighbouring tile (across an
-//                     edge or a corner) and to that cell's exit.
-//   resolve_fwd       accumulates the forest of exit cells and records each
-//                     perimeter cell's cross-tile inflow.
+//                     edge or a corner) and to that cell's exit; counts each
+//                     exit's children.
+//   resolve_fwd_*     accumulates the forest of exit cells and records each
+//                     perimeter cell's cross-tile inflow; resolve_check
+//                     reports exits whose children never all arrived.
 //   fwd_walk<2>       Algorithm 1 again per tile with the inflow added to the
 //                     receiving cell's own weight (EVICT), writes A.
 // Adjoint (lambda = (I-P)^-T g, not in the paper):
-//   adj_walk<1>       per tile: sum of g along each entry cell's in-tile
-//                     path and the same links;
-//   graph_build, adj_jump_*   downstream sums over the exit forest by pointer
-//                     jumping;
-//   adj_walk<2>       per tile: lambda for every cell by upstream walks in LDS.
+//   adj_walk          per tile: upstream walks give lambda_loc (the sum of g
+//                     along each cell's in-tile path) and each cell's root
+//                     label; records (link, S) per perimeter cell.
+//   adj_compact_*     dense numbers for the exits;
+//   adj_jump_*        each exit's edge (as graph_build finds it), then the
+//                     downstream sums over the exit forest by pointer jumping;
+//   adj_finish        lambda = lambda_loc + the sum of the cell's root exit.
+// D8 directions: d8_kernel.
 #pragma once
 #include "d8_common.h"
 #include "walk.h"
@@ -189,6 +194,32 @@ d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t row
 // (itself if it is FlowExternal, none if its path terminates).  indeg (when
 // given) counts each exit node's children in the exit forest; it is not
 // changed afterwards, so the resolve can tell leaves from inner nodes.
+// The edge of exit `id` (link kLinkExt) of a raster whose nodes start at
+// node0: e = the perimeter node its flow enters, s = that node's exit (or
+// kNone; e = kNone too when the flow enters NoData).
+__device__ inline void graph_edge(const uint8_t *__restrict__ dirs, const Geo &g, int64_t node0,
+                                  int64_t id, const uint16_t *__restrict__ link, uint32_t &e,
+                                  uint32_t &s)
+{
+    e = s = kNone;
+    int ty, tx, p, r, c;
+    node_tile(g, id, ty, tx, p);
+    ring_cell(p, tile_h(g, ty), tile_w(g, tx), r, c);
+    int64_t gr = (int64_t)ty * g.th + r, gc = (int64_t)tx * g.tw + c;
+    int k = dirs[gr * g.cols + gc];
+    int64_t nr = gr + dir_dr(k), nc = gc + dir_dc(k);
+    int uty = (int)(nr / g.th), utx = (int)(nc / g.tw);
+    int lr = (int)(nr - (int64_t)uty * g.th), lc = (int)(nc - (int64_t)utx * g.tw);
+    int64_t ub = node0 + node_base(g, uty, utx);
+    int q = ring_index(lr, lc, tile_h(g, uty), tile_w(g, utx));  // >= 0: borders a tile edge
+    int64_t n = ub + (q < 0 ? 0 : q);
+    uint16_t L = q < 0 ? kLinkNoData : link[n];
+    if (L != kLinkNoData) {
+        e = (uint32_t)n;
+        s = (L == kLinkExt) ? (uint32_t)n : (L == kLinkTerm ? kNone : (uint32_t)(ub + L));
+    }
+}
+
 __device__ inline void graph_node(const uint8_t *__restrict__ dirs, const Geo &g, int64_t node0,
                                   int64_t id, const uint16_t *__restrict__ link,
                                   uint32_t *__restrict__ entry, uint32_t *__restrict__ succ,
@@ -196,24 +227,7 @@ __device__ inline void graph_node(const uint8_t *__restrict__ dirs, const Geo &g
 {
     const int64_t gid = node0 + id;
     uint32_t e = kNone, s = kNone;
-    if (link[gid] == kLinkExt) {
-        int ty, tx, p, r, c;
-        node_tile(g, id, ty, tx, p);
-        ring_cell(p, tile_h(g, ty), tile_w(g, tx), r, c);
-        int64_t gr = (int64_t)ty * g.th + r, gc = (int64_t)tx * g.tw + c;
-        int k = dirs[gr * g.cols + gc];
-        int64_t nr = gr + dir_dr(k), nc = gc + dir_dc(k);
-        int uty = (int)(nr / g.th), utx = (int)(nc / g.tw);
-        int lr = (int)(nr - (int64_t)uty * g.th), lc = (int)(nc - (int64_t)utx * g.tw);
-        int64_t ub = node0 + node_base(g, uty, utx);
-        int q = ring_index(lr, lc, tile_h(g, uty), tile_w(g, utx));  // >= 0: borders a tile edge
-        int64_t n = ub + (q < 0 ? 0 : q);
-        uint16_t L = q < 0 ? kLinkNoData : link[n];
-        if (L != kLinkNoData) {
-            e = (uint32_t)n;
-            s = (L == kLinkExt) ? (uint32_t)n : (L == kLinkTerm ? kNone : (uint32_t)(ub + L));
-        }
-    }
+    if (link[gid] == kLinkExt) graph_edge(dirs, g, node0, id, link, e, s);
     entry[gid] = e;
     succ[gid] = s;
     if (indeg && s != kNone) atomicAdd(&indeg[s], 1u);
@@ -232,6 +246,14 @@ __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
 // found by stepping forward over the (few) rasters that start in the chunk.
 constexpr int kChunkShift = 12;
 
+__device__ inline int dem_of(const DemDesc *__restrict__ dems, int ndem,
+                             const uint32_t *__restrict__ chunk_dem, int64_t id)
+{
+    int d = (int)chunk_dem[id >> kChunkShift];
+    while (d + 1 < ndem && dems[d + 1].node0 <= id) ++d;
+    return d;
+}
+
 __global__ void graph_build_batch(const DemDesc *__restrict__ dems, int ndem,
                                   const uint32_t *__restrict__ chunk_dem, int64_t nnodes,
                                   const uint16_t *__restrict__ link, uint32_t *__restrict__ entry,
@@ -239,9 +261,7 @@ __global__ void graph_build_batch(const DemDesc *__restrict__ dems, int ndem,
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nnodes) return;
-    int d = (int)chunk_dem[id >> kChunkShift];
-    while (d + 1 < ndem && dems[d + 1].node0 <= id) ++d;
-    const DemDesc &D = dems[d];
+    const DemDesc &D = dems[dem_of(dems, ndem, chunk_dem, id)];
     graph_node(D.dirs, D.g, D.node0, id - D.node0, link, entry, succ, indeg);
 }
 
@@ -477,20 +497,36 @@ adj_compact_map(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_
     }
 }
 
-// Initial words of the exits (a fixed grid strides over them): pointer = the
-// dense index of the successor (kNone at a root), val = S(entry).  Round 0
-// writes every word of the other buffer, which holds inv until then.
+// Where the adjoint's exits find their edges: one raster (dems == nullptr)
+// or a batch.
+struct JumpGraph {
+    const uint8_t *dirs;
+    Geo g;
+    const DemDesc *dems;
+    int ndem;
+    const uint32_t *chunk_dem;
+};
+
+// Initial words of the exits (a fixed grid strides over them): each exit's
+// edge (as graph_build finds it), pointer = the dense index of the
+// successor (kNone at a root), val = S(entry).  Round 0 writes every word of
+// the other buffer, which holds inv until then.
 __global__ void __launch_bounds__(256)
-adj_jump_init(const uint32_t *__restrict__ nexit, const uint32_t *__restrict__ inv,
-              const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
-              const float *__restrict__ S, const uint32_t *__restrict__ cmap,
-              unsigned long long *__restrict__ buf0)
+adj_jump_init(const uint32_t *__restrict__ nexit, const uint32_t *__restrict__ inv, JumpGraph G,
+              const uint16_t *__restrict__ link, const float *__restrict__ S,
+              const uint32_t *__restrict__ cmap, unsigned long long *__restrict__ buf0)
 {
     const int64_t E = *nexit;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += stride) {
-        const uint32_t id = inv[i];
-        const uint32_t n = entry[id], s = succ[id];
+        const int64_t id = inv[i];
+        uint32_t n, s;
+        if (G.dems) {
+            const DemDesc &D = G.dems[dem_of(G.dems, G.ndem, G.chunk_dem, id)];
+            graph_edge(D.dirs, D.g, D.node0, id - D.node0, link, n, s);
+        } else {
+            graph_edge(G.dirs, G.g, 0, id, link, n, s);
+        }
         buf0[i] = jump_word(s != kNone ? cmap[s] : kNone, n != kNone ? S[n] : 0.0f);
     }
 }
