@@ -153,3 +153,28 @@ def batch_shapes(n: int = 2000, seed: int = 55, smin: int = 64, smax: int = 4096
         lam = max(16, int(round(max(rows, cols) / 8)))
         out.append((rows, cols, lam, 5000 + i, 6000 + i, 7000 + i))
     return out
+
+
+def sqrt2_blocks() -> np.ndarray:
+    """3 x 3k float32 raster of independent 3 x 3 blocks for the D8 slope
+    compare at its hardest: each block's centre is 0, its north neighbour
+    -dc and its north-east neighbour -dd, with dd within a few float32 ulps
+    of dc * sqrt(2) (and the other neighbours far higher), for drops dc from
+    subnormal to 1e38.  Input only: no direction is computed here."""
+    pairs = []
+    for dc in (1.0, 3.7e-3, 0.125, 7.0, 1e-29, 2e-30, 1e-40, 1e20, 9e36, 2e37, 1e38):
+        dc = np.float32(dc)
+        mid = np.float32(float(dc) * 2.0 ** 0.5)
+        dd = mid
+        for _ in range(6):
+            dd = np.nextafter(dd, np.float32(0))
+        for _ in range(13):
+            if np.isfinite(dd):
+                pairs.append((dc, dd))
+            dd = np.nextafter(dd, np.float32(np.inf))
+    z = np.full((3, 3 * len(pairs)), np.float32(1e30), dtype=np.float32)
+    for j, (dc, dd) in enumerate(pairs):
+        z[1, 3 * j + 1] = 0.0
+        z[0, 3 * j + 1] = -dc
+        z[0, 3 * j + 2] = -dd
+    return z

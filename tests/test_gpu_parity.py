@@ -109,6 +109,17 @@ def test_d8_directions_strips_blocks_and_alignment(d8m):
         assert int(obuf[0]) == 0 and (obuf[1 + z.size:] == 0).all()
 
 
+def test_d8_directions_near_sqrt2(d8m):
+    """The slope compare where the diagonal drop is within a few ulps of
+    sqrt(2) times the cardinal one (the kernel's float fast path must defer
+    to the exact compare there), per element and 4-aligned."""
+    z = synth.sqrt2_blocks()
+    np.testing.assert_array_equal(d8m.d8_directions(dev(z)).cpu().numpy(), oracle.d8(z))
+    zp = np.concatenate([z, np.full((3, 3), np.float32(1e30), np.float32)], axis=1)
+    assert zp.shape[1] % 4 == 0
+    np.testing.assert_array_equal(d8m.d8_directions(dev(zp)).cpu().numpy(), oracle.d8(zp))
+
+
 # ------------------------------------------------------------ hand fixtures --
 def test_golden_fixtures_u32(d8m):
     from conftest import GOLDEN_FILES, load_golden

@@ -340,6 +340,16 @@ def test_d8_random_floats_and_terrain():
     np.testing.assert_array_equal(oracle.d8(t), exact_d8(t))
 
 
+def test_d8_near_sqrt2_boundary():
+    # diagonal drops within a few ulps of sqrt(2) times the cardinal drop, for
+    # drops from subnormal to 1e38: the slope compare must be exact
+    z = synth.sqrt2_blocks()
+    got = oracle.d8(z)
+    np.testing.assert_array_equal(got, exact_d8(z))
+    centres = got[1, 1::3]
+    assert (centres == 1).any() and (centres == 2).any()
+
+
 def test_d8_tie_breaks_lowest_index():
     # centre 1, all eight neighbours 0: cardinal slope 1 beats diagonal 1/sqrt2;
     # of the four cardinals (N=1, W=3, E=4, S=6) the lowest index N wins
