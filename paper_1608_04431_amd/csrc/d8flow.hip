@@ -279,7 +279,7 @@ struct BatchLayout {
 };
 
 // Rasters of one tile shape: a contiguous range of the batch's tiles, run by
-// one persistent launch per stage with that shape's LDS size.
+// one launch per stage (a wavefront per tile) with that shape's LDS size.
 struct TileGroup {
     int th, tw;
     int64_t t_begin, t_end;
