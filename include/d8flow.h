@@ -140,6 +140,41 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                        size_t ws_bytes, void *stream);
 
 /*
+ * Forward accumulation (unit weights, uint32 counts) of a raster that stays
+ * in host memory, for rasters larger than the device's memory -- the regime
+ * the paper's tiles were designed for (Introduction; the EVICT strategy of
+ * Section "Broadcasting & Finalizing" recomputes each tile from its codes, so
+ * only the perimeter records persist between the passes).  The raster goes
+ * through the device in bands of band_rows rows (whole tile rows): pass 1 per
+ * band (the band's codes plus one halo row above and below), the band's
+ * perimeter-graph edges, the resolve over the whole perimeter graph, which
+ * stays in the workspace, then pass 2 per band with the band's counts copied
+ * back.  Host traffic: the codes twice and the counts once (6 B per cell).
+ * Copies run on a stream of the library's own and overlap the kernels;
+ * results equal flow_accum's with the same tile shape, bit for bit.
+ *
+ * dirs_host: uint8 [rows*cols] codes in host memory (in).
+ * acc_host:  uint32 [rows*cols] counts in host memory (out), 0 on NoData
+ *            cells; complete when `stream` reaches the end of this call.
+ *            Pinned memory (hipHostMalloc, torch's pin_memory) lets the
+ *            copies overlap the kernels; pageable memory works, slower.
+ * band_rows: rows per band, a multiple of the tile height after the tile is
+ *            cut to the raster (0 = 16 tile rows); cut to the raster.
+ * ws, ws_bytes: device workspace (256-byte aligned) of at least
+ *            d8_stream_workspace_bytes(...) bytes: the perimeter graph of the
+ *            whole raster, three code slots and two count slots of a band.
+ * Other arguments and returns as for flow_accum (data errors via
+ * d8_check_status(ws, stream)).  Calls that share a workspace, or run at the
+ * same time on one device, must be ordered (the library's copy stream and
+ * events are one per device).
+ */
+size_t d8_stream_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols,
+                                 int64_t band_rows);
+int flow_accum_streamed(const uint8_t *dirs_host, uint32_t *acc_host, int64_t rows, int64_t cols,
+                        int tile_rows, int tile_cols, int64_t band_rows, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/*
  * Batches of rasters.  Many rasters of uneven sizes go through the same
  * three stages together: a few launches per stage for the whole batch
  * instead of several per raster.  The tile passes launch one wavefront per

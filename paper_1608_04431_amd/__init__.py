@@ -17,7 +17,8 @@ NOFLOW = 8
 NODATA = 9
 
 __all__ = ["d8_directions", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
-           "check_status", "FlowAccum", "D8Error", "Raster", "Batch", "BatchGraph"]
+           "check_status", "FlowAccum", "D8Error", "Raster", "Batch", "BatchGraph",
+           "stream_workspace_bytes", "flow_accum_streamed"]
 
 
 def _stream(device: torch.device) -> int:
@@ -118,6 +119,46 @@ def flow_accum_adjoint(dirs: torch.Tensor, grad_acc: torch.Tensor, tile=(0, 0),
                                         tile[0], tile[1], _ptr(ws.buf), ws.nbytes,
                                         _stream(dirs.device))
     _lib.check(rc, "flow_accum_adjoint")
+    return out
+
+
+def stream_workspace_bytes(rows: int, cols: int, tile: tuple[int, int] = (0, 0),
+                           band_rows: int = 0) -> int:
+    n = _lib.load().d8_stream_workspace_bytes(rows, cols, tile[0], tile[1], band_rows)
+    if n == 0:
+        raise D8Error(_lib.D8_EINVAL, f"tile {tile}, band_rows {band_rows} for {rows}x{cols}")
+    return n
+
+
+def flow_accum_streamed(dirs_host: torch.Tensor, tile: tuple[int, int] = (0, 0), band_rows: int = 0,
+                        ws: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                        device=None, sync: bool = True) -> torch.Tensor:
+    """Unit-count accumulation of a raster held in host memory, in bands of
+    band_rows rows (flow_accum_streamed in d8flow.h).  dirs_host: uint8 CPU
+    tensor (pinned memory lets copies overlap); returns the counts as an int32
+    CPU tensor holding uint32 bits (pinned when allocated here).  With
+    sync=False the result is complete once the device's current stream is,
+    and `dirs_host`, `out` and `ws` must stay alive until then."""
+    if dirs_host.dtype != torch.uint8 or dirs_host.is_cuda or dirs_host.dim() != 2 \
+            or not dirs_host.is_contiguous():
+        raise ValueError("dirs_host must be a contiguous 2-D uint8 CPU tensor")
+    rows, cols = dirs_host.shape
+    dev = torch.device(device or "cuda")
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.int32, pin_memory=True)
+    if out.dtype != torch.int32 or out.is_cuda or tuple(out.shape) != (rows, cols) \
+            or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 CPU tensor of the raster's shape")
+    nbytes = stream_workspace_bytes(rows, cols, tile, band_rows)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if ws.dtype != torch.uint8 or not ws.is_cuda or ws.numel() < nbytes:
+        raise ValueError(f"ws must be a device uint8 tensor of at least {nbytes} bytes")
+    rc = _lib.load().flow_accum_streamed(_ptr(dirs_host), _ptr(out), rows, cols, tile[0], tile[1],
+                                         band_rows, _ptr(ws), ws.numel(), _stream(ws.device))
+    _lib.check(rc, "flow_accum_streamed")
+    if sync:
+        _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(ws.device)), "status")
     return out
 
 

@@ -245,9 +245,9 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
     unsigned nb = blocks_for(g.nnodes, kNodeBlock);
     D8_LAUNCH("fwd_pass1", st,
               (fwd_walk<1, T, V, E><<<ntiles, thr, lds1, st>>>(dirs, w, g, link, aloc, indeg, cnt,
-                                                               acc, ext, nullptr, status)));
+                                                               acc, ext, nullptr, status, 0)));
     D8_LAUNCH("graph_build", st,
-              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg)));
+              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, 0, g.nnodes)));
     if constexpr (kCounts) {
         D8_LAUNCH("resolve_fwd", st,
                   (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg, acc,
@@ -263,7 +263,7 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
               (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, packed, cnt, status)));
     D8_LAUNCH("fwd_pass2", st,
               (fwd_walk<2, T, V, E><<<ntiles, thr, lds2, st>>>(dirs, w, g, link, aloc, indeg, cnt,
-                                                               acc, ext, out, status)));
+                                                               acc, ext, out, status, 0)));
     return last_error();
 }
 
@@ -502,6 +502,186 @@ struct GraphHandle {
     hipGraphExec_t exec = nullptr;
 };
 
+// --------------------------------------------------------------- streaming --
+// A raster in host memory, processed in bands of whole tile rows: pass 1 per
+// band (codes of the band plus one halo row above and below), the band's
+// graph edges once the next band's links exist, the resolve over the whole
+// perimeter graph (which stays in the workspace), then pass 2 per band with
+// the counts copied back.  Copies run on a private stream of the library and
+// overlap the kernels on the caller's stream; events order slot reuse.
+struct StreamLayout {
+    Layout L;           // perimeter-graph arrays (root8 unused)
+    size_t cslot[3];    // codes: (band_rows + 2) x cols bytes each
+    size_t oslot[2];    // counts: band_rows x cols uint32 each
+    size_t total;
+    int64_t band_rows;  // a multiple of the tile height
+};
+
+int stream_layout(int64_t rows, int64_t cols, int &th, int &tw, int64_t band_rows, Geo &g,
+                  bool &empty, StreamLayout &S)
+{
+    int rc = check_common(rows, cols, th, tw, g, empty);
+    if (rc != D8_OK) return rc;
+    if (band_rows < 0) return D8_EINVAL;
+    if (empty) return D8_OK;
+    if (band_rows == 0) band_rows = (int64_t)16 * th;
+    if (band_rows % th != 0) return D8_EINVAL;
+    if (band_rows > rows) band_rows = ((rows + th - 1) / th) * th;
+    S.band_rows = band_rows;
+    S.L = layout_for(g);
+    size_t off = align256(S.L.root8);
+    for (int i = 0; i < 3; ++i) {
+        S.cslot[i] = off;
+        off = align256(off + (size_t)(band_rows + 2) * (size_t)cols);
+    }
+    for (int i = 0; i < 2; ++i) {
+        S.oslot[i] = off;
+        off = align256(off + (size_t)band_rows * (size_t)cols * sizeof(uint32_t));
+    }
+    S.total = off;
+    return D8_OK;
+}
+
+// Per device: the copy stream and the events of the pipeline.
+struct StreamRes {
+    hipStream_t cs = nullptr;
+    hipEvent_t ev[16] = {};
+};
+enum { kEvFree = 0, kEvReady = 3, kEvP1 = 6, kEvCFree = 7, kEvCReady = 9, kEvOFree = 11,
+       kEvODone = 13, kEvEnd = 15 };
+
+int stream_res(StreamRes *&R)
+{
+    static std::mutex mu;
+    static std::vector<StreamRes> res;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return D8_EHIP;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)res.size() <= dev) res.resize(dev + 1);
+    StreamRes &r = res[dev];
+    if (!r.cs) {
+        if (hipStreamCreateWithFlags(&r.cs, hipStreamNonBlocking) != hipSuccess) return D8_EHIP;
+        for (hipEvent_t &e : r.ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return D8_EHIP;
+    }
+    R = &r;
+    return D8_OK;
+}
+
+int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const StreamLayout &S, char *ws,
+                 hipStream_t st)
+{
+    using V = unsigned long long;
+    using E = uint32_t;
+    StreamRes *R = nullptr;
+    if (stream_res(R) != D8_OK) return D8_EHIP;
+    hipStream_t cs = R->cs;
+    hipEvent_t *ev = R->ev;
+    const Layout &L = S.L;
+    uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.status);
+    uint32_t *jstate = reinterpret_cast<uint32_t *>(ws + L.jstate);
+    uint16_t *link = reinterpret_cast<uint16_t *>(ws + L.link);
+    uint32_t *entry = reinterpret_cast<uint32_t *>(ws + L.entry);
+    uint32_t *succ = reinterpret_cast<uint32_t *>(ws + L.succ);
+    uint32_t *indeg = reinterpret_cast<uint32_t *>(ws + L.indeg);
+    uint32_t *aloc = reinterpret_cast<uint32_t *>(ws + L.val32);
+    V *acc = reinterpret_cast<V *>(ws + L.acc64);
+    E *ext = reinterpret_cast<E *>(ws + L.ext64);
+    const int64_t cols = g.cols, rows = g.rows;
+    const int tb = (int)(S.band_rows / g.th);  // tile rows per band
+    const int nband = (g.nty + tb - 1) / tb;
+    const size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1, (int)sizeof(FwdLds<1, uint32_t>));
+    const size_t lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2, (int)sizeof(FwdLds<2, uint32_t>));
+    if (allow_lds(fwd_walk<1, uint32_t, V, E>, lds1) || allow_lds(fwd_walk<2, uint32_t, V, E>, lds2))
+        return D8_EHIP;
+    auto band = [&](int b, int &ty0, int &ty1, int64_t &r0, int64_t &r1) {
+        ty0 = b * tb;
+        ty1 = std::min(g.nty, ty0 + tb);
+        r0 = (int64_t)ty0 * g.th;
+        r1 = std::min(rows, (int64_t)ty1 * g.th);
+    };
+    // a band's codes in slot i: slot row 0 is raster row r0 - 1
+    auto codes_ptr = [&](size_t slot, int64_t r0) {
+        return reinterpret_cast<const uint8_t *>(ws + slot) - (r0 - 1) * cols;
+    };
+    auto nodes_of = [&](int ty0, int ty1, int64_t &n0, int64_t &n1) {
+        n0 = (int64_t)ty0 * g.row_nodes;
+        n1 = ty1 >= g.nty ? g.nnodes : (int64_t)ty1 * g.row_nodes;
+    };
+    auto edges = [&](int b) {
+        int ty0, ty1;
+        int64_t r0, r1, n0, n1;
+        band(b, ty0, ty1, r0, r1);
+        nodes_of(ty0, ty1, n0, n1);
+        D8_LAUNCH("stream_graph_build", st,
+                  (graph_build<<<blocks_for(n1 - n0, kNodeBlock), kNodeBlock, 0, st>>>(
+                      codes_ptr(S.cslot[b % 3], r0), g, link, entry, succ, indeg, n0, n1)));
+        (void)hipEventRecord(ev[kEvFree + b % 3], st);
+    };
+
+    init_state<<<1, 1, 0, st>>>(status, jstate);
+    // the copy stream starts after the caller's earlier work on `st`
+    (void)hipEventRecord(ev[kEvEnd], st);
+    (void)hipStreamWaitEvent(cs, ev[kEvEnd], 0);
+    // pass 1 over the bands; band b - 1's edges after band b's links
+    for (int b = 0; b < nband; ++b) {
+        int ty0, ty1;
+        int64_t r0, r1;
+        band(b, ty0, ty1, r0, r1);
+        const int slot = b % 3;
+        if (b >= 3) (void)hipStreamWaitEvent(cs, ev[kEvFree + slot], 0);
+        const int64_t h0 = std::max<int64_t>(0, r0 - 1), h1 = std::min(rows, r1 + 1);
+        (void)hipMemcpyAsync(ws + S.cslot[slot] + (h0 - (r0 - 1)) * cols, dirs_h + h0 * cols,
+                             (size_t)(h1 - h0) * cols, hipMemcpyHostToDevice, cs);
+        (void)hipEventRecord(ev[kEvReady + slot], cs);
+        (void)hipStreamWaitEvent(st, ev[kEvReady + slot], 0);
+        const int t0 = ty0 * g.ntx, nt = (ty1 - ty0) * g.ntx;
+        D8_LAUNCH("stream_fwd_pass1", st,
+                  (fwd_walk<1, uint32_t, V, E><<<nt, kTileThreads, lds1, st>>>(
+                      codes_ptr(S.cslot[slot], r0), nullptr, g, link, aloc, indeg, nullptr, acc, ext,
+                      nullptr, status, t0)));
+        if (b >= 1) edges(b - 1);
+    }
+    edges(nband - 1);
+    D8_LAUNCH("stream_resolve", st,
+              (resolve_fwd_u32<<<blocks_for(g.nnodes, kNodeBlock), kNodeBlock, 0, st>>>(
+                  g.nnodes, link, aloc, entry, succ, indeg, acc, ext)));
+    D8_LAUNCH("stream_resolve_check", st,
+              (resolve_check<<<blocks_for(g.nnodes, kNodeBlock), kNodeBlock, 0, st>>>(
+                  g.nnodes, link, indeg, acc, nullptr, status)));
+    // pass 2 over the bands: code slots 0 and 1, count slots 0 and 1
+    (void)hipEventRecord(ev[kEvP1], st);
+    (void)hipStreamWaitEvent(cs, ev[kEvP1], 0);
+    for (int b = 0; b < nband; ++b) {
+        int ty0, ty1;
+        int64_t r0, r1;
+        band(b, ty0, ty1, r0, r1);
+        const int cslot = b & 1, oslot = b & 1;
+        if (b >= 2) (void)hipStreamWaitEvent(cs, ev[kEvCFree + cslot], 0);
+        (void)hipMemcpyAsync(ws + S.cslot[cslot] + cols, dirs_h + r0 * cols, (size_t)(r1 - r0) * cols,
+                             hipMemcpyHostToDevice, cs);
+        (void)hipEventRecord(ev[kEvCReady + cslot], cs);
+        (void)hipStreamWaitEvent(st, ev[kEvCReady + cslot], 0);
+        if (b >= 2) (void)hipStreamWaitEvent(st, ev[kEvOFree + oslot], 0);
+        uint32_t *out = reinterpret_cast<uint32_t *>(ws + S.oslot[oslot]) - r0 * cols;
+        const int t0 = ty0 * g.ntx, nt = (ty1 - ty0) * g.ntx;
+        D8_LAUNCH("stream_fwd_pass2", st,
+                  (fwd_walk<2, uint32_t, V, E><<<nt, kTileThreads, lds2, st>>>(
+                      codes_ptr(S.cslot[cslot], r0), nullptr, g, link, aloc, indeg, nullptr, acc, ext,
+                      out, status, t0)));
+        (void)hipEventRecord(ev[kEvCFree + cslot], st);
+        (void)hipEventRecord(ev[kEvODone + oslot], st);
+        (void)hipStreamWaitEvent(cs, ev[kEvODone + oslot], 0);
+        (void)hipMemcpyAsync(acc_h + r0 * cols, ws + S.oslot[oslot], (size_t)(r1 - r0) * cols * sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, cs);
+        (void)hipEventRecord(ev[kEvOFree + oslot], cs);
+    }
+    // the call is complete when `st` is: it waits for the last copy
+    (void)hipEventRecord(ev[kEvEnd], cs);
+    (void)hipStreamWaitEvent(st, ev[kEvEnd], 0);
+    return last_error();
+}
+
 }  // namespace
 
 extern "C" {
@@ -634,6 +814,39 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
 }
 
 // ---------------------------------------------------------------- batch --
+
+size_t d8_stream_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols,
+                                 int64_t band_rows)
+{
+    Geo g;
+    bool empty;
+    StreamLayout S;
+    if (stream_layout(rows, cols, tile_rows, tile_cols, band_rows, g, empty, S) != D8_OK) return 0;
+    if (empty) return 512;
+    return S.total;
+}
+
+int flow_accum_streamed(const uint8_t *dirs_host, uint32_t *acc_host, int64_t rows, int64_t cols,
+                        int tile_rows, int tile_cols, int64_t band_rows, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    Geo g;
+    bool empty;
+    StreamLayout S;
+    int rc = stream_layout(rows, cols, tile_rows, tile_cols, band_rows, g, empty, S);
+    if (rc != D8_OK) return rc;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;
+    if (empty) {
+        if (ws_bytes < 512) return D8_EWORKSPACE;
+        init_state<<<1, 1, 0, as_stream(stream)>>>(reinterpret_cast<uint32_t *>(ws),
+                                                   reinterpret_cast<uint32_t *>((char *)ws + 256));
+        return last_error();
+    }
+    if (!dirs_host || !acc_host) return D8_EINVAL;
+    if (ws_bytes < S.total) return D8_EWORKSPACE;
+    begin_call();
+    return run_streamed(dirs_host, acc_host, g, S, reinterpret_cast<char *>(ws), as_stream(stream));
+}
 
 size_t d8_batch_workspace_bytes(const d8_batch_item *items, int n)
 {

@@ -233,12 +233,14 @@ __device__ inline void graph_node(const uint8_t *__restrict__ dirs, const Geo &g
     if (indeg && s != kNone) atomicAdd(&indeg[s], 1u);
 }
 
+// Nodes id0 .. id1 - 1 (all of them, or one band's when streaming).
 __global__ void graph_build(const uint8_t *__restrict__ dirs, Geo g,
                             const uint16_t *__restrict__ link, uint32_t *__restrict__ entry,
-                            uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg)
+                            uint32_t *__restrict__ succ, uint32_t *__restrict__ indeg, int64_t id0,
+                            int64_t id1)
 {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
+    int64_t id = id0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= id1) return;
     graph_node(dirs, g, 0, id, link, entry, succ, indeg);
 }
 

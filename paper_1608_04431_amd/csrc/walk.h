@@ -1288,11 +1288,12 @@ __global__ void __launch_bounds__(64)
 fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
          uint16_t *__restrict__ link, T *__restrict__ aloc, uint32_t *__restrict__ indeg,
          uint32_t *__restrict__ cnt, V *__restrict__ acc, E *__restrict__ ext, T *__restrict__ out,
-         uint32_t *status)
+         uint32_t *status, int t0)
 {
+    // tiles t0 .. t0 + gridDim.x - 1 (a band of tile rows when streaming)
     extern __shared__ __align__(16) uint8_t lds8[];
-    fwd_tile<PASS, T, V, E>(dirs, w, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, aloc, indeg, cnt, acc,
-                            ext, out, status, lds8);
+    fwd_tile<PASS, T, V, E>(dirs, w, g, 0, t0 + xcd_tile(blockIdx.x, gridDim.x), link, aloc, indeg, cnt,
+                            acc, ext, out, status, lds8);
 }
 
 __global__ void __launch_bounds__(64, 3)

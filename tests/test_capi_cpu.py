@@ -76,6 +76,28 @@ def test_argument_errors_return_before_launch():
     assert lib.d8_directions(None, None, 0, 4, 0.0, None) == _lib.D8_OK
 
 
+def test_stream_workspace_and_argument_errors():
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x1000)
+    n = lib.d8_stream_workspace_bytes(1000, 300, 64, 48, 128)
+    assert n > lib.d8_workspace_bytes(1000, 300, 64, 48) // 2
+    assert lib.d8_stream_workspace_bytes(1000, 300, 64, 48, 0) > 0          # default bands
+    assert lib.d8_stream_workspace_bytes(1000, 300, 64, 48, 100) == 0       # not whole tile rows
+    assert lib.d8_stream_workspace_bytes(1000, 300, 64, 48, -64) == 0
+    assert lib.d8_stream_workspace_bytes(0, 300, 64, 48, 64) > 0            # empty: status only
+    # bigger bands need bigger slots; bands beyond the raster are cut to it
+    assert lib.d8_stream_workspace_bytes(1000, 300, 64, 48, 256) > n
+    assert lib.d8_stream_workspace_bytes(1000, 300, 64, 48, 4096) == \
+        lib.d8_stream_workspace_bytes(1000, 300, 64, 48, 1024)
+    EINVAL, EWS = _lib.D8_EINVAL, _lib.D8_EWORKSPACE
+    assert lib.flow_accum_streamed(fake, fake, 1000, 300, 64, 48, 100, fake, n, None) == EINVAL
+    assert lib.flow_accum_streamed(None, fake, 1000, 300, 64, 48, 128, fake, n, None) == EINVAL
+    assert lib.flow_accum_streamed(fake, fake, 1000, 300, 64, 48, 128, fake, n - 1, None) == EWS
+    assert lib.flow_accum_streamed(fake, fake, 1000, 300, 64, 48, 128, None, n, None) == EWS
+    odd = ctypes.c_void_p(0x1000 + 8)
+    assert lib.flow_accum_streamed(fake, fake, 1000, 300, 64, 48, 128, odd, n, None) == EWS
+
+
 def test_batch_argument_errors_return_before_launch():
     lib = _lib.load()
     fake = 0x1000
