@@ -507,8 +507,9 @@ struct GraphHandle {
 // band (codes of the band plus one halo row above and below), the band's
 // graph edges once the next band's links exist, the resolve over the whole
 // perimeter graph (which stays in the workspace), then pass 2 per band with
-// the counts copied back.  Copies run on a private stream of the library and
-// overlap the kernels on the caller's stream; events order slot reuse.
+// the counts copied back.  Host-to-device and device-to-host copies run on
+// two streams of the library's own (the link is full duplex) and overlap the
+// kernels on the caller's stream; events order slot reuse.
 struct StreamLayout {
     Layout L;           // perimeter-graph arrays (root8 unused)
     size_t cslot[3];    // codes: (band_rows + 2) x cols bytes each
@@ -542,9 +543,9 @@ int stream_layout(int64_t rows, int64_t cols, int &th, int &tw, int64_t band_row
     return D8_OK;
 }
 
-// Per device: the copy stream and the events of the pipeline.
+// Per device: the copy streams (in, out) and the events of the pipeline.
 struct StreamRes {
-    hipStream_t cs = nullptr;
+    hipStream_t cs = nullptr, cs2 = nullptr;
     hipEvent_t ev[16] = {};
 };
 enum { kEvFree = 0, kEvReady = 3, kEvP1 = 6, kEvCFree = 7, kEvCReady = 9, kEvOFree = 11,
@@ -560,7 +561,9 @@ int stream_res(StreamRes *&R)
     if ((int)res.size() <= dev) res.resize(dev + 1);
     StreamRes &r = res[dev];
     if (!r.cs) {
-        if (hipStreamCreateWithFlags(&r.cs, hipStreamNonBlocking) != hipSuccess) return D8_EHIP;
+        if (hipStreamCreateWithFlags(&r.cs, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&r.cs2, hipStreamNonBlocking) != hipSuccess)
+            return D8_EHIP;
         for (hipEvent_t &e : r.ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return D8_EHIP;
     }
@@ -575,7 +578,7 @@ int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const Str
     using E = uint32_t;
     StreamRes *R = nullptr;
     if (stream_res(R) != D8_OK) return D8_EHIP;
-    hipStream_t cs = R->cs;
+    hipStream_t cs = R->cs, cs2 = R->cs2;
     hipEvent_t *ev = R->ev;
     const Layout &L = S.L;
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.status);
@@ -671,13 +674,13 @@ int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const Str
                       out, status, t0)));
         (void)hipEventRecord(ev[kEvCFree + cslot], st);
         (void)hipEventRecord(ev[kEvODone + oslot], st);
-        (void)hipStreamWaitEvent(cs, ev[kEvODone + oslot], 0);
+        (void)hipStreamWaitEvent(cs2, ev[kEvODone + oslot], 0);
         (void)hipMemcpyAsync(acc_h + r0 * cols, ws + S.oslot[oslot], (size_t)(r1 - r0) * cols * sizeof(uint32_t),
-                             hipMemcpyDeviceToHost, cs);
-        (void)hipEventRecord(ev[kEvOFree + oslot], cs);
+                             hipMemcpyDeviceToHost, cs2);
+        (void)hipEventRecord(ev[kEvOFree + oslot], cs2);
     }
-    // the call is complete when `st` is: it waits for the last copy
-    (void)hipEventRecord(ev[kEvEnd], cs);
+    // the call is complete when `st` is: it waits for the last copy out
+    (void)hipEventRecord(ev[kEvEnd], cs2);
     (void)hipStreamWaitEvent(st, ev[kEvEnd], 0);
     return last_error();
 }

@@ -62,6 +62,10 @@ def test_dem32768_full_size(d8m):
     g = torch.from_numpy(synth.uniform((rows, cols), wl["seed_g"])).cuda()
     lam = d8m.flow_accum_adjoint(dirs, g, tile=tile)
     torch.cuda.synchronize()
+    # the same forward with the raster in host memory, streamed in bands
+    As = d8m.flow_accum_streamed(dirs.cpu().pin_memory(), tile=tile)
+    assert torch.equal(As, A.cpu())
+    del As
 
     recv = receivers(dirs)
     data = dirs.view(-1) != 9
