@@ -62,6 +62,7 @@ def _load():
     vp = ctypes.c_void_p
     i64 = ctypes.c_int64
     lib.orc_d8.argtypes = [vp, vp, i64, i64, ctypes.c_float]
+    lib.orc_rho8.argtypes = [vp, vp, vp, i64, i64, ctypes.c_float]
     lib.orc_receivers.argtypes = [vp, i64, i64, vp]
     lib.orc_accum_u64.argtypes = [vp, i64, i64, vp, vp, vp, vp]
     lib.orc_accum_f64.argtypes = [vp, i64, i64, vp, vp, vp, vp]
@@ -102,6 +103,17 @@ def d8(z: np.ndarray, nodata: float = -9999.0) -> np.ndarray:
     z = np.ascontiguousarray(z, dtype=np.float32)
     out = np.empty(z.shape, dtype=np.uint8)
     _check(_load().orc_d8(_p(z), _p(out), z.shape[0], z.shape[1], ctypes.c_float(nodata)))
+    return out
+
+
+def rho8(z: np.ndarray, rnd: np.ndarray, nodata: float = -9999.0) -> np.ndarray:
+    """rho8 directions (orc_rho8): rnd float32 in [0, 1), one draw per cell."""
+    z = np.ascontiguousarray(z, dtype=np.float32)
+    rnd = np.ascontiguousarray(rnd, dtype=np.float32)
+    if rnd.shape != z.shape:
+        raise ValueError("rnd and z differ in shape")
+    out = np.empty(z.shape, dtype=np.uint8)
+    _check(_load().orc_rho8(_p(z), _p(rnd), _p(out), z.shape[0], z.shape[1], ctypes.c_float(nodata)))
     return out
 
 

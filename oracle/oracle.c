@@ -75,6 +75,48 @@ int orc_d8(const float *z, uint8_t *dirs, int64_t rows, int64_t cols, float noda
     return OR_OK;
 }
 
+/*
+ * rho8 directions (Fairfield and Leymarie, 1991), which the paper's
+ * Introduction names beside D8 as a non-divergent flow metric: as D8, but the
+ * distance to a diagonal neighbour is t = fl32(2 - r) with r in [0, 1) drawn
+ * once per cell (given in rnd), instead of sqrt 2 -- so the diagonal factor
+ * 1 / t lies in (1/2, 1] with mean ln 2, near 1 / sqrt 2.  The steepest slope
+ * d / dist over the strictly lower data neighbours wins, the lowest index on
+ * ties; two slopes are compared exactly as d1 * dist2 against d2 * dist1 in
+ * double (each product of two floats is exact).
+ */
+int orc_rho8(const float *z, const float *rnd, uint8_t *dirs, int64_t rows, int64_t cols,
+             float nodata)
+{
+    if (rows < 0 || cols < 0) return OR_EINVAL;
+    for (int64_t r = 0; r < rows; ++r) {
+        for (int64_t c = 0; c < cols; ++c) {
+            const int64_t i = r * cols + c;
+            float zc = z[i];
+            if (zc == nodata || isnan(zc)) { dirs[i] = OR_NODATA; continue; }
+            volatile float t = 2.0f - rnd[i];
+            int best = OR_NOFLOW;
+            double best_d = 0.0, best_dist = 1.0;
+            for (int k = 0; k < 8; ++k) {
+                int64_t rr = r + OR_DR[k], cc = c + OR_DC[k];
+                if (rr < 0 || rr >= rows || cc < 0 || cc >= cols) continue;
+                float zn = z[rr * cols + cc];
+                if (zn == nodata || isnan(zn)) continue;
+                volatile float d = zc - zn;
+                if (!(d > 0.0f)) continue;
+                double dist = (OR_DR[k] == 0 || OR_DC[k] == 0) ? 1.0 : (double)t;
+                if ((double)d * best_dist > best_d * dist) {
+                    best = k;
+                    best_d = (double)d;
+                    best_dist = dist;
+                }
+            }
+            dirs[i] = (uint8_t)best;
+        }
+    }
+    return OR_OK;
+}
+
 /* ------------------------------------------------------- flow graph --- */
 /*
  * The receiver of a cell, from Eq. (1) with alpha in {0,1}: a data cell with

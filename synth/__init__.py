@@ -178,3 +178,21 @@ def sqrt2_blocks() -> np.ndarray:
         z[0, 3 * j + 1] = -dc
         z[0, 3 * j + 2] = -dd
     return z
+
+
+def rho8_half_blocks(rnd: np.ndarray):
+    """3 x 3k float32 raster of independent 3 x 3 blocks: centre 0, north
+    neighbour -1, north-east neighbour -1.5, the others far higher.  With
+    rho8's diagonal distance t = 2 - r the diagonal slope 1.5 / t beats the
+    cardinal 1 exactly when r > 1/2.  rnd (length k) gives each block's r; the
+    returned per-cell r raster puts it at the block centres (0.5 elsewhere).
+    Input only: no direction is computed here."""
+    k = len(rnd)
+    z = np.full((3, 3 * k), np.float32(1e30), dtype=np.float32)
+    r = np.full((3, 3 * k), np.float32(0.5), dtype=np.float32)
+    for j in range(k):
+        z[1, 3 * j + 1] = 0.0
+        z[0, 3 * j + 1] = -1.0
+        z[0, 3 * j + 2] = -1.5
+        r[1, 3 * j + 1] = rnd[j]
+    return z, r

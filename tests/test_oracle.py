@@ -350,6 +350,69 @@ def test_d8_near_sqrt2_boundary():
     assert (centres == 1).any() and (centres == 2).any()
 
 
+def exact_rho8(z, rnd, nodata=-9999.0):
+    """rho8 again with exact rationals: slope = d / 1 (cardinal) or
+    d / t (diagonal) with t = fl32(2 - r) of the cell and d the float32 drop;
+    largest wins, lowest index on ties."""
+    rows, cols = z.shape
+    out = np.zeros(z.shape, dtype=np.uint8)
+    for r in range(rows):
+        for c in range(cols):
+            zc = z[r, c]
+            if zc == np.float32(nodata) or np.isnan(zc):
+                out[r, c] = 9
+                continue
+            t = Fraction(float(np.float32(2.0) - np.float32(rnd[r, c])))
+            best, best_s = 8, Fraction(0)
+            for k in range(8):
+                rr, cc = r + DR[k], c + DC[k]
+                if not (0 <= rr < rows and 0 <= cc < cols):
+                    continue
+                zn = z[rr, cc]
+                if zn == np.float32(nodata) or np.isnan(zn):
+                    continue
+                d = Fraction(float(np.float32(zc) - np.float32(zn)))
+                if d <= 0:
+                    continue
+                s = d if (DR[k] == 0 or DC[k] == 0) else d / t
+                if s > best_s:
+                    best, best_s = k, s
+            out[r, c] = best
+    return out
+
+
+def test_rho8_exact_on_terrain_and_ties():
+    rng = np.random.default_rng(91)
+    z = rng.integers(0, 5, (21, 27)).astype(np.float32)     # many tied drops
+    z[rng.random(z.shape) < 0.05] = -9999.0
+    rnd = synth.uniform(z.shape, 3)
+    np.testing.assert_array_equal(oracle.rho8(z, rnd), exact_rho8(z, rnd))
+    t = synth.dem(30, 41, seed=8, lambda0=12, ocean=True)
+    rnd = synth.uniform(t.shape, 4)
+    got = oracle.rho8(t, rnd)
+    np.testing.assert_array_equal(got, exact_rho8(t, rnd))
+    # r = 0 everywhere: t = 2, diagonal slopes halved; r -> 1: t -> 1
+    for rv in (0.0, np.nextafter(np.float32(1), np.float32(0))):
+        rr = np.full(t.shape, rv, np.float32)
+        np.testing.assert_array_equal(oracle.rho8(t, rr), exact_rho8(t, rr))
+
+
+def test_rho8_half_blocks_closed_form():
+    # diagonal drop 1.5, cardinal 1: the diagonal wins iff 1.5 / (2 - r) > 1,
+    # i.e. r > 1/2; r = 1/2 is a tie and the lower index (north) wins
+    rv = np.array([0.0, 0.25, 0.4999999, 0.5, 0.5000001, 0.75, 0.9999999], np.float32)
+    z, r = synth.rho8_half_blocks(rv)
+    got = oracle.rho8(z, r)[1, 1::3]
+    want = np.where(rv > 0.5, 2, 1)
+    np.testing.assert_array_equal(got, want)
+    # over many uniform draws the diagonal share is the share of r above 1/2
+    rv = synth.uniform((1, 4000), 12)[0]
+    z, r = synth.rho8_half_blocks(rv)
+    got = oracle.rho8(z, r)[1, 1::3]
+    np.testing.assert_array_equal(got == 2, rv > 0.5)
+    assert abs((got == 2).mean() - 0.5) < 0.03
+
+
 def test_d8_tie_breaks_lowest_index():
     # centre 1, all eight neighbours 0: cardinal slope 1 beats diagonal 1/sqrt2;
     # of the four cardinals (N=1, W=3, E=4, S=6) the lowest index N wins
