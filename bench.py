@@ -36,6 +36,7 @@ KERNEL_BYTES_PER_CELL = {
     "adj_pass1": 5.0,   # directions + g
     "adj_pass2": 4.0,   # lambda
     "d8_directions": 5.0,
+    "d8_directions_rho8": 9.0,  # z 4 + r 4 + code 1
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
 SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (56, 48), (48, 64), (48, 48), (32, 64))
@@ -407,7 +408,21 @@ def run(args, bd):
     d8_ms = e0.elapsed_time(e1) / 5
     d8_gbps = KERNEL_BYTES_PER_CELL["d8_directions"] * n_cells / (d8_ms * 1e-3) / 1e9
     log(f"d8_directions: {d8_ms:.3f} ms, {d8_gbps:.0f} GB/s algorithmic")
-    del dem
+    # rho8 on the same DEM, one U[0,1) draw per cell (an input)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(8)
+    rnd = torch.rand((rows, cols), generator=gen, device=dev, dtype=torch.float32)
+    dr8 = d8.d8_directions_rho8(dem, rnd)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        d8.d8_directions_rho8(dem, rnd, out=dr8)
+    e1.record()
+    torch.cuda.synchronize()
+    rho8_ms = e0.elapsed_time(e1) / 5
+    rho8_gbps = KERNEL_BYTES_PER_CELL["d8_directions_rho8"] * n_cells / (rho8_ms * 1e-3) / 1e9
+    log(f"d8_directions_rho8: {rho8_ms:.3f} ms, {rho8_gbps:.0f} GB/s algorithmic")
+    del dem, rnd, dr8
     g = torch.from_numpy(synth.uniform((rows, cols), wl.get("seed_g", 31))).to(dev)
     A = torch.empty((rows, cols), dtype=torch.int32, device=dev)
     lam = torch.empty((rows, cols), dtype=torch.float32, device=dev)
@@ -522,6 +537,9 @@ def run(args, bd):
         "roofline": roofline,
         "d8_directions": {"ms": round(d8_ms, 4), "bytes_per_cell": KERNEL_BYTES_PER_CELL["d8_directions"],
                           "achieved_GBps": d8_gbps, "frac_hbm_peak": d8_gbps / HBM_PEAK_GBPS},
+        "d8_directions_rho8": {"ms": round(rho8_ms, 4),
+                               "bytes_per_cell": KERNEL_BYTES_PER_CELL["d8_directions_rho8"],
+                               "achieved_GBps": rho8_gbps, "frac_hbm_peak": rho8_gbps / HBM_PEAK_GBPS},
         "streamed": streamed,
         "cpu_baseline": cpu,
     }

@@ -83,6 +83,20 @@ int d8_directions(const float *dem, uint8_t *dirs, int64_t rows, int64_t cols, f
                   void *stream);
 
 /*
+ * rho8 directions (Fairfield and Leymarie, 1991), the other non-divergent
+ * metric the paper's Introduction names: as d8_directions, but the distance
+ * to a diagonal neighbour is t = fl32(2 - r(c)) instead of sqrt 2, with r(c)
+ * one uniform draw in [0, 1) per cell supplied by the caller (rnd, float32
+ * [rows*cols], the dem's layout; values outside [0, 1) are used as given).
+ * The diagonal factor 1 / t lies in (1/2, 1] with mean ln 2, so straight
+ * drainage lines no longer follow the grid's preferred directions.  The
+ * steepest slope wins, compared exactly (drop against t times the cardinal
+ * drop in double); the lowest index wins ties.  Returns as d8_directions.
+ */
+int d8_directions_rho8(const float *dem, const float *rnd, uint8_t *dirs, int64_t rows, int64_t cols,
+                       float nodata, void *stream);
+
+/*
  * Workspace needed by flow_accum / flow_accum_adjoint for this raster and tile
  * shape (tile_rows = tile_cols = 0 picks the default shape).  One workspace
  * serves both calls.  Returns 0 for an invalid tile shape.

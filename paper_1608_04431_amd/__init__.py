@@ -16,7 +16,7 @@ from ._lib import D8_ACC_F32, D8_ACC_U32, D8Error  # noqa: F401
 NOFLOW = 8
 NODATA = 9
 
-__all__ = ["d8_directions", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
+__all__ = ["d8_directions", "d8_directions_rho8", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
            "check_status", "FlowAccum", "D8Error", "Raster", "Batch", "BatchGraph",
            "stream_workspace_bytes", "flow_accum_streamed"]
 
@@ -72,6 +72,23 @@ def d8_directions(dem: torch.Tensor, nodata: float = -9999.0, out: torch.Tensor 
     rc = _lib.load().d8_directions(_ptr(dem), _ptr(out), dem.shape[0], dem.shape[1],
                                    float(nodata), _stream(dem.device))
     _lib.check(rc, "d8_directions")
+    return out
+
+
+def d8_directions_rho8(dem: torch.Tensor, rnd: torch.Tensor, nodata: float = -9999.0,
+                       out: torch.Tensor | None = None):
+    """rho8 codes (uint8) of a float32 DEM with one uniform draw in [0, 1) per
+    cell in rnd (float32, same shape; see d8_directions_rho8 in d8flow.h)."""
+    _check_raster(dem, torch.float32, "dem")
+    _check_raster(rnd, torch.float32, "rnd")
+    if rnd.shape != dem.shape:
+        raise ValueError("rnd and dem differ in shape")
+    if out is None:
+        out = torch.empty(dem.shape, dtype=torch.uint8, device=dem.device)
+    _check_raster(out, torch.uint8, "out")
+    rc = _lib.load().d8_directions_rho8(_ptr(dem), _ptr(rnd), _ptr(out), dem.shape[0], dem.shape[1],
+                                        float(nodata), _stream(dem.device))
+    _lib.check(rc, "d8_directions_rho8")
     return out
 
 

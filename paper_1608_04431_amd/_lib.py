@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd8flow.so")
 
 # every symbol declared in include/d8flow.h
-EXPORTS = ("d8_directions", "d8_workspace_bytes", "flow_accum", "flow_accum_adjoint",
+EXPORTS = ("d8_directions", "d8_directions_rho8", "d8_workspace_bytes", "flow_accum", "flow_accum_adjoint",
            "d8_stream_workspace_bytes", "flow_accum_streamed",
            "d8_batch_workspace_bytes", "flow_accum_batched", "d8_graph_create",
            "d8_graph_launch", "d8_graph_destroy",
@@ -59,6 +59,8 @@ def load() -> ctypes.CDLL:
     vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
     lib.d8_directions.argtypes = [vp, vp, i64, i64, ctypes.c_float, vp]
     lib.d8_directions.restype = i32
+    lib.d8_directions_rho8.argtypes = [vp, vp, vp, i64, i64, ctypes.c_float, vp]
+    lib.d8_directions_rho8.restype = i32
     lib.d8_workspace_bytes.argtypes = [i64, i64, i32, i32]
     lib.d8_workspace_bytes.restype = sz
     lib.flow_accum.argtypes = [vp, vp, vp, i32, i64, i64, i32, i32, vp, sz, vp]

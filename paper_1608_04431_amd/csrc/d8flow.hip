@@ -685,6 +685,38 @@ int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const Str
     return last_error();
 }
 
+// D8 (or rho8) over the raster in strips of kD8Rows rows and blocks of
+// kD8Cols columns.
+template <bool RHO>
+int launch_d8(const float *dem, const float *rnd, uint8_t *dirs, int64_t rows, int64_t cols,
+              float nodata, hipStream_t st)
+{
+    if (rows < 0 || cols < 0) return D8_EINVAL;
+    if (rows == 0 || cols == 0) return D8_OK;
+    if (!dem || !dirs) return D8_EINVAL;
+    begin_call();
+    const int64_t ncb = (cols + kD8Cols - 1) / kD8Cols, nstrips = (rows + kD8Rows - 1) / kD8Rows;
+    const bool vec = cols % 4 == 0 && (reinterpret_cast<uintptr_t>(dem) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(rnd) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(dirs) & 3) == 0;
+    const char *name = RHO ? "d8_directions_rho8" : "d8_directions";
+    // at most 2^22 blocks per launch (grid size in lanes stays below 2^32)
+    const int64_t per = std::max<int64_t>(1, ((int64_t)1 << 22) / ncb);
+    for (int64_t s0 = 0; s0 < nstrips; s0 += per) {
+        const int64_t ns = nstrips - s0 < per ? nstrips - s0 : per;
+        const unsigned nb = (unsigned)(ns * ncb);
+        if (vec)
+            D8_LAUNCH(name, st,
+                      (d8_kernel<true, RHO><<<nb, kD8Threads, 0, st>>>(dem, rnd, dirs, rows, cols, nodata,
+                                                                      ncb, s0)));
+        else
+            D8_LAUNCH(name, st,
+                      (d8_kernel<false, RHO><<<nb, kD8Threads, 0, st>>>(dem, rnd, dirs, rows, cols,
+                                                                       nodata, ncb, s0)));
+    }
+    return last_error();
+}
+
 }  // namespace
 
 extern "C" {
@@ -707,28 +739,14 @@ const char *d8_strerror(int code)
 int d8_directions(const float *dem, uint8_t *dirs, int64_t rows, int64_t cols, float nodata,
                   void *stream)
 {
-    if (rows < 0 || cols < 0) return D8_EINVAL;
-    if (rows == 0 || cols == 0) return D8_OK;
-    if (!dem || !dirs) return D8_EINVAL;
-    begin_call();
-    const int64_t ncb = (cols + kD8Cols - 1) / kD8Cols, nstrips = (rows + kD8Rows - 1) / kD8Rows;
-    const bool vec = cols % 4 == 0 && (reinterpret_cast<uintptr_t>(dem) & 15) == 0 &&
-                     (reinterpret_cast<uintptr_t>(dirs) & 3) == 0;
-    // at most 2^22 blocks per launch (grid size in lanes stays below 2^32)
-    const int64_t per = std::max<int64_t>(1, ((int64_t)1 << 22) / ncb);
-    for (int64_t s0 = 0; s0 < nstrips; s0 += per) {
-        const int64_t ns = nstrips - s0 < per ? nstrips - s0 : per;
-        const unsigned nb = (unsigned)(ns * ncb);
-        if (vec)
-            D8_LAUNCH("d8_directions", as_stream(stream),
-                      (d8_kernel<true><<<nb, kD8Threads, 0, as_stream(stream)>>>(
-                          dem, dirs, rows, cols, nodata, ncb, s0)));
-        else
-            D8_LAUNCH("d8_directions", as_stream(stream),
-                      (d8_kernel<false><<<nb, kD8Threads, 0, as_stream(stream)>>>(
-                          dem, dirs, rows, cols, nodata, ncb, s0)));
-    }
-    return last_error();
+    return launch_d8<false>(dem, nullptr, dirs, rows, cols, nodata, as_stream(stream));
+}
+
+int d8_directions_rho8(const float *dem, const float *rnd, uint8_t *dirs, int64_t rows, int64_t cols,
+                       float nodata, void *stream)
+{
+    if (rows > 0 && cols > 0 && !rnd) return D8_EINVAL;
+    return launch_d8<true>(dem, rnd, dirs, rows, cols, nodata, as_stream(stream));
 }
 
 size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols)

@@ -21,7 +21,7 @@
 //   adj_jump_*        each exit's edge (as graph_build finds it), then the
 //                     downstream sums over the exit forest by pointer jumping;
 //   adj_finish        lambda = lambda_loc + the sum of the cell's root exit.
-// D8 directions: d8_kernel.
+// D8 directions (and rho8's): d8_kernel.
 #pragma once
 #include "d8_common.h"
 #include "walk.h"
@@ -121,7 +121,12 @@ __device__ inline void d8_consider(float zc, float zn, int k, float &best, int &
     }
 }
 
-__device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8Row &dn)
+// RHO: rho8 (Fairfield and Leymarie) -- the diagonal distance of cell i is
+// t[i] = fl32(2 - r) for its random r in [0, 1) instead of sqrt 2; the
+// diagonal wins when bd / t > bc, compared exactly as bd > bc * t in double.
+template <bool RHO = false>
+__device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8Row &dn,
+                                     const float *t = nullptr)
 {
     uint32_t out = 0;
 #pragma unroll
@@ -140,7 +145,14 @@ __device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8
             d8_consider(zc, d8_at(dn, i), 6, bc, kc);
             d8_consider(zc, d8_at(dn, i + 1), 7, bd, kd);
             const double dc = bc, dd = bd;
-            const double keyc = 2.0 * (dc * dc), keyd = dd * dd;
+            double keyc, keyd;
+            if constexpr (RHO) {
+                keyc = dc * (double)t[i];
+                keyd = dd;
+            } else {
+                keyc = 2.0 * (dc * dc);
+                keyd = dd * dd;
+            }
             code = keyd > keyc ? kd : (keyc > keyd ? kc : (kc < kd ? kc : kd));
         }
         out |= (uint32_t)code << (8 * i);
@@ -148,10 +160,33 @@ __device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8
     return out;
 }
 
-template <bool VEC>
+// rnd (RHO only): rho8's per-cell random values, the dem's layout.
+template <bool VEC, bool RHO>
+__device__ inline void d8_rnd_load(const float *__restrict__ rnd, int64_t rows, int64_t cols, int64_t r,
+                                   int64_t c0, float4 &t)
+{
+    t = make_float4(2.0f, 2.0f, 2.0f, 2.0f);
+    if constexpr (RHO) {
+        if (r < 0 || r >= rows || c0 >= cols) return;
+        const float *p = rnd + r * cols;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if constexpr (VEC) {
+            v = *reinterpret_cast<const float4 *>(p + c0);
+        } else {
+            v.x = p[c0];
+            if (c0 + 1 < cols) v.y = p[c0 + 1];
+            if (c0 + 2 < cols) v.z = p[c0 + 2];
+            if (c0 + 3 < cols) v.w = p[c0 + 3];
+        }
+        t = make_float4(__fsub_rn(2.0f, v.x), __fsub_rn(2.0f, v.y), __fsub_rn(2.0f, v.z),
+                        __fsub_rn(2.0f, v.w));
+    }
+}
+
+template <bool VEC, bool RHO>
 __global__ void __launch_bounds__(kD8Threads)
-d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t rows, int64_t cols,
-          float nodata, int64_t ncb, int64_t strip0)
+d8_kernel(const float *__restrict__ dem, const float *__restrict__ rnd, uint8_t *__restrict__ dirs,
+          int64_t rows, int64_t cols, float nodata, int64_t ncb, int64_t strip0)
 {
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t strip = strip0 + t / ncb, cb = t - (t / ncb) * ncb;
@@ -159,12 +194,13 @@ d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t row
     const int64_t r0 = strip * kD8Rows;
     const int64_t r1 = rows - r0 < kD8Rows ? rows : r0 + kD8Rows;
     const float nodata_ = nodata;
-    float4 q, q2;
+    float4 q, q2, tn;
     float hl, hr, hl2, hr2;
     d8_row_load<VEC>(dem, rows, cols, r0 - 1, c0, q, hl, hr);
     D8Row up = d8_row_finish(q, hl, hr, nodata_);
     d8_row_load<VEC>(dem, rows, cols, r0, c0, q, hl, hr);
     D8Row mid = d8_row_finish(q, hl, hr, nodata_);
+    d8_rnd_load<VEC, RHO>(rnd, rows, cols, r0, c0, tn);
     // two rows in flight: q (row r + 1) and q2 (row r + 2)
     d8_row_load<VEC>(dem, rows, cols, r0 + 1, c0, q, hl, hr);
     d8_row_load<VEC>(dem, rows, cols, r0 + 2, c0, q2, hl2, hr2);
@@ -174,7 +210,9 @@ d8_kernel(const float *__restrict__ dem, uint8_t *__restrict__ dirs, int64_t row
         hl = hl2;
         hr = hr2;
         d8_row_load<VEC>(dem, rows, cols, r + 3, c0, q2, hl2, hr2);  // in flight during two compares
-        const uint32_t codes = d8_codes4(up, mid, dn);
+        const float tr[4] = {tn.x, tn.y, tn.z, tn.w};
+        d8_rnd_load<VEC, RHO>(rnd, rows, cols, r + 1, c0, tn);
+        const uint32_t codes = d8_codes4<RHO>(up, mid, dn, tr);
         uint8_t *o = dirs + r * cols + c0;
         if constexpr (VEC) {
             if (c0 < cols) *reinterpret_cast<uint32_t *>(o) = codes;

@@ -120,6 +120,32 @@ def test_d8_directions_near_sqrt2(d8m):
     np.testing.assert_array_equal(d8m.d8_directions(dev(zp)).cpu().numpy(), oracle.d8(zp))
 
 
+def test_rho8_directions_match_oracle(d8m):
+    """rho8 (random diagonal distance 2 - r per cell) against the oracle on
+    terrain with NoData, integer DEMs with ties, strips / blocks / ragged
+    edges, the r > 1/2 blocks; and accumulation over rho8 directions."""
+    rng = np.random.default_rng(21)
+    zi = rng.integers(0, 5, (70, 1030)).astype(np.float32)
+    zi[rng.random(zi.shape) < 0.05] = -9999.0
+    cases = [synth.dem(300, 257, seed=7, lambda0=64, ocean=True), zi, zi[:, :1029],
+             synth.workload_dem("dem512")]
+    for i, z in enumerate(cases):
+        rnd = synth.uniform(z.shape, 40 + i)
+        got = d8m.d8_directions_rho8(dev(z), dev(rnd)).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.rho8(z, rnd), err_msg=f"case {i}")
+    rv = synth.uniform((1, 500), 9)[0]
+    z, r = synth.rho8_half_blocks(rv)
+    zp = np.concatenate([z, np.full((3, 2), np.float32(1e30), np.float32)], axis=1)
+    rp = np.concatenate([r, np.full((3, 2), np.float32(0.5), np.float32)], axis=1)
+    assert z.shape[1] % 4 == 0 and zp.shape[1] % 4 != 0  # 16-byte and per-element paths
+    for zz, rr in ((z, r), (zp, rp)):
+        got = d8m.d8_directions_rho8(dev(zz), dev(rr)).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.rho8(zz, rr))
+    d = d8m.d8_directions_rho8(dev(cases[3]), dev(synth.uniform(cases[3].shape, 43)))
+    assert_u32_exact(d8m.flow_accum(d, acc_type="u32", tile=(64, 48)).cpu().numpy().view(np.uint32),
+                     d.cpu().numpy())
+
+
 # ------------------------------------------------------------ hand fixtures --
 def test_golden_fixtures_u32(d8m):
     from conftest import GOLDEN_FILES, load_golden
