@@ -63,6 +63,8 @@ def _load():
     i64 = ctypes.c_int64
     lib.orc_d8.argtypes = [vp, vp, i64, i64, ctypes.c_float]
     lib.orc_rho8.argtypes = [vp, vp, vp, i64, i64, ctypes.c_float]
+    lib.orc_accum_absorb_f64.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
+    lib.orc_transpose_absorb_f64.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
     lib.orc_receivers.argtypes = [vp, i64, i64, vp]
     lib.orc_accum_u64.argtypes = [vp, i64, i64, vp, vp, vp, vp]
     lib.orc_accum_f64.argtypes = [vp, i64, i64, vp, vp, vp, vp]
@@ -146,6 +148,33 @@ def accum_f64(dirs: np.ndarray, w: np.ndarray | None = None, want_order: bool = 
     _check(_load().orc_accum_f64(_p(dirs), dirs.shape[0], dirs.shape[1], _p(w), _p(A),
                                  _p(order), ctypes.byref(n)))
     return (A, order[: n.value]) if want_order else A
+
+
+def accum_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, w: np.ndarray | None = None) -> np.ndarray:
+    """Eq. (1) with absorption: A(p) = w(p) + sum over donors n of alpha(n) A(n)."""
+    dirs = _dirs(dirs)
+    _, order = accum_u64(dirs, want_order=True)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float32)
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+    A = np.empty(dirs.shape, dtype=np.float64)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    _check(_load().orc_accum_absorb_f64(_p(dirs), dirs.shape[0], dirs.shape[1], _p(order), order.size,
+                                        _p(w), _p(alpha), _p(A)))
+    return A
+
+
+def transpose_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """lambda(c) = g(c) + alpha(c) lambda(receiver(c)) (the transpose of accum_absorb_f64)."""
+    dirs = _dirs(dirs)
+    _, order = accum_u64(dirs, want_order=True)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float32)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    lam = np.empty(dirs.shape, dtype=np.float64)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    _check(_load().orc_transpose_absorb_f64(_p(dirs), dirs.shape[0], dirs.shape[1], _p(order),
+                                            order.size, _p(g), _p(alpha), _p(lam)))
+    return lam
 
 
 def accum_f64d(dirs: np.ndarray, w: np.ndarray) -> np.ndarray:

@@ -256,6 +256,47 @@ int orc_transpose_f64(const uint8_t *dirs, int64_t rows, int64_t cols, const int
 }
 
 /*
+ * Eq. (1) with absorption: alpha(n, p) = alpha(n) in [0, 1] for n's single
+ * receiver p (the fraction of n's accumulation that reaches it), so
+ * A(p) = w(p) + sum over donors n of alpha(n) A(n).  A cell's accumulation is
+ * complete when it is popped in a topological order (from orc_accum_*), so
+ * one sweep of that order computes A; its transpose,
+ * lambda(c) = g(c) + alpha(c) lambda(receiver(c)), sweeps the order in
+ * reverse.  w = NULL means w = 1.  NoData cells hold 0.
+ */
+int orc_accum_absorb_f64(const uint8_t *dirs, int64_t rows, int64_t cols, const int64_t *order,
+                         int64_t n_order, const float *w, const float *alpha, double *A)
+{
+    int64_t n = rows * cols;
+    for (int64_t i = 0; i < n; ++i) A[i] = 0.0;
+    for (int64_t t = 0; t < n_order; ++t) {
+        int64_t c = order[t];
+        A[c] += w ? (double)w[c] : 1.0;
+    }
+    for (int64_t t = 0; t < n_order; ++t) {
+        int64_t c = order[t];
+        int64_t r = receiver(dirs, rows, cols, c);
+        if (r == -2) return OR_EDIRCODE;
+        if (r >= 0) A[r] += (double)alpha[c] * A[c];
+    }
+    return OR_OK;
+}
+
+int orc_transpose_absorb_f64(const uint8_t *dirs, int64_t rows, int64_t cols, const int64_t *order,
+                             int64_t n_order, const float *g, const float *alpha, double *lam)
+{
+    int64_t n = rows * cols;
+    for (int64_t i = 0; i < n; ++i) lam[i] = 0.0;
+    for (int64_t t = n_order - 1; t >= 0; --t) {
+        int64_t c = order[t];
+        int64_t r = receiver(dirs, rows, cols, c);
+        if (r == -2) return OR_EDIRCODE;
+        lam[c] = (double)g[c] + (r >= 0 ? (double)alpha[c] * lam[r] : 0.0);
+    }
+    return OR_OK;
+}
+
+/*
  * Brute force by path walking (independent of the Kahn order): every data
  * cell y adds w(y) to each cell on its flow path, itself included, so
  * A(x) = sum of w(y) over all y whose path passes x; and lambda(y) is the sum

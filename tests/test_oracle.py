@@ -468,3 +468,56 @@ def test_path_stats_hand():
     s = oracle.path_stats(d, 1, 4)
     assert s == dict(max_in_tile_run=4, max_crossings=1, perimeter_cells=8, exit_cells=1,
                      entry_cells=1, longest_path=8)
+
+
+# ------------------------------------------------------------ absorption ----
+def py_absorb_brute(d, w, alpha):
+    """A(x) = sum over cells y whose path passes x of w(y) times the product
+    of alpha over the path's cells before x (path walking, no Kahn order)."""
+    A = np.zeros(d.shape)
+    for r in range(d.shape[0]):
+        for c in range(d.shape[1]):
+            if d[r, c] == 9:
+                continue
+            v, cell = float(w[r, c]), (r, c)
+            while cell is not None:
+                A[cell] += v
+                v *= float(alpha[cell])
+                cell = py_receiver(d, *cell)
+    return A
+
+
+def test_absorb_reduces_to_eq1_and_to_w():
+    d = random_acyclic_dirs(23, 31, 7)
+    w = synth.uniform(d.shape, 5)
+    valid = d != 9
+    one = np.ones(d.shape, np.float32)
+    np.testing.assert_array_equal(oracle.accum_absorb_f64(d, one, w), oracle.accum_f64(d, w))
+    zero = np.zeros(d.shape, np.float32)
+    np.testing.assert_array_equal(oracle.accum_absorb_f64(d, zero, w), np.where(valid, w, 0.0))
+    g = synth.uniform(d.shape, 6)
+    np.testing.assert_array_equal(oracle.transpose_absorb_f64(d, one, g), oracle.transpose_f64(d, g))
+    np.testing.assert_array_equal(oracle.transpose_absorb_f64(d, zero, g), np.where(valid, g, 0.0))
+
+
+def test_absorb_brute_force_and_duality():
+    d = random_acyclic_dirs(17, 19, 8)
+    w = synth.uniform(d.shape, 9)
+    alpha = synth.uniform(d.shape, 10)
+    A = oracle.accum_absorb_f64(d, alpha, w)
+    np.testing.assert_allclose(A, py_absorb_brute(d, w, alpha), rtol=1e-12, atol=1e-12)
+    # transpose: <g, A(w)> = <lambda(g), w> (one linear operator and its adjoint)
+    g = synth.uniform(d.shape, 11)
+    lam = oracle.transpose_absorb_f64(d, alpha, g)
+    assert abs(float((g.astype(np.float64) * A).sum()) - float((lam * w).sum())) < 1e-9 * A.sum()
+
+
+def test_absorb_chain_closed_form():
+    # a row flowing east: A at position k (0-based) = sum_{j<=k} a^j
+    d = np.full((1, 12), 4, np.uint8)
+    d[0, -1] = 8
+    for a in (0.25, 0.5, 0.9):
+        alpha = np.full(d.shape, a, np.float32)
+        A = oracle.accum_absorb_f64(d, alpha)
+        want = np.array([sum(float(np.float32(a)) ** j for j in range(k + 1)) for k in range(12)])
+        np.testing.assert_allclose(A[0], want, rtol=1e-14)
