@@ -154,6 +154,26 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
                        size_t ws_bytes, void *stream);
 
 /*
+ * Flow accumulation with absorption: Eq. (1) with alpha(n, p) = alpha(n) in
+ * [0, 1] for n's single receiver p, i.e. A(p) = w(p) + sum over donors n of
+ * alpha(n) A(n) -- the fraction alpha(n) of a cell's flow reaches its
+ * receiver (the paper's Eq. (1) and its remark that absorption is a simple
+ * extension of the tiled method).  Same three stages as flow_accum; each
+ * perimeter link also carries the product of alpha along the entry's in-tile
+ * path, and the cross-tile resolve multiplies by it (float64).
+ *
+ * dirs: uint8 codes; weights: float32 w or NULL (w = 1); alpha: float32 per
+ * cell (values outside [0, 1] are used as given); acc: float32 A (out), 0 on
+ * NoData cells.  ws: at least d8_absorb_workspace_bytes(...) (256-byte
+ * aligned).  Other arguments and returns as for flow_accum; the tile's LDS
+ * holds alpha besides the values, so large tiles run fewer per CU.
+ */
+size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols);
+int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *alpha, float *acc,
+                      int64_t rows, int64_t cols, int tile_rows, int tile_cols, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/*
  * Forward accumulation (unit weights, uint32 counts) of a raster that stays
  * in host memory, for rasters larger than the device's memory -- the regime
  * the paper's tiles were designed for (Introduction; the EVICT strategy of

@@ -18,7 +18,7 @@ NODATA = 9
 
 __all__ = ["d8_directions", "d8_directions_rho8", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
            "check_status", "FlowAccum", "D8Error", "Raster", "Batch", "BatchGraph",
-           "stream_workspace_bytes", "flow_accum_streamed"]
+           "stream_workspace_bytes", "flow_accum_streamed", "flow_accum_absorb"]
 
 
 def _stream(device: torch.device) -> int:
@@ -136,6 +136,36 @@ def flow_accum_adjoint(dirs: torch.Tensor, grad_acc: torch.Tensor, tile=(0, 0),
                                         tile[0], tile[1], _ptr(ws.buf), ws.nbytes,
                                         _stream(dirs.device))
     _lib.check(rc, "flow_accum_adjoint")
+    return out
+
+
+def flow_accum_absorb(dirs: torch.Tensor, alpha: torch.Tensor, weights: torch.Tensor | None = None,
+                      tile: tuple[int, int] = (0, 0), ws: torch.Tensor | None = None,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """A(p) = w(p) + sum over donors n of alpha(n) A(n), float32 (see
+    flow_accum_absorb in d8flow.h).  ws: a device uint8 tensor of at least
+    d8_absorb_workspace_bytes, or None."""
+    _check_raster(dirs, torch.uint8, "dirs")
+    _check_raster(alpha, torch.float32, "alpha")
+    if alpha.shape != dirs.shape:
+        raise ValueError("alpha and dirs differ in shape")
+    if weights is not None:
+        _check_raster(weights, torch.float32, "weights")
+        if weights.shape != dirs.shape:
+            raise ValueError("weights and dirs differ in shape")
+    rows, cols = dirs.shape
+    n = _lib.load().d8_absorb_workspace_bytes(rows, cols, tile[0], tile[1])
+    if n == 0:
+        raise D8Error(_lib.D8_EINVAL, f"tile {tile} for {rows}x{cols}")
+    if ws is None:
+        ws = torch.empty(n, dtype=torch.uint8, device=dirs.device)
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float32, device=dirs.device)
+    _check_raster(out, torch.float32, "out")
+    rc = _lib.load().flow_accum_absorb(_ptr(dirs), _ptr(weights), _ptr(alpha), _ptr(out), rows, cols,
+                                       tile[0], tile[1], _ptr(ws), ws.numel(), _stream(dirs.device))
+    _lib.check(rc, "flow_accum_absorb")
+    _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(dirs.device)), "status")
     return out
 
 

@@ -268,6 +268,56 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
 }
 
 
+// Forward with absorption (float weights): the float path with each cell's
+// alpha in the tile passes and per-node coefficients in the resolve.  The
+// workspace is the one-raster layout plus anode and pathp (a float per node).
+size_t absorb_extra(const Layout &L, const Geo &g, size_t &anode, size_t &pathp)
+{
+    anode = align256(L.total);
+    pathp = align256(anode + (size_t)g.nnodes * sizeof(float));
+    return align256(pathp + (size_t)g.nnodes * sizeof(float));
+}
+
+int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, float *out, const Geo &g,
+                       char *ws, const Layout &L, hipStream_t st)
+{
+    size_t oa, op;
+    absorb_extra(L, g, oa, op);
+    uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.status);
+    uint32_t *jstate = reinterpret_cast<uint32_t *>(ws + L.jstate);
+    uint16_t *link = reinterpret_cast<uint16_t *>(ws + L.link);
+    uint32_t *entry = reinterpret_cast<uint32_t *>(ws + L.entry);
+    uint32_t *succ = reinterpret_cast<uint32_t *>(ws + L.succ);
+    uint32_t *indeg = reinterpret_cast<uint32_t *>(ws + L.indeg);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + L.ptr2);
+    float *aloc = reinterpret_cast<float *>(ws + L.val32);
+    double *acc = reinterpret_cast<double *>(ws + L.acc64);
+    double *ext = reinterpret_cast<double *>(ws + L.ext64);
+    float *anode = reinterpret_cast<float *>(ws + oa);
+    float *pathp = reinterpret_cast<float *>(ws + op);
+    const int ntiles = g.nty * g.ntx;
+    const size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4, true);
+    const size_t lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4, true);
+    if (allow_lds(fwd_walk_absorb<1>, lds1) || allow_lds(fwd_walk_absorb<2>, lds2)) return D8_EHIP;
+    const unsigned nb = blocks_for(g.nnodes, kNodeBlock);
+    init_state<<<1, 1, 0, st>>>(status, jstate);
+    D8_LAUNCH("absorb_pass1", st,
+              (fwd_walk_absorb<1><<<ntiles, kTileThreads, lds1, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt,
+                                                                      acc, ext, nullptr, status, anode,
+                                                                      pathp)));
+    D8_LAUNCH("graph_build", st,
+              (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, 0, g.nnodes)));
+    D8_LAUNCH("absorb_resolve", st,
+              (resolve_fwd_f64<float, true><<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg,
+                                                                      cnt, acc, ext, anode, pathp)));
+    D8_LAUNCH("resolve_check", st,
+              (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, nullptr, cnt, status)));
+    D8_LAUNCH("absorb_pass2", st,
+              (fwd_walk_absorb<2><<<ntiles, kTileThreads, lds2, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt,
+                                                                      acc, ext, out, status, anode, pathp)));
+    return last_error();
+}
+
 // ------------------------------------------------------------------ batch --
 // A batch plan: rasters with cells, sorted by decreasing cell count (the
 // tile work queue hands out the largest rasters' tiles first), their
@@ -834,7 +884,41 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     return last_error();
 }
 
-// ---------------------------------------------------------------- batch --
+// ----------------------------------------------------------- absorption --
+
+size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols)
+{
+    Geo g;
+    bool empty;
+    if (check_common(rows, cols, tile_rows, tile_cols, g, empty) != D8_OK) return 0;
+    if (empty) return 512;
+    size_t a, p;
+    return absorb_extra(layout_for(g), g, a, p);
+}
+
+int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *alpha, float *acc,
+                      int64_t rows, int64_t cols, int tile_rows, int tile_cols, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    Geo g;
+    bool empty;
+    int rc = check_common(rows, cols, tile_rows, tile_cols, g, empty);
+    if (rc != D8_OK) return rc;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;
+    if (empty) {
+        if (ws_bytes < 512) return D8_EWORKSPACE;
+        init_state<<<1, 1, 0, as_stream(stream)>>>(reinterpret_cast<uint32_t *>(ws),
+                                                   reinterpret_cast<uint32_t *>((char *)ws + 256));
+        return last_error();
+    }
+    if (!dirs || !alpha || !acc) return D8_EINVAL;
+    const Layout L = layout_for(g);
+    size_t a, p;
+    if (ws_bytes < absorb_extra(L, g, a, p)) return D8_EWORKSPACE;
+    begin_call();
+    return run_forward_absorb(dirs, weights, alpha, acc, g, reinterpret_cast<char *>(ws), L,
+                              as_stream(stream));
+}
 
 size_t d8_stream_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols,
                                  int64_t band_rows)

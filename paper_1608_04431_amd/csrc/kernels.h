@@ -342,24 +342,31 @@ __global__ void resolve_fwd_u32(int64_t nnodes, const uint16_t *__restrict__ lin
 // access to acc and cnt is an atomic (performed where all XCDs see it), and
 // a child counts its arrival only after its add has returned, so the last
 // child's atomic read of acc sees every child's sum -- no cache-wide fences.
-template <typename T>
+// ABS (absorption): exit u sends alpha(u) A(u) into its entry n, and that
+// reaches n's exit s multiplied by the path product of n (anode, pathp).
+template <typename T, bool ABS = false>
 __global__ void resolve_fwd_f64(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
                                 const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
                                 const uint32_t *__restrict__ indeg, uint32_t *cnt, double *acc,
-                                double *ext)
+                                double *ext, const float *__restrict__ anode = nullptr,
+                                const float *__restrict__ pathp = nullptr)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nnodes) return;
     if (link[id] != kLinkExt || indeg[id] != 0) return;
     double v = (double)aloc[id];
     uint32_t n = entry[id], s = succ[id];
+    float au = ABS ? anode[id] : 1.0f;
     for (;;) {
         if (n == kNone) break;
-        atomicAdd(&ext[n], v);
+        const double o = ABS ? (double)au * v : v;
+        atomicAdd(&ext[n], o);
         if (s == kNone) break;
         const double as = (double)aloc[s];
         const uint32_t is = indeg[s], ns = entry[s], ss = succ[s];
-        const double before = atomicAdd(&acc[s], v);
+        const double c = ABS ? o * (double)pathp[n] : o;
+        if constexpr (ABS) au = anode[s];
+        const double before = atomicAdd(&acc[s], c);
         uint32_t one = 1u;
         asm volatile("" : "+v"(one) : "v"(before));  // the count waits for the add
         const uint32_t old = atomicAdd(&cnt[s], one);

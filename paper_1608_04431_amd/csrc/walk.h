@@ -526,9 +526,12 @@ __device__ inline uint16_t link_of(const WTile &Tl, uint16_t v, uint32_t *status
 // of a frame column (row lane % h, column -1), which nothing reads.  Only the
 // confluence step branches.  SEED: 0 = seeds are read from avp at a claim
 // (the read completes with the step's reads), 1 = every seed is 1.
-template <typename VT, int SEED>
+// ABS (absorption, Eq. (1) with alpha(n, p) = alpha(n) in [0, 1]): a walker
+// passes alpha(cur) A(cur) on; alp holds alpha per cell, laid out like avp.
+template <typename VT, int SEED, bool ABS = false>
 __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, uint32_t *cbw, VT *avp,
-                                uint32_t *q, uint32_t qcap, uint64_t src, uint64_t noflow)
+                                uint32_t *q, uint32_t qcap, uint64_t src, uint64_t noflow,
+                                const float *alp = nullptr)
 {
     using T = typename Acc<VT>::type;
     const int S = Tl.S;
@@ -582,19 +585,25 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
         const uint32_t nb = cb8[ni];
         T sv = (T)avp[ni];
         keep_read(sv);
+        T al = (T)1;
+        if constexpr (ABS) {
+            al = (T)alp[base];
+            keep_read(al);
+        }
         keep_read(a0);
         a = took ? a0 : a;
+        const T out = ABS ? al * a : a;  // what reaches the next cell
         const uint32_t nk = nb & 15u;
         const bool fw = act && nk < (uint32_t)kNoData;
         const bool plain = fw && nb < 16u;
-        const T ap = a + sv;
+        const T ap = out + sv;
         *(plain ? &avp[ni] : mine) = (VT)ap;
         bool last = false;
         if (fw && nb >= 16u) {
             // confluence: add this donor's total, count the arrival; the
             // last donor to arrive continues with the cell's total
             const int sh = 8 * (ni & 3) + 4;
-            lds_add(lds8, &avp[ni], a);
+            lds_add(lds8, &avp[ni], out);
             const uint32_t old = atomicSub(&cbw[ni >> 2], 1u << sh);
             last = ((old >> sh) & 15u) == 1u;
             if (last) a = (T)avp[ni];
@@ -615,8 +624,12 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
 // steps than the tile has cells.  Only the low nibble (the code) of each
 // cell byte is read.  Offsets as in fwd_walks; an idle lane steps to frame
 // cell 0 and writes ll[ll_dummy].
+// ABS: also the product of alpha over each entry's path up to (without) its
+// exit, stored to pathp[node] (global) for the entry's node.
+template <bool ABS = false>
 __device__ inline void link_walks(const WTile &Tl, const uint8_t *cb8, uint32_t *q, uint32_t qcap,
-                                  uint64_t ent, uint16_t *ll, int ll_dummy)
+                                  uint64_t ent, uint16_t *ll, int ll_dummy, const float *alp = nullptr,
+                                  float *pathp = nullptr)
 {
     const uint32_t s8 = (uint32_t)Tl.S;
     const uint32_t lut_lo = (128u - s8 - 1u) | ((128u - s8) << 8) | ((128u - s8 + 1u) << 16) | (127u << 24);
@@ -627,6 +640,7 @@ __device__ inline void link_walks(const WTile &Tl, const uint8_t *cb8, uint32_t 
     bool more = __ballot(ent != 0) != 0;
     int cur = -1, steps = 0, ring = ll_dummy;
     uint32_t code = 12u;
+    float p = 1.0f;
     const int max_steps = Tl.h * Tl.w;
     for (;;) {
         const uint64_t idle = __ballot(cur < 0);
@@ -647,17 +661,25 @@ __device__ inline void link_walks(const WTile &Tl, const uint8_t *cb8, uint32_t 
             code = take ? ((t >> kQByte) & 15u) : code;
             ring = take ? (int)(t >> kQRing) : ring;
             steps = take ? 0 : steps;
+            p = take ? 1.0f : p;
             const uint32_t nidle = (uint32_t)__popcll(idle);
             head = (ntask - head < nidle) ? ntask : head + nidle;
         }
         const bool act = cur >= 0;
         const uint32_t sel = act ? code : 12u;
-        const int ni = (act ? cur : 128) + (int)__builtin_amdgcn_perm(lut_hi, lut_lo, 0x0C0C0C00u | sel) - 128;
+        const int base = act ? cur : 128;
+        const int ni = base + (int)__builtin_amdgcn_perm(lut_hi, lut_lo, 0x0C0C0C00u | sel) - 128;
         const uint32_t nk = cb8[ni] & 15u;
+        float al = 1.0f;
+        if constexpr (ABS) al = alp[base];
         ++steps;
         const bool stop = nk >= (uint32_t)kNoFlow || steps > max_steps;
         const uint16_t v = steps > max_steps ? kLlCycle : (nk == kFrameTile ? (uint16_t)cur : kLlTerm);
         ll[(act && stop) ? ring : ll_dummy] = v;
+        if constexpr (ABS) {
+            if (act && stop) pathp[Tl.base + ring] = p;
+            p *= al;
+        }
         cur = (act && !stop) ? ni : -1;
         code = nk;
     }
@@ -845,7 +867,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
 // value reads of frame rows land in the cell bytes (before) or the queue
 // (after), both at least 4 (S + 1) bytes long.
 struct WLayout {
-    int av, q, tail, total;
+    int av, al, q, tail, total;
     uint32_t qcap;
 };
 
@@ -855,14 +877,17 @@ using FwdLds = typename std::conditional<PASS == 1 && std::is_same<T, uint32_t>:
 
 enum WalkKind { kWalkFwd1 = 0, kWalkFwd2 = 1, kWalkAdj1 = 2, kWalkAdj2 = 3 };
 
-__host__ __device__ inline WLayout walk_layout(int th, int tw, int kind, int vbytes = 4)
+__host__ __device__ inline WLayout walk_layout(int th, int tw, int kind, int vbytes = 4,
+                                               bool absorb = false)
 {
     WLayout L;
     const int S = tw + 2;
     int cb = (th + 2) * S;
     if (cb < 4 * (S + 1)) cb = 4 * (S + 1);
     L.av = (cb + 15) & ~15;
-    L.q = L.av + ((th * S * vbytes + 15) & ~15);
+    // absorption: each cell's alpha after the values, laid out like them
+    L.al = L.av + ((th * S * vbytes + 15) & ~15);
+    L.q = absorb ? L.al + ((th * S * 4 + 15) & ~15) : L.al;
     // queue entries: the adjoint's queue also takes side donors as walks
     // branch (256 keep overflow rare); forward queues hold start cells and
     // are refilled from the lanes' masks when empty
@@ -1034,18 +1059,21 @@ __device__ inline void bytes_out(const wk::WTile &Tl, const Geo &g, const uint8_
 // Resolve state: indeg = children in the exit forest (graph_build); unit
 // counts keep (inflow sum << 32 | arrivals) in acc; float weights keep the
 // double sum in acc and arrivals in cnt.
-template <int PASS, typename T, typename V, typename E>
+template <int PASS, typename T, typename V, typename E, bool ABS = false>
 __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ w,
                                 const Geo &g, int64_t node0, int t, uint16_t *__restrict__ link,
                                 T *__restrict__ aloc, uint32_t *__restrict__ indeg,
                                 uint32_t *__restrict__ cnt, V *__restrict__ acc, E *__restrict__ ext,
-                                T *__restrict__ out, uint32_t *status, uint8_t *lds8)
+                                T *__restrict__ out, uint32_t *status, uint8_t *lds8,
+                                const float *__restrict__ alpha = nullptr, float *anode = nullptr,
+                                float *pathp = nullptr)
 {
     using namespace wk;
     WTile Tl = wtile_of(g, t);
     Tl.base += node0;
     using VT = FwdLds<PASS, T>;
-    const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkFwd1 : kWalkFwd2, (int)sizeof(VT));
+    const WLayout L = walk_layout(g.th, g.tw, PASS == 1 ? kWalkFwd1 : kWalkFwd2, (int)sizeof(VT), ABS);
+    float *alp = reinterpret_cast<float *>(lds8 + L.al) - Tl.S;  // ABS only
     uint8_t *cb8 = lds8;
     uint32_t *cbw = reinterpret_cast<uint32_t *>(lds8);
     VT *avp = reinterpret_cast<VT *>(lds8 + L.av) - Tl.S;
@@ -1062,6 +1090,7 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
     } else {
         rows_fill(Tl, avp, (VT)1);
     }
+    if constexpr (ABS) rows_in(Tl, g, alp, alpha);
     if constexpr (PASS == 2) {
         __syncthreads();
         // all of a lane's loads first (a ring has at most 4 x 64 cells)
@@ -1088,12 +1117,12 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
     // unit weights (uint32 counts): every seed is 1 in pass 1, and 1 plus the
     // resolved inflow on the perimeter in pass 2
     constexpr int kSeed = (std::is_same<T, uint32_t>::value && PASS == 1) ? 1 : 0;
-    int visited = fwd_walks<VT, kSeed>(Tl, lds8, cb8, cbw, avp, q, L.qcap, St.src, St.noflow);
+    int visited = fwd_walks<VT, kSeed, ABS>(Tl, lds8, cb8, cbw, avp, q, L.qcap, St.src, St.noflow, alp);
     if (wave_sum(visited) != wave_sum(__popcll(St.valid)) && lane == 0) set_status(status, kStatusCycle);
     __syncthreads();
     // Algorithm 2's links of the entries (NoFlow entries keep kLlTerm)
     if constexpr (PASS == 1) {
-        link_walks(Tl, cb8, q, L.qcap, St.entry & ~St.noflow, ll, Tl.P);
+        link_walks<ABS>(Tl, cb8, q, L.qcap, St.entry & ~St.noflow, ll, Tl.P, alp, pathp);
         __syncthreads();
     }
 
@@ -1114,6 +1143,7 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
         int64_t id = Tl.base + p;
         link[id] = Lk;
         aloc[id] = k < (uint32_t)kNoData ? (T)avp[idx] : (T)0;
+        if constexpr (ABS) anode[id] = alp[idx];
         indeg[id] = 0;
         if (cnt) cnt[id] = 0;
         acc[id] = (V)0;
@@ -1296,6 +1326,22 @@ fwd_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ w, Geo g,
                             acc, ext, out, status, lds8);
 }
 
+// Forward passes with absorption (float weights): alpha per cell, and per
+// perimeter node its alpha (anode) and an entry's path product (pathp).
+template <int PASS>
+__global__ void __launch_bounds__(64)
+fwd_walk_absorb(const uint8_t *__restrict__ dirs, const float *__restrict__ w,
+                const float *__restrict__ alpha, Geo g, uint16_t *__restrict__ link,
+                float *__restrict__ aloc, uint32_t *__restrict__ indeg, uint32_t *__restrict__ cnt,
+                double *__restrict__ acc, double *__restrict__ ext, float *__restrict__ out,
+                uint32_t *status, float *anode, float *pathp)
+{
+    extern __shared__ __align__(16) uint8_t lds8[];
+    fwd_tile<PASS, float, double, double, true>(dirs, w, g, 0, xcd_tile(blockIdx.x, gridDim.x), link,
+                                                aloc, indeg, cnt, acc, ext, out, status, lds8, alpha,
+                                                anode, pathp);
+}
+
 __global__ void __launch_bounds__(64, 3)
 adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
          uint16_t *__restrict__ link, float *__restrict__ Sg, float *__restrict__ out,
@@ -1363,9 +1409,9 @@ adj_finish_batch(const DemDesc *__restrict__ dems, const uint32_t *__restrict__ 
     adj_finish_tile(D.g, D.node0, (int)(t - D.tile0), D.root8, cmap, mu, D.gw, mu_l);
 }
 
-__host__ inline size_t walk_lds_bytes(int th, int tw, int kind, int vbytes = 4)
+__host__ inline size_t walk_lds_bytes(int th, int tw, int kind, int vbytes = 4, bool absorb = false)
 {
-    return (size_t)walk_layout(th, tw, kind, vbytes).total;
+    return (size_t)walk_layout(th, tw, kind, vbytes, absorb).total;
 }
 
 

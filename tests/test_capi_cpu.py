@@ -98,6 +98,22 @@ def test_stream_workspace_and_argument_errors():
     assert lib.flow_accum_streamed(fake, fake, 1000, 300, 64, 48, 128, odd, n, None) == EWS
 
 
+def test_absorb_workspace_and_argument_errors():
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x1000)
+    n = lib.d8_absorb_workspace_bytes(1000, 300, 64, 48)
+    assert n > lib.d8_workspace_bytes(1000, 300, 64, 48)      # alpha path products per node
+    assert lib.d8_absorb_workspace_bytes(1000, 300, 64, -1) == 0
+    assert lib.d8_absorb_workspace_bytes(0, 300, 64, 48) == 512
+    EINVAL, EWS = _lib.D8_EINVAL, _lib.D8_EWORKSPACE
+    assert lib.flow_accum_absorb(fake, None, None, fake, 1000, 300, 64, 48, fake, n, None) == EINVAL
+    assert lib.flow_accum_absorb(None, None, fake, fake, 1000, 300, 64, 48, fake, n, None) == EINVAL
+    assert lib.flow_accum_absorb(fake, None, fake, fake, 1000, 300, 64, -1, fake, n, None) == EINVAL
+    assert lib.flow_accum_absorb(fake, None, fake, fake, 1000, 300, 64, 48, fake, n - 1, None) == EWS
+    odd = ctypes.c_void_p(0x1000 + 8)
+    assert lib.flow_accum_absorb(fake, None, fake, fake, 1000, 300, 64, 48, odd, n, None) == EWS
+
+
 def test_batch_argument_errors_return_before_launch():
     lib = _lib.load()
     fake = 0x1000

@@ -1,0 +1,83 @@
+"""Flow accumulation with absorption (flow_accum_absorb) against the oracle's
+Eq. (1) with alpha per cell: float32 within the float32 parity bound of the
+float64 oracle, over tile shapes across edges and corners, alpha = 1 (equal
+to flow_accum f32) and alpha = 0 (A = w)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+F32_RTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def d8m():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    import paper_1608_04431_amd as m
+    m._lib.load()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def random_acyclic_dirs(rows, cols, seed, nodata_frac=0.1, noflow_frac=0.02):
+    rng = np.random.default_rng(seed)
+    z = rng.permutation(rows * cols).astype(np.float32).reshape(rows, cols)
+    z[rng.random((rows, cols)) < nodata_frac] = -9999.0
+    d = oracle.d8(z)
+    d[(rng.random((rows, cols)) < noflow_frac) & (d != 9)] = 8
+    return d
+
+
+def assert_rel(got, want, valid):
+    got = got.astype(np.float64)
+    pos = valid & (want > 0)
+    rel = np.abs(got[pos] - want[pos]) / want[pos]
+    assert rel.size == 0 or rel.max() <= F32_RTOL, f"max rel err {rel.max():.3e}"
+    assert (got[~valid] == 0).all()
+
+
+@pytest.mark.parametrize("shape,tile", [((300, 257), (32, 32)), ((130, 200), (64, 48)),
+                                        ((97, 64), (16, 64)), ((200, 131), (64, 64))])
+def test_absorb_matches_oracle(d8m, shape, tile):
+    cases = [random_acyclic_dirs(*shape, seed=sum(shape)),
+             oracle.d8(synth.dem(*shape, seed=13, lambda0=32, ocean=True))]
+    for i, d in enumerate(cases):
+        alpha = (0.5 + 0.5 * synth.uniform(d.shape, 70 + i)).astype(np.float32)  # [0.5, 1)
+        w = synth.uniform(d.shape, 80 + i)
+        want = oracle.accum_absorb_f64(d, alpha, w)
+        got = d8m.flow_accum_absorb(dev(d), dev(alpha), dev(w), tile=tile).cpu().numpy()
+        assert_rel(got, want, d != 9)
+        got1 = d8m.flow_accum_absorb(dev(d), dev(alpha), None, tile=tile).cpu().numpy()
+        assert_rel(got1, oracle.accum_absorb_f64(d, alpha), d != 9)
+
+
+def test_absorb_special_alphas(d8m):
+    z = synth.workload_dem("dem512")
+    d = oracle.d8(z)
+    w = synth.uniform(d.shape, 3)
+    one = np.ones(d.shape, np.float32)
+    got = d8m.flow_accum_absorb(dev(d), dev(one), dev(w), tile=(64, 48)).cpu().numpy()
+    ref = d8m.flow_accum(dev(d), dev(w), acc_type="f32", tile=(64, 48)).cpu().numpy()
+    assert_rel(got, ref.astype(np.float64), d != 9)
+    zero = np.zeros(d.shape, np.float32)
+    got = d8m.flow_accum_absorb(dev(d), dev(zero), dev(w), tile=(64, 48)).cpu().numpy()
+    np.testing.assert_array_equal(got, np.where(d != 9, w, 0).astype(np.float32))
+    alpha = synth.uniform(d.shape, 4)                                        # [0, 1)
+    got = d8m.flow_accum_absorb(dev(d), dev(alpha), dev(w), tile=(64, 48)).cpu().numpy()
+    assert_rel(got, oracle.accum_absorb_f64(d, alpha, w), d != 9)
+
+
+def test_absorb_empty_and_single_tile(d8m):
+    e = torch.empty((0, 5), dtype=torch.uint8, device="cuda")
+    assert d8m.flow_accum_absorb(e, torch.empty((0, 5), device="cuda")).shape == (0, 5)
+    d = random_acyclic_dirs(5, 7, seed=2, nodata_frac=0.0)
+    alpha = synth.uniform(d.shape, 5)
+    got = d8m.flow_accum_absorb(dev(d), dev(alpha)).cpu().numpy()
+    assert_rel(got, oracle.accum_absorb_f64(d, alpha), d != 9)
