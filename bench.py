@@ -37,6 +37,7 @@ KERNEL_BYTES_PER_CELL = {
     "adj_pass2": 4.0,   # lambda
     "d8_directions": 5.0,
     "d8_directions_rho8": 9.0,  # z 4 + r 4 + code 1
+    "flow_accum_absorb": 13.0,  # code 1 + alpha 4 + w 4 read, A 4 written
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
 SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (56, 48), (48, 64), (48, 48), (32, 64))
@@ -322,6 +323,8 @@ def main():
                     help="rows per band of the streamed leg (0 = the library's default)")
     ap.add_argument("--no-stream", action="store_true",
                     help="skip the streamed leg (raster in pinned host memory)")
+    ap.add_argument("--no-absorb", action="store_true",
+                    help="skip the timing of accumulation with absorption")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB before timing (a kernel of known "
                          "traffic for scaling hardware counters)")
@@ -345,6 +348,34 @@ def main():
         if bd is not None:
             bd.close()
     print(json.dumps(out), flush=True)
+
+
+def absorb_leg(d8, dirs, w, tile, seed, reps=3):
+    """Eq. (1) with absorption on the same directions: alpha ~ U[0.5, 1) per
+    cell, the adjoint's U[0, 1) draws as weights; events around `reps` calls
+    after one warm call, on the launch stream."""
+    import torch
+    rows, cols = dirs.shape
+    alpha = torch.from_numpy(0.5 + 0.5 * synth.uniform((rows, cols), seed)).to(dirs.device)
+    ws = torch.empty(d8._lib.load().d8_absorb_workspace_bytes(rows, cols, *tile), dtype=torch.uint8,
+                     device=dirs.device)
+    out = torch.empty((rows, cols), dtype=torch.float32, device=dirs.device)
+    d8.flow_accum_absorb(dirs, alpha, w, tile=tile, ws=ws, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        d8.flow_accum_absorb(dirs, alpha, w, tile=tile, ws=ws, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbps = KERNEL_BYTES_PER_CELL["flow_accum_absorb"] * rows * cols / (ms * 1e-3) / 1e9
+    log(f"flow_accum_absorb: {ms:.3f} ms, {gbps:.0f} GB/s algorithmic")
+    del alpha, ws, out
+    torch.cuda.empty_cache()
+    return {"ms": round(ms, 4), "cells_per_s": rows * cols / (ms * 1e-3),
+            "bytes_per_cell": KERNEL_BYTES_PER_CELL["flow_accum_absorb"], "achieved_GBps": gbps,
+            "frac_hbm_peak": gbps / HBM_PEAK_GBPS, "alpha": "U[0.5,1) per cell", "weights": "U[0,1)"}
 
 
 def streamed_leg(d8, dirs, A, tile, band_rows, reps=3):
@@ -502,6 +533,10 @@ def run(args, bd):
                         note="latency-bound graph kernel: no per-cell byte model")
     step_gbps = STEP_BYTES_PER_CELL * n_cells / (ms_step * 1e-3) / 1e9
 
+    absorb = None
+    if not args.no_absorb:
+        absorb = absorb_leg(d8, dirs, g, tile, wl.get("seed_g", 31) + 1)
+
     streamed = None
     if not args.no_stream:
         streamed = streamed_leg(d8, dirs, A, tile, args.stream_band)
@@ -540,6 +575,7 @@ def run(args, bd):
         "d8_directions_rho8": {"ms": round(rho8_ms, 4),
                                "bytes_per_cell": KERNEL_BYTES_PER_CELL["d8_directions_rho8"],
                                "achieved_GBps": rho8_gbps, "frac_hbm_peak": rho8_gbps / HBM_PEAK_GBPS},
+        "absorb": absorb,
         "streamed": streamed,
         "cpu_baseline": cpu,
     }
