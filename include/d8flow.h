@@ -169,6 +169,23 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
  * holds alpha besides the values, so large tiles run fewer per CU.
  */
 size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols);
+
+/*
+ * Adjoint of flow_accum_absorb with respect to the weights:
+ * lambda(c) = g(c) + alpha(c) lambda(receiver(c)) (0 beyond a cell without a
+ * receiver), i.e. lambda = (I - P_alpha)^-T g for the absorbing transfer
+ * matrix P_alpha of Eq. (1).  Not in the paper; the same tiles as
+ * flow_accum_adjoint, with each cell's in-tile alpha product carried to the
+ * exit-level resolve, which composes affine maps by pointer jumping.
+ *
+ * dirs, alpha as for flow_accum_absorb; grad_acc: float32 g; grad_weights:
+ * float32 lambda (out), 0 on NoData cells.  ws: at least
+ * d8_absorb_workspace_bytes(...) (256-byte aligned; the forward and the
+ * adjoint take the same size).  Returns as for flow_accum_adjoint.
+ */
+int flow_accum_absorb_adjoint(const uint8_t *dirs, const float *alpha, const float *grad_acc,
+                              float *grad_weights, int64_t rows, int64_t cols, int tile_rows, int tile_cols,
+                              void *ws, size_t ws_bytes, void *stream);
 int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *alpha, float *acc,
                       int64_t rows, int64_t cols, int tile_rows, int tile_cols, void *ws, size_t ws_bytes,
                       void *stream);

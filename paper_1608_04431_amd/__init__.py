@@ -18,7 +18,8 @@ NODATA = 9
 
 __all__ = ["d8_directions", "d8_directions_rho8", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
            "check_status", "FlowAccum", "D8Error", "Raster", "Batch", "BatchGraph",
-           "stream_workspace_bytes", "flow_accum_streamed", "flow_accum_absorb"]
+           "stream_workspace_bytes", "flow_accum_streamed", "flow_accum_absorb",
+           "flow_accum_absorb_adjoint"]
 
 
 def _stream(device: torch.device) -> int:
@@ -165,6 +166,32 @@ def flow_accum_absorb(dirs: torch.Tensor, alpha: torch.Tensor, weights: torch.Te
     rc = _lib.load().flow_accum_absorb(_ptr(dirs), _ptr(weights), _ptr(alpha), _ptr(out), rows, cols,
                                        tile[0], tile[1], _ptr(ws), ws.numel(), _stream(dirs.device))
     _lib.check(rc, "flow_accum_absorb")
+    _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(dirs.device)), "status")
+    return out
+
+
+def flow_accum_absorb_adjoint(dirs: torch.Tensor, alpha: torch.Tensor, grad: torch.Tensor,
+                              tile: tuple[int, int] = (0, 0), ws: torch.Tensor | None = None,
+                              out: torch.Tensor | None = None) -> torch.Tensor:
+    """lambda(c) = g(c) + alpha(c) lambda(receiver(c)), float32 (see
+    flow_accum_absorb_adjoint in d8flow.h)."""
+    _check_raster(dirs, torch.uint8, "dirs")
+    for t, name in ((alpha, "alpha"), (grad, "grad")):
+        _check_raster(t, torch.float32, name)
+        if t.shape != dirs.shape:
+            raise ValueError(f"{name} and dirs differ in shape")
+    rows, cols = dirs.shape
+    n = _lib.load().d8_absorb_workspace_bytes(rows, cols, tile[0], tile[1])
+    if n == 0:
+        raise D8Error(_lib.D8_EINVAL, f"tile {tile} for {rows}x{cols}")
+    if ws is None:
+        ws = torch.empty(n, dtype=torch.uint8, device=dirs.device)
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float32, device=dirs.device)
+    _check_raster(out, torch.float32, "out")
+    rc = _lib.load().flow_accum_absorb_adjoint(_ptr(dirs), _ptr(alpha), _ptr(grad), _ptr(out), rows, cols,
+                                               tile[0], tile[1], _ptr(ws), ws.numel(), _stream(dirs.device))
+    _lib.check(rc, "flow_accum_absorb_adjoint")
     _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(dirs.device)), "status")
     return out
 

@@ -139,6 +139,20 @@ inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block 
 // the convergence check.  bsum takes one word per 4096 nodes, cmap one per
 // node; the sums end in jw[jstate[0]] at the exits' dense numbers.  Returns
 // the number of rounds.
+// Dense numbers of the exits among the N perimeter nodes: cmap (node ->
+// number), inv (number -> node), *nexit.
+void compact_exits(hipStream_t st, int64_t N, const uint16_t *link, uint32_t *bsum, uint32_t *cmap,
+                   uint32_t *inv, uint32_t *nexit, bool batch)
+{
+#define CNAME (batch ? "batch_adj_compact" : "adj_compact")
+    const int64_t ncb = (N + kCompactNodes - 1) / kCompactNodes;
+    D8_LAUNCH(CNAME, st, (adj_compact_count<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum)));
+    D8_LAUNCH(CNAME, st, (adj_compact_scan<<<1, 1024, 0, st>>>(ncb, bsum, nexit)));
+    D8_LAUNCH(CNAME, st,
+              (adj_compact_map<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum, cmap, inv)));
+#undef CNAME
+}
+
 int jump_exits(hipStream_t st, int64_t N, const JumpGraph &G, const uint16_t *link, const float *S,
                uint32_t *bsum, uint32_t *cmap, unsigned long long *const jw[2], uint32_t *jstate,
                uint32_t *status, bool batch)
@@ -146,15 +160,10 @@ int jump_exits(hipStream_t st, int64_t N, const JumpGraph &G, const uint16_t *li
     // timing labels are kept by pointer: literals only
 #define JNAME(s) (batch ? "batch_" s : s)
     uint32_t *nexit = jstate + 4;
-    const int64_t ncb = (N + kCompactNodes - 1) / kCompactNodes;
-    D8_LAUNCH(JNAME("adj_compact"), st,
-              (adj_compact_count<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum)));
-    D8_LAUNCH(JNAME("adj_compact"), st, (adj_compact_scan<<<1, 1024, 0, st>>>(ncb, bsum, nexit)));
     // inv (dense index -> node) lives in jw[1] until round 0 overwrites it
     uint32_t *inv = reinterpret_cast<uint32_t *>(jw[1]);
+    compact_exits(st, N, link, bsum, cmap, inv, nexit, batch);
     const unsigned jb = std::min<unsigned>(blocks_for(N, 2 * kNodeBlock), 4096u);
-    D8_LAUNCH(JNAME("adj_compact"), st,
-              (adj_compact_map<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, link, bsum, cmap, inv)));
     D8_LAUNCH(JNAME("adj_jump_init"), st,
               (adj_jump_init<<<jb, kNodeBlock, 0, st>>>(nexit, inv, G, link, S, cmap, jw[0])));
     int rounds = 1;
@@ -271,18 +280,31 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
 // Forward with absorption (float weights): the float path with each cell's
 // alpha in the tile passes and per-node coefficients in the resolve.  The
 // workspace is the one-raster layout plus anode and pathp (a float per node).
-size_t absorb_extra(const Layout &L, const Geo &g, size_t &anode, size_t &pathp)
+// Absorption's areas after the common layout: per perimeter node its alpha
+// (anode, forward) and its path product (pathp: an entry's product in the
+// forward pass, every node's P in the adjoint); the adjoint's second buffer
+// of 16-byte exit words (the first takes acc64 and ext64, which are
+// contiguous and at least 16 bytes per node) and P per cell.
+struct AbsorbLayout {
+    size_t anode, pathp, jw, pcell, total;
+};
+
+AbsorbLayout absorb_layout(const Layout &L, const Geo &g)
 {
-    anode = align256(L.total);
-    pathp = align256(anode + (size_t)g.nnodes * sizeof(float));
-    return align256(pathp + (size_t)g.nnodes * sizeof(float));
+    const size_t N = (size_t)g.nnodes;
+    AbsorbLayout A;
+    A.anode = align256(L.total);
+    A.pathp = align256(A.anode + N * sizeof(float));
+    A.jw = align256(A.pathp + N * sizeof(float));
+    A.pcell = align256(A.jw + N * sizeof(uint4));
+    A.total = align256(A.pcell + (size_t)g.rows * (size_t)g.cols * sizeof(float));
+    return A;
 }
 
 int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, float *out, const Geo &g,
                        char *ws, const Layout &L, hipStream_t st)
 {
-    size_t oa, op;
-    absorb_extra(L, g, oa, op);
+    const AbsorbLayout A = absorb_layout(L, g);
     uint32_t *status = reinterpret_cast<uint32_t *>(ws + L.status);
     uint32_t *jstate = reinterpret_cast<uint32_t *>(ws + L.jstate);
     uint16_t *link = reinterpret_cast<uint16_t *>(ws + L.link);
@@ -293,8 +315,8 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
     float *aloc = reinterpret_cast<float *>(ws + L.val32);
     double *acc = reinterpret_cast<double *>(ws + L.acc64);
     double *ext = reinterpret_cast<double *>(ws + L.ext64);
-    float *anode = reinterpret_cast<float *>(ws + oa);
-    float *pathp = reinterpret_cast<float *>(ws + op);
+    float *anode = reinterpret_cast<float *>(ws + A.anode);
+    float *pathp = reinterpret_cast<float *>(ws + A.pathp);
     const int ntiles = g.nty * g.ntx;
     const size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4, true);
     const size_t lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4, true);
@@ -892,8 +914,7 @@ size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int 
     bool empty;
     if (check_common(rows, cols, tile_rows, tile_cols, g, empty) != D8_OK) return 0;
     if (empty) return 512;
-    size_t a, p;
-    return absorb_extra(layout_for(g), g, a, p);
+    return absorb_layout(layout_for(g), g).total;
 }
 
 int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *alpha, float *acc,
@@ -913,11 +934,70 @@ int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *al
     }
     if (!dirs || !alpha || !acc) return D8_EINVAL;
     const Layout L = layout_for(g);
-    size_t a, p;
-    if (ws_bytes < absorb_extra(L, g, a, p)) return D8_EWORKSPACE;
+    if (ws_bytes < absorb_layout(L, g).total) return D8_EWORKSPACE;
     begin_call();
     return run_forward_absorb(dirs, weights, alpha, acc, g, reinterpret_cast<char *>(ws), L,
                               as_stream(stream));
+}
+
+int flow_accum_absorb_adjoint(const uint8_t *dirs, const float *alpha, const float *grad_acc,
+                              float *grad_weights, int64_t rows, int64_t cols, int tile_rows, int tile_cols,
+                              void *ws, size_t ws_bytes, void *stream)
+{
+    Geo g;
+    bool empty;
+    int rc = check_common(rows, cols, tile_rows, tile_cols, g, empty);
+    if (rc != D8_OK) return rc;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;
+    hipStream_t st = as_stream(stream);
+    if (empty) {
+        if (ws_bytes < 512) return D8_EWORKSPACE;
+        init_state<<<1, 1, 0, st>>>(reinterpret_cast<uint32_t *>(ws),
+                                    reinterpret_cast<uint32_t *>((char *)ws + 256));
+        return last_error();
+    }
+    if (!dirs || !alpha || !grad_acc || !grad_weights) return D8_EINVAL;
+    const Layout L = layout_for(g);
+    const AbsorbLayout A = absorb_layout(L, g);
+    if (ws_bytes < A.total) return D8_EWORKSPACE;
+    char *w8 = reinterpret_cast<char *>(ws);
+    uint32_t *status = reinterpret_cast<uint32_t *>(w8 + L.status);
+    uint32_t *jstate = reinterpret_cast<uint32_t *>(w8 + L.jstate);
+    uint16_t *link = reinterpret_cast<uint16_t *>(w8 + L.link);
+    float *S = reinterpret_cast<float *>(w8 + L.val32);
+    float *P = reinterpret_cast<float *>(w8 + A.pathp);
+    float *pcell = reinterpret_cast<float *>(w8 + A.pcell);
+    uint8_t *root8 = reinterpret_cast<uint8_t *>(w8 + L.root8);
+    uint32_t *cmap = reinterpret_cast<uint32_t *>(w8 + L.ptr2);
+    uint32_t *bsum = reinterpret_cast<uint32_t *>(w8 + L.indeg);
+    uint4 *jw[2] = {reinterpret_cast<uint4 *>(w8 + L.acc64), reinterpret_cast<uint4 *>(w8 + A.jw)};
+    uint32_t *nexit = jstate + 4;
+    const int ntiles = g.nty * g.ntx;
+    const size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1, 4, true);
+    begin_call();
+    if (allow_lds(adj_walk_absorb, lds1)) return D8_EHIP;
+    init_state<<<1, 1, 0, st>>>(status, jstate);
+    D8_LAUNCH("absorb_adj_pass1", st,
+              (adj_walk_absorb<<<ntiles, kTileThreads, lds1, st>>>(dirs, grad_acc, alpha, g, link, S, P,
+                                                                   grad_weights, pcell, root8, status)));
+    // inv (dense index -> node) lives in jw[1] until round 0 overwrites it
+    uint32_t *inv = reinterpret_cast<uint32_t *>(jw[1]);
+    compact_exits(st, g.nnodes, link, bsum, cmap, inv, nexit, false);
+    const unsigned jb = std::min<unsigned>(blocks_for(g.nnodes, 2 * kNodeBlock), 4096u);
+    const JumpGraph G{dirs, g, nullptr, 0, nullptr};
+    D8_LAUNCH("absorb_jump_init", st,
+              (adj_jump_init_absorb<<<jb, kNodeBlock, 0, st>>>(nexit, inv, G, link, S, P, cmap, jw[0])));
+    int rounds = 1;
+    while (((int64_t)1 << (rounds - 1)) <= g.nnodes) ++rounds;
+    for (int r = 0; r < rounds; ++r)
+        D8_LAUNCH("absorb_jump_round", st,
+                  (adj_jump_round_absorb<<<jb, kNodeBlock, 0, st>>>(nexit, jw[r & 1], jw[(r + 1) & 1], jstate,
+                                                                    r)));
+    D8_LAUNCH("adj_jump_finish", st, (adj_jump_finish<<<1, 1, 0, st>>>(jstate, rounds, status)));
+    D8_LAUNCH("absorb_adj_pass2", st,
+              (adj_finish_absorb<<<ntiles, kTileThreads, 0, st>>>(g, root8, cmap, jw[0], jw[1], jstate, pcell,
+                                                                 grad_weights)));
+    return last_error();
 }
 
 size_t d8_stream_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols,

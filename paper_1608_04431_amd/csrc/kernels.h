@@ -21,6 +21,8 @@
 //   adj_jump_*        each exit's edge (as graph_build finds it), then the
 //                     downstream sums over the exit forest by pointer jumping;
 //   adj_finish        lambda = lambda_loc + the sum of the cell's root exit.
+// With absorption (Eq. (1) with alpha(n) in [0, 1]) the same stages carry
+// the product of alpha along paths: *_absorb kernels here and in walk.h.
 // D8 directions (and rho8's): d8_kernel.
 #pragma once
 #include "d8_common.h"
@@ -636,6 +638,65 @@ adj_jump_round(const uint32_t *__restrict__ nexit, unsigned long long *w_in,
                 alive |= np != kNone;
                 w_out[j] = jump_word(np, jump_val(w2) + jump_val(t2));
             }
+        }
+    }
+    if (__ballot(alive) != 0 && (threadIdx.x & 63) == 0) live[round % 3] = 1;
+}
+
+// With absorption, mu(e) = S(entry(e)) + P(entry(e)) mu(succ(e)): an affine
+// chain.  Words of 16 bytes: pointer, sum a and product b, with
+// mu(e) = a + b mu(pointer); a round composes a word with its pointer's
+// word, (a, b) o (a', b') = (a + b a', b b').  Same conventions as above
+// (kNone: complete; kJumpDone: complete in both buffers).
+__global__ void __launch_bounds__(256)
+adj_jump_init_absorb(const uint32_t *__restrict__ nexit, const uint32_t *__restrict__ inv,
+                     JumpGraph G, const uint16_t *__restrict__ link, const float *__restrict__ S,
+                     const float *__restrict__ P, const uint32_t *__restrict__ cmap,
+                     uint4 *__restrict__ buf0)
+{
+    const int64_t E = *nexit;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += stride) {
+        const int64_t id = inv[i];
+        uint32_t n, s;
+        graph_edge(G.dirs, G.g, 0, id, link, n, s);
+        const float a = n != kNone ? S[n] : 0.0f, b = n != kNone ? P[n] : 0.0f;
+        buf0[i] = make_uint4(s != kNone ? cmap[s] : kNone, __float_as_uint(a), __float_as_uint(b), 0u);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+adj_jump_round_absorb(const uint32_t *__restrict__ nexit, uint4 *w_in, uint4 *__restrict__ w_out,
+                      uint32_t *state, int round)
+{
+    uint32_t *live = state + 1;
+    if (live[(round + 2) % 3] == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (state[0] == kNone) state[0] = (uint32_t)(round & 1);
+            live[(round + 1) % 3] = 0;
+        }
+        return;
+    }
+    const int64_t E = *nexit;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t id0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id0 == 0) live[(round + 1) % 3] = 0;
+    bool alive = false;
+    for (int64_t i = id0; i < E; i += stride) {
+        const uint4 w = w_in[i];
+        const uint32_t p = w.x;
+        if (p == kNone) {
+            const uint4 d = make_uint4(kJumpDone, w.y, w.z, 0u);
+            w_out[i] = d;
+            w_in[i] = d;
+        } else if (p != kJumpDone) {
+            const uint4 t = w_in[p];
+            uint32_t np = t.x;
+            if (np == kJumpDone) np = kNone;
+            alive |= np != kNone;
+            const float a = __uint_as_float(w.y), b = __uint_as_float(w.z);
+            const float a2 = __uint_as_float(t.y), b2 = __uint_as_float(t.z);
+            w_out[i] = make_uint4(np, __float_as_uint(a + b * a2), __float_as_uint(b * b2), 0u);
         }
     }
     if (__ballot(alive) != 0 && (threadIdx.x & 63) == 0) live[round % 3] = 1;

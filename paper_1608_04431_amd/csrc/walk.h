@@ -751,9 +751,14 @@ __device__ inline uint32_t fill_up(uint32_t *q, uint32_t cap, const WTile &Tl, c
     return total < cap ? total : cap;
 }
 
+// With absorption (ABS), lambda_loc(d) = g(d) + alpha(d) lambda_loc(receiver)
+// and each cell also gets P(d), the product of alpha along its in-tile path,
+// itself and its root included: alp holds alpha and is overwritten with P as
+// cells are reached (a root keeps P = alpha(root)).
+template <bool ABS = false>
 __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__restrict__ dirs,
                                uint8_t *cb8, float *avp, uint32_t *q, uint32_t qcap, uint64_t roots,
-                               uint64_t *pend, const uint32_t *exitbits)
+                               uint64_t *pend, const uint32_t *exitbits, float *alp = nullptr)
 {
     const int S = Tl.S;
     const int lane = lane_id();
@@ -766,7 +771,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
     pend[lane] = 0;
     int cur = -1;
     uint32_t mask = 0, label = 0;
-    float a = 0.0f;
+    float a = 0.0f, pp = 1.0f;
     for (;;) {
         const uint64_t idle = __ballot(cur < 0);
         if (head >= tail) {
@@ -796,6 +801,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
                 mask = (t >> kQByte) & 0xFFu;
                 label = t >> kQRing;
                 a = avp[cur];
+                if constexpr (ABS) pp = alp[cur];
                 cb8[cur] = (uint8_t)label;
             }
             const uint32_t nidle = (uint32_t)__popcll(idle);
@@ -803,7 +809,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
         }
         uint32_t rest = 0;
         const int from = cur;
-        const float af = a;
+        const float af = a, pf = pp;
         if (cur >= 0) {
             if (mask == 0) {
                 cur = -1;
@@ -815,7 +821,15 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
                 float sd = avp[d];
                 keep_read(sd);
                 cb8[d] = (uint8_t)label;
-                a += sd;
+                if constexpr (ABS) {
+                    float ad = alp[d];
+                    keep_read(ad);
+                    a = sd + ad * a;
+                    pp = ad * pp;
+                    alp[d] = pp;
+                } else {
+                    a += sd;
+                }
                 avp[d] = a;
                 ++visited;
                 cur = d;
@@ -833,7 +847,13 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
                 d = from + dir_off(j, S);
                 dm = cb8[d];
                 cb8[d] = (uint8_t)label;
-                avp[d] += af;
+                if constexpr (ABS) {
+                    const float ad = alp[d];
+                    avp[d] = avp[d] + ad * af;
+                    alp[d] = ad * pf;
+                } else {
+                    avp[d] += af;
+                }
                 ++visited;
             }
             const uint64_t b = __ballot(has);
@@ -1158,17 +1178,24 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
 // (written to out) and every cell's root label (written to root8, one byte
 // per cell); each perimeter cell's record is its link (from its label) and
 // S = lambda_loc, the sum of g along its in-tile path.
+// With absorption (ABS): alpha is read too, lambda_loc follows the absorbing
+// recursion, each perimeter cell's record also holds P (the alpha product of
+// its in-tile path, Pg) and every cell's P goes to pout.
+template <bool ABS = false>
 __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const float *__restrict__ gin,
                                 const Geo &g, int64_t node0, int t, uint16_t *__restrict__ link,
                                 float *__restrict__ Sg, float *__restrict__ out,
-                                uint8_t *__restrict__ root8, uint32_t *status, uint8_t *lds8)
+                                uint8_t *__restrict__ root8, uint32_t *status, uint8_t *lds8,
+                                const float *__restrict__ alpha = nullptr, float *__restrict__ Pg = nullptr,
+                                float *__restrict__ pout = nullptr)
 {
     using namespace wk;
     WTile Tl = wtile_of(g, t);
     Tl.base += node0;
-    const WLayout L = walk_layout(g.th, g.tw, kWalkAdj1);
+    const WLayout L = walk_layout(g.th, g.tw, kWalkAdj1, 4, ABS);
     uint8_t *cb8 = lds8;
     float *avp = reinterpret_cast<float *>(lds8 + L.av) - Tl.S;
+    float *alp = reinterpret_cast<float *>(lds8 + L.al) - Tl.S;  // ABS only
     uint32_t *q = reinterpret_cast<uint32_t *>(lds8 + L.q);
     uint64_t *pend = reinterpret_cast<uint64_t *>(lds8 + L.tail);
     uint32_t *exitbits = reinterpret_cast<uint32_t *>(lds8 + L.tail + 64 * 8);
@@ -1176,6 +1203,7 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
 
     Setup St = setup_tile<2, false>(dirs, g, Tl, cb8, status);
     rows_in(Tl, g, avp, gin);
+    if constexpr (ABS) rows_in(Tl, g, alp, alpha);
     // exits: perimeter cells whose flow leaves the tile into the raster
     if (lane < 8) exitbits[lane] = 0;
     __syncthreads();
@@ -1204,7 +1232,7 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
             atomicOr(&exitbits[p >> 5], 1u << (p & 31));
     }
     __syncthreads();
-    int visited = up_walks(Tl, g, dirs, cb8, avp, q, L.qcap, St.root, pend, exitbits);
+    int visited = up_walks<ABS>(Tl, g, dirs, cb8, avp, q, L.qcap, St.root, pend, exitbits, alp);
     if (wave_sum(visited + __popcll(St.root)) != wave_sum(__popcll(St.valid)) && lane == 0)
         set_status(status, kStatusCycle);
     __syncthreads();
@@ -1220,19 +1248,28 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
         else Lk = (uint16_t)lab;
         link[Tl.base + p] = Lk;
         Sg[Tl.base + p] = lab == kLabelNoData ? 0.0f : avp[idx];
+        if constexpr (ABS) Pg[Tl.base + p] = lab == kLabelNoData ? 0.0f : alp[idx];
     }
     rows_out(Tl, g, avp, St.valid, out);
     bytes_out(Tl, g, cb8, root8);
+    if constexpr (ABS) rows_out(Tl, g, alp, St.valid, pout);
 }
 
 // Adjoint pass 2, one wavefront per tile, no walks: lambda = lambda_loc +
 // the downstream sum of the cell's root exit (mu of that perimeter node),
 // in place in out.
+// With absorption (ABS): lambda = lambda_loc + P mu, P per cell from pcell,
+// mu words of 16 bytes (pointer, sum, product, unused).
+__device__ inline float mu_value(unsigned long long w) { return __uint_as_float((uint32_t)(w >> 32)); }
+__device__ inline float mu_value(uint4 w) { return __uint_as_float(w.y); }
+
+template <bool ABS = false, typename W = unsigned long long>
 __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int t,
                                        const uint8_t *__restrict__ root8,
                                        const uint32_t *__restrict__ cmap,
-                                       const unsigned long long *__restrict__ mu,
-                                       float *__restrict__ out, float *mu_l)
+                                       const W *__restrict__ mu,
+                                       float *__restrict__ out, float *mu_l,
+                                       const float *__restrict__ pcell = nullptr)
 {
     using namespace wk;
     WTile Tl = wtile_of(g, t);
@@ -1244,6 +1281,7 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
     const int ncg = Tl.w >> 2, ngr = Tl.h * ncg;
     const uint32_t inv = (65536u + (uint32_t)ncg - 1u) / (uint32_t)(ncg > 0 ? ncg : 1);
     float4 v[16];
+    float4 pv[ABS ? 16 : 1];
     uint32_t lb[16];
     if (vec) {
 #pragma unroll
@@ -1254,6 +1292,7 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
                 const int64_t o = (Tl.r0 + r) * g.cols + Tl.c0 + 4 * cg;
                 v[k] = *reinterpret_cast<const float4 *>(out + o);
                 lb[k] = *reinterpret_cast<const uint32_t *>(root8 + o);
+                if constexpr (ABS) pv[k] = *reinterpret_cast<const float4 *>(pcell + o);
             }
         }
     }
@@ -1267,7 +1306,7 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
     float m[kRingPerLane];
 #pragma unroll
     for (int k = 0; k < kRingPerLane; ++k)
-        m[k] = cm[k] != kNone ? __uint_as_float((uint32_t)(mu[cm[k]] >> 32)) : 0.0f;
+        m[k] = cm[k] != kNone ? mu_value(mu[cm[k]]) : 0.0f;
 #pragma unroll
     for (int k = 0; k < kRingPerLane; ++k) {
         const int p = lane + 64 * k;
@@ -1283,10 +1322,18 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
                 const uint32_t l0 = lb[k] & 0xFFu, l1 = (lb[k] >> 8) & 0xFFu;
                 const uint32_t l2 = (lb[k] >> 16) & 0xFFu, l3 = lb[k] >> 24;
                 float4 x = v[k];
-                if (l0 < kLabelTerm) x.x += mu_l[l0];
-                if (l1 < kLabelTerm) x.y += mu_l[l1];
-                if (l2 < kLabelTerm) x.z += mu_l[l2];
-                if (l3 < kLabelTerm) x.w += mu_l[l3];
+                if constexpr (ABS) {
+                    const float4 pk = pv[k];
+                    if (l0 < kLabelTerm) x.x += pk.x * mu_l[l0];
+                    if (l1 < kLabelTerm) x.y += pk.y * mu_l[l1];
+                    if (l2 < kLabelTerm) x.z += pk.z * mu_l[l2];
+                    if (l3 < kLabelTerm) x.w += pk.w * mu_l[l3];
+                } else {
+                    if (l0 < kLabelTerm) x.x += mu_l[l0];
+                    if (l1 < kLabelTerm) x.y += mu_l[l1];
+                    if (l2 < kLabelTerm) x.z += mu_l[l2];
+                    if (l3 < kLabelTerm) x.w += mu_l[l3];
+                }
                 *reinterpret_cast<float4 *>(out + (Tl.r0 + r) * g.cols + Tl.c0 + 4 * cg) = x;
             }
         }
@@ -1297,7 +1344,7 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
     for (int r = 0; r < Tl.h; ++r) {
         const int64_t o = (Tl.r0 + r) * g.cols + Tl.c0 + c;
         const uint32_t l = root8[o];
-        if (l < kLabelTerm) out[o] += mu_l[l];
+        if (l < kLabelTerm) out[o] += ABS ? pcell[o] * mu_l[l] : mu_l[l];
     }
 }
 
@@ -1349,6 +1396,30 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
 {
     extern __shared__ __align__(16) uint8_t lds8[];
     adj_tile(dirs, gin, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, Sg, out, root8, status, lds8);
+}
+
+// Adjoint with absorption: pass 1 also writes P per perimeter node (Pg) and
+// per cell (pout); pass 2 reads P and 16-byte exit words.
+__global__ void __launch_bounds__(64, 3)
+adj_walk_absorb(const uint8_t *__restrict__ dirs, const float *__restrict__ gin,
+                const float *__restrict__ alpha, Geo g, uint16_t *__restrict__ link,
+                float *__restrict__ Sg, float *__restrict__ Pg, float *__restrict__ out,
+                float *__restrict__ pout, uint8_t *__restrict__ root8, uint32_t *status)
+{
+    extern __shared__ __align__(16) uint8_t lds8[];
+    adj_tile<true>(dirs, gin, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, Sg, out, root8, status, lds8,
+                   alpha, Pg, pout);
+}
+
+__global__ void __launch_bounds__(64)
+adj_finish_absorb(Geo g, const uint8_t *__restrict__ root8, const uint32_t *__restrict__ cmap,
+                  const uint4 *__restrict__ mu0, const uint4 *__restrict__ mu1,
+                  const uint32_t *__restrict__ jstate, const float *__restrict__ pcell,
+                  float *__restrict__ out)
+{
+    __shared__ float mu_l[256];
+    const uint4 *mu = jstate[0] == 1 ? mu1 : mu0;
+    adj_finish_tile<true>(g, 0, xcd_tile(blockIdx.x, gridDim.x), root8, cmap, mu, out, mu_l, pcell);
 }
 
 __global__ void __launch_bounds__(64)

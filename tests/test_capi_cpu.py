@@ -112,6 +112,13 @@ def test_absorb_workspace_and_argument_errors():
     assert lib.flow_accum_absorb(fake, None, fake, fake, 1000, 300, 64, 48, fake, n - 1, None) == EWS
     odd = ctypes.c_void_p(0x1000 + 8)
     assert lib.flow_accum_absorb(fake, None, fake, fake, 1000, 300, 64, 48, odd, n, None) == EWS
+    adj = lib.flow_accum_absorb_adjoint
+    assert adj(fake, None, fake, fake, 1000, 300, 64, 48, fake, n, None) == EINVAL      # no alpha
+    assert adj(fake, fake, None, fake, 1000, 300, 64, 48, fake, n, None) == EINVAL      # no g
+    assert adj(fake, fake, fake, None, 1000, 300, 64, 48, fake, n, None) == EINVAL      # no out
+    assert adj(fake, fake, fake, fake, 1000, 300, 64, -1, fake, n, None) == EINVAL
+    assert adj(fake, fake, fake, fake, 1000, 300, 64, 48, fake, n - 1, None) == EWS
+    assert adj(fake, fake, fake, fake, 1000, 300, 64, 48, odd, n, None) == EWS
 
 
 def test_batch_argument_errors_return_before_launch():

@@ -1,7 +1,8 @@
-"""Flow accumulation with absorption (flow_accum_absorb) against the oracle's
-Eq. (1) with alpha per cell: float32 within the float32 parity bound of the
-float64 oracle, over tile shapes across edges and corners, alpha = 1 (equal
-to flow_accum f32) and alpha = 0 (A = w)."""
+"""Flow accumulation with absorption (flow_accum_absorb) and its adjoint
+(flow_accum_absorb_adjoint) against the oracle's Eq. (1) with alpha per cell
+and its transpose: float32 within the float32 parity bound of the float64
+oracle, over tile shapes across edges and corners, alpha = 1 (equal to
+flow_accum f32 / flow_accum_adjoint) and alpha = 0 (A = w, lambda = g)."""
 import numpy as np
 import pytest
 import torch
@@ -81,3 +82,47 @@ def test_absorb_empty_and_single_tile(d8m):
     alpha = synth.uniform(d.shape, 5)
     got = d8m.flow_accum_absorb(dev(d), dev(alpha)).cpu().numpy()
     assert_rel(got, oracle.accum_absorb_f64(d, alpha), d != 9)
+
+
+@pytest.mark.parametrize("shape,tile", [((300, 257), (32, 32)), ((130, 200), (64, 48)),
+                                        ((97, 64), (16, 64)), ((200, 131), (64, 64))])
+def test_absorb_adjoint_matches_oracle(d8m, shape, tile):
+    cases = [random_acyclic_dirs(*shape, seed=sum(shape) + 1),
+             oracle.d8(synth.dem(*shape, seed=17, lambda0=32, ocean=True))]
+    for i, d in enumerate(cases):
+        alpha = (0.5 + 0.5 * synth.uniform(d.shape, 90 + i)).astype(np.float32)
+        g = synth.uniform(d.shape, 100 + i)
+        want = oracle.transpose_absorb_f64(d, alpha, g)
+        got = d8m.flow_accum_absorb_adjoint(dev(d), dev(alpha), dev(g), tile=tile).cpu().numpy()
+        assert_rel(got, want, d != 9)
+
+
+def test_absorb_adjoint_special_alphas_and_duality(d8m):
+    z = synth.workload_dem("dem512")
+    d = oracle.d8(z)
+    g = synth.uniform(d.shape, 5)
+    one = np.ones(d.shape, np.float32)
+    got = d8m.flow_accum_absorb_adjoint(dev(d), dev(one), dev(g), tile=(64, 48)).cpu().numpy()
+    ref = d8m.flow_accum_adjoint(dev(d), dev(g), tile=(64, 48)).cpu().numpy()
+    assert_rel(got, ref.astype(np.float64), d != 9)
+    zero = np.zeros(d.shape, np.float32)
+    got = d8m.flow_accum_absorb_adjoint(dev(d), dev(zero), dev(g), tile=(64, 48)).cpu().numpy()
+    np.testing.assert_array_equal(got, np.where(d != 9, g, 0).astype(np.float32))
+    # <A_alpha(w), g> = <w, lambda_alpha(g)>: the two entry points are transposes
+    alpha = synth.uniform(d.shape, 6)
+    w = synth.uniform(d.shape, 7)
+    A = d8m.flow_accum_absorb(dev(d), dev(alpha), dev(w), tile=(32, 64)).double().cpu().numpy()
+    lam = d8m.flow_accum_absorb_adjoint(dev(d), dev(alpha), dev(g), tile=(32, 64)).double().cpu().numpy()
+    lhs, rhs = float((A * g).sum()), float((w * lam).sum())
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+    assert_rel(lam, oracle.transpose_absorb_f64(d, alpha, g), d != 9)
+
+
+def test_absorb_adjoint_empty_and_single_tile(d8m):
+    e = torch.empty((0, 5), dtype=torch.uint8, device="cuda")
+    ef = torch.empty((0, 5), device="cuda")
+    assert d8m.flow_accum_absorb_adjoint(e, ef, ef).shape == (0, 5)
+    d = random_acyclic_dirs(5, 7, seed=3, nodata_frac=0.0)
+    alpha, g = synth.uniform(d.shape, 8), synth.uniform(d.shape, 9)
+    got = d8m.flow_accum_absorb_adjoint(dev(d), dev(alpha), dev(g)).cpu().numpy()
+    assert_rel(got, oracle.transpose_absorb_f64(d, alpha, g), d != 9)
