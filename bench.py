@@ -38,10 +38,13 @@ KERNEL_BYTES_PER_CELL = {
     "d8_directions": 5.0,
     "d8_directions_rho8": 9.0,  # z 4 + r 4 + code 1
     "flow_accum_absorb": 13.0,  # code 1 + alpha 4 + w 4 read, A 4 written
+    "flow_accum_absorb_adjoint": 13.0,  # code 1 + alpha 4 + g 4 read, lambda 4 written
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
 SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (56, 48), (48, 64), (48, 48), (32, 64))
 
+
+ABSORB_TILE = (32, 48)  # the absorption entry points' default shape
 
 KERNEL_NAMES = {  # timing label -> kernel symbol prefix in profiler output
     "fwd_pass1": "void d8::fwd_walk<1, unsigned int",
@@ -351,31 +354,38 @@ def main():
 
 
 def absorb_leg(d8, dirs, w, tile, seed, reps=3):
-    """Eq. (1) with absorption on the same directions: alpha ~ U[0.5, 1) per
-    cell, the adjoint's U[0, 1) draws as weights; events around `reps` calls
-    after one warm call, on the launch stream."""
+    """Eq. (1) with absorption and its adjoint on the same directions:
+    alpha ~ U[0.5, 1) per cell, the adjoint's U[0, 1) draws as weights and as
+    g; events around `reps` calls after one warm call, on the launch stream."""
     import torch
     rows, cols = dirs.shape
     alpha = torch.from_numpy(0.5 + 0.5 * synth.uniform((rows, cols), seed)).to(dirs.device)
     ws = torch.empty(d8._lib.load().d8_absorb_workspace_bytes(rows, cols, *tile), dtype=torch.uint8,
                      device=dirs.device)
     out = torch.empty((rows, cols), dtype=torch.float32, device=dirs.device)
-    d8.flow_accum_absorb(dirs, alpha, w, tile=tile, ws=ws, out=out)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        d8.flow_accum_absorb(dirs, alpha, w, tile=tile, ws=ws, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    gbps = KERNEL_BYTES_PER_CELL["flow_accum_absorb"] * rows * cols / (ms * 1e-3) / 1e9
-    log(f"flow_accum_absorb: {ms:.3f} ms, {gbps:.0f} GB/s algorithmic")
-    del alpha, ws, out
+    lam = torch.empty_like(out)
+    res = {"alpha": "U[0.5,1) per cell", "weights and g": "U[0,1)", "tile": list(tile)}
+    for name, fn in (("flow_accum_absorb", lambda: d8.flow_accum_absorb(dirs, alpha, w, tile=tile, ws=ws,
+                                                                        out=out)),
+                     ("flow_accum_absorb_adjoint", lambda: d8.flow_accum_absorb_adjoint(
+                         dirs, alpha, w, tile=tile, ws=ws, out=lam))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbps = KERNEL_BYTES_PER_CELL[name] * rows * cols / (ms * 1e-3) / 1e9
+        log(f"{name}: {ms:.3f} ms, {gbps:.0f} GB/s algorithmic")
+        res[name] = {"ms": round(ms, 4), "cells_per_s": rows * cols / (ms * 1e-3),
+                     "bytes_per_cell": KERNEL_BYTES_PER_CELL[name], "achieved_GBps": gbps,
+                     "frac_hbm_peak": gbps / HBM_PEAK_GBPS}
+    del alpha, ws, out, lam
     torch.cuda.empty_cache()
-    return {"ms": round(ms, 4), "cells_per_s": rows * cols / (ms * 1e-3),
-            "bytes_per_cell": KERNEL_BYTES_PER_CELL["flow_accum_absorb"], "achieved_GBps": gbps,
-            "frac_hbm_peak": gbps / HBM_PEAK_GBPS, "alpha": "U[0.5,1) per cell", "weights": "U[0,1)"}
+    return res
 
 
 def streamed_leg(d8, dirs, A, tile, band_rows, reps=3):
@@ -535,7 +545,7 @@ def run(args, bd):
 
     absorb = None
     if not args.no_absorb:
-        absorb = absorb_leg(d8, dirs, g, tile, wl.get("seed_g", 31) + 1)
+        absorb = absorb_leg(d8, dirs, g, ABSORB_TILE, wl.get("seed_g", 31) + 1)
 
     streamed = None
     if not args.no_stream:

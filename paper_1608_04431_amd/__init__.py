@@ -17,7 +17,7 @@ NOFLOW = 8
 NODATA = 9
 
 __all__ = ["d8_directions", "d8_directions_rho8", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
-           "check_status", "FlowAccum", "D8Error", "Raster", "Batch", "BatchGraph",
+           "check_status", "FlowAccum", "FlowAccumAbsorb", "D8Error", "Raster", "Batch", "BatchGraph",
            "stream_workspace_bytes", "flow_accum_streamed", "flow_accum_absorb",
            "flow_accum_absorb_adjoint"]
 
@@ -275,6 +275,26 @@ class FlowAccum(torch.autograd.Function):
         (dirs,) = ctx.saved_tensors
         gw = flow_accum_adjoint(dirs, grad_a.contiguous(), tile=ctx.tile)
         return gw, None, None
+
+
+class FlowAccumAbsorb(torch.autograd.Function):
+    """A = FlowAccumAbsorb.apply(w, dirs, alpha[, tile]): accumulation with
+    absorption, differentiable in the weights w (the backward pass is
+    flow_accum_absorb_adjoint); alpha is a constant of the operator and gets
+    no gradient."""
+
+    @staticmethod
+    def forward(ctx, w, dirs, alpha, tile=(0, 0)):
+        alpha = alpha.detach().contiguous()
+        ctx.save_for_backward(dirs, alpha)
+        ctx.tile = tuple(tile)
+        return flow_accum_absorb(dirs, alpha, w.contiguous(), tile=ctx.tile)
+
+    @staticmethod
+    def backward(ctx, grad_a):
+        dirs, alpha = ctx.saved_tensors
+        gw = flow_accum_absorb_adjoint(dirs, alpha, grad_a.contiguous(), tile=ctx.tile)
+        return gw, None, None, None
 
 
 # ----------------------------------------------------------------- batches --

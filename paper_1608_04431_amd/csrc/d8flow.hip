@@ -19,6 +19,16 @@ using namespace d8;
 namespace {
 
 constexpr int kDefaultTile = 64;
+// Absorption keeps alpha beside the values in LDS, so its tiles default to a
+// smaller shape (more tiles resident per CU): 32 x 48.
+constexpr int kAbsorbTileRows = 32, kAbsorbTileCols = 48;
+inline void absorb_default_tile(int &th, int &tw)
+{
+    if (th == 0 && tw == 0) {
+        th = kAbsorbTileRows;
+        tw = kAbsorbTileCols;
+    }
+}
 constexpr int kNodeBlock = 256;
 
 struct Layout {
@@ -912,6 +922,7 @@ size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int 
 {
     Geo g;
     bool empty;
+    absorb_default_tile(tile_rows, tile_cols);
     if (check_common(rows, cols, tile_rows, tile_cols, g, empty) != D8_OK) return 0;
     if (empty) return 512;
     return absorb_layout(layout_for(g), g).total;
@@ -923,6 +934,7 @@ int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *al
 {
     Geo g;
     bool empty;
+    absorb_default_tile(tile_rows, tile_cols);
     int rc = check_common(rows, cols, tile_rows, tile_cols, g, empty);
     if (rc != D8_OK) return rc;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;
@@ -946,6 +958,7 @@ int flow_accum_absorb_adjoint(const uint8_t *dirs, const float *alpha, const flo
 {
     Geo g;
     bool empty;
+    absorb_default_tile(tile_rows, tile_cols);
     int rc = check_common(rows, cols, tile_rows, tile_cols, g, empty);
     if (rc != D8_OK) return rc;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;

@@ -126,3 +126,15 @@ def test_absorb_adjoint_empty_and_single_tile(d8m):
     alpha, g = synth.uniform(d.shape, 8), synth.uniform(d.shape, 9)
     got = d8m.flow_accum_absorb_adjoint(dev(d), dev(alpha), dev(g)).cpu().numpy()
     assert_rel(got, oracle.transpose_absorb_f64(d, alpha, g), d != 9)
+
+
+def test_absorb_autograd(d8m):
+    d = oracle.d8(synth.dem(150, 170, seed=21, lambda0=32, ocean=True))
+    alpha = synth.uniform(d.shape, 11)
+    w = torch.from_numpy(synth.uniform(d.shape, 12)).cuda().requires_grad_(True)
+    c = synth.uniform(d.shape, 13)
+    A = d8m.FlowAccumAbsorb.apply(w, dev(d), dev(alpha), (32, 48))
+    loss = (A * dev(c)).sum()
+    loss.backward()
+    assert_rel(A.detach().cpu().numpy(), oracle.accum_absorb_f64(d, alpha, w.detach().cpu().numpy()), d != 9)
+    assert_rel(w.grad.cpu().numpy(), oracle.transpose_absorb_f64(d, alpha, c), d != 9)
