@@ -9,6 +9,10 @@ Functions (each follows one passage of the paper; see ``oracle.c``):
   accum_u64     Eq. (1) by the Kahn order of Algorithm 1, 64-bit counts
   accum_f64     Eq. (1) with float32 weights, summed in double
   transpose_f64 the adjoint lambda = (I-P)^-T g (reverse topological sweep)
+  rho8          rho8 directions from a per-cell draw r (diagonal distance 2 - r)
+  accum_absorb_f64 / transpose_absorb_f64  Eq. (1) with absorption alpha per
+                cell, and its transpose
+  absorb_alpha_grad_f64  derivative of <c, A> with respect to alpha
   brute_*       path walking, independent of the Kahn order (small inputs)
   upstream_sum  one value of A from its definition (catchment search)
   downstream_sum one value of the adjoint from its definition (path walk)
@@ -175,6 +179,20 @@ def transpose_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, g: np.ndarray) -> 
     _check(_load().orc_transpose_absorb_f64(_p(dirs), dirs.shape[0], dirs.shape[1], _p(order),
                                             order.size, _p(g), _p(alpha), _p(lam)))
     return lam
+
+
+def absorb_alpha_grad_f64(dirs: np.ndarray, alpha: np.ndarray, w: np.ndarray | None,
+                          c: np.ndarray) -> np.ndarray:
+    """d<c, A>/d alpha(n) for A of Eq. (1) with absorption: alpha(n) scales the
+    one edge n -> receiver(n), so the derivative is A(n) lambda(receiver(n)),
+    lambda = transpose_absorb_f64(c); 0 for cells without a data receiver."""
+    A = accum_absorb_f64(dirs, alpha, w)
+    lam = transpose_absorb_f64(dirs, alpha, c)
+    r = receivers(dirs)
+    out = np.zeros(A.shape, dtype=np.float64)
+    has = r >= 0
+    out[has] = A[has] * lam.reshape(-1)[r[has]]
+    return out
 
 
 def accum_f64d(dirs: np.ndarray, w: np.ndarray) -> np.ndarray:

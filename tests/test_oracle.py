@@ -521,3 +521,45 @@ def test_absorb_chain_closed_form():
         A = oracle.accum_absorb_f64(d, alpha)
         want = np.array([sum(float(np.float32(a)) ** j for j in range(k + 1)) for k in range(12)])
         np.testing.assert_allclose(A[0], want, rtol=1e-14)
+
+
+def test_absorb_alpha_grad_central_differences():
+    # <c, A_alpha(w)> is affine in each single alpha(n): every flow path passes
+    # n at most once, so alpha(n) enters each path product at most once.  A
+    # central difference is then exact; alpha +- h are exact in float32.
+    d = random_acyclic_dirs(11, 13, 21)
+    rng = np.random.default_rng(22)
+    alpha = (rng.integers(8, 57, d.shape) / 64.0).astype(np.float32)
+    w = synth.uniform(d.shape, 23)
+    c = synth.uniform(d.shape, 24)
+    grad = oracle.absorb_alpha_grad_f64(d, alpha, w, c)
+    h = 0.125
+    for n in range(d.size):
+        ap, am = alpha.copy(), alpha.copy()
+        ap.flat[n] += h
+        am.flat[n] -= h
+        fd = (float((c * oracle.accum_absorb_f64(d, ap, w)).sum()) -
+              float((c * oracle.accum_absorb_f64(d, am, w)).sum())) / (2 * h)
+        assert abs(fd - grad.flat[n]) <= 1e-12 * max(1.0, abs(fd)), n
+    # no data receiver (NoData, NoFlow, off the raster): no dependence on alpha
+    r = oracle.receivers(d)
+    assert (grad[r < 0] == 0).all()
+    assert (grad[(r >= 0) & (d != 9)] != 0).any()
+
+
+def test_absorb_alpha_grad_chain_closed_form():
+    # a row flowing east into a NoFlow cell, w = 1, c = e_last: A(k) = sum_{j<=k} a^j,
+    # lambda(m) = a^(last - m), so dA(last)/d alpha(k) = A(k) a^(last - k - 1)
+    n = 9
+    d = np.full((1, n), 4, np.uint8)
+    d[0, -1] = 8
+    a = np.float32(0.75)
+    alpha = np.full(d.shape, a, np.float32)
+    c = np.zeros(d.shape, np.float32)
+    c[0, -1] = 1
+    grad = oracle.absorb_alpha_grad_f64(d, alpha, None, c)[0]
+    af = float(a)
+    for k in range(n - 1):
+        Ak = sum(af ** j for j in range(k + 1))
+        assert abs(grad[k] - Ak * af ** (n - 2 - k)) < 1e-14
+    assert grad[-1] == 0
