@@ -192,6 +192,22 @@ int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *al
                       void *stream);
 
 /*
+ * Gradient with respect to the absorption fractions: for a loss with
+ * gradient c with respect to A (the output of flow_accum_absorb), alpha(n)
+ * scales only the edge from n to its receiver in Eq. (1), so
+ * dL/dalpha(n) = A(n) lambda(receiver(n)), lambda = flow_accum_absorb_adjoint
+ * of c (not in the paper).  0 where n has no data receiver (NoFlow, NoData,
+ * off the raster, invalid codes).  One elementwise pass.
+ *
+ * dirs: uint8 codes; acc: float32 A from flow_accum_absorb; grad_lam: float32
+ * lambda from flow_accum_absorb_adjoint; grad_alpha: float32 (out).  All
+ * device, [rows*cols] row-major.  Returns D8_OK, D8_EINVAL (sizes, NULL
+ * pointers for a non-empty raster) or D8_EHIP.
+ */
+int flow_accum_absorb_alpha_grad(const uint8_t *dirs, const float *acc, const float *grad_lam,
+                                 float *grad_alpha, int64_t rows, int64_t cols, void *stream);
+
+/*
  * Forward accumulation (unit weights, uint32 counts) of a raster that stays
  * in host memory, for rasters larger than the device's memory -- the regime
  * the paper's tiles were designed for (Introduction; the EVICT strategy of

@@ -19,7 +19,7 @@ NODATA = 9
 __all__ = ["d8_directions", "d8_directions_rho8", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
            "check_status", "FlowAccum", "FlowAccumAbsorb", "D8Error", "Raster", "Batch", "BatchGraph",
            "stream_workspace_bytes", "flow_accum_streamed", "flow_accum_absorb",
-           "flow_accum_absorb_adjoint"]
+           "flow_accum_absorb_adjoint", "flow_accum_absorb_alpha_grad"]
 
 
 def _stream(device: torch.device) -> int:
@@ -196,6 +196,25 @@ def flow_accum_absorb_adjoint(dirs: torch.Tensor, alpha: torch.Tensor, grad: tor
     return out
 
 
+def flow_accum_absorb_alpha_grad(dirs: torch.Tensor, acc: torch.Tensor, lam: torch.Tensor,
+                                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dalpha(n) = A(n) lambda(receiver(n)) (see flow_accum_absorb_alpha_grad
+    in d8flow.h): acc from flow_accum_absorb, lam from flow_accum_absorb_adjoint
+    of dL/dA."""
+    _check_raster(dirs, torch.uint8, "dirs")
+    for t, name in ((acc, "acc"), (lam, "lam")):
+        _check_raster(t, torch.float32, name)
+        if t.shape != dirs.shape:
+            raise ValueError(f"{name} and dirs differ in shape")
+    if out is None:
+        out = torch.empty(dirs.shape, dtype=torch.float32, device=dirs.device)
+    _check_raster(out, torch.float32, "out")
+    rc = _lib.load().flow_accum_absorb_alpha_grad(_ptr(dirs), _ptr(acc), _ptr(lam), _ptr(out),
+                                                  dirs.shape[0], dirs.shape[1], _stream(dirs.device))
+    _lib.check(rc, "flow_accum_absorb_alpha_grad")
+    return out
+
+
 def stream_workspace_bytes(rows: int, cols: int, tile: tuple[int, int] = (0, 0),
                            band_rows: int = 0) -> int:
     n = _lib.load().d8_stream_workspace_bytes(rows, cols, tile[0], tile[1], band_rows)
@@ -279,22 +298,24 @@ class FlowAccum(torch.autograd.Function):
 
 class FlowAccumAbsorb(torch.autograd.Function):
     """A = FlowAccumAbsorb.apply(w, dirs, alpha[, tile]): accumulation with
-    absorption, differentiable in the weights w (the backward pass is
-    flow_accum_absorb_adjoint); alpha is a constant of the operator and gets
-    no gradient."""
+    absorption, differentiable in the weights w (flow_accum_absorb_adjoint)
+    and in the fractions alpha (flow_accum_absorb_alpha_grad on A and that
+    adjoint)."""
 
     @staticmethod
     def forward(ctx, w, dirs, alpha, tile=(0, 0)):
         alpha = alpha.detach().contiguous()
-        ctx.save_for_backward(dirs, alpha)
         ctx.tile = tuple(tile)
-        return flow_accum_absorb(dirs, alpha, w.contiguous(), tile=ctx.tile)
+        A = flow_accum_absorb(dirs, alpha, w.detach().contiguous(), tile=ctx.tile)
+        ctx.save_for_backward(dirs, alpha, A)
+        return A
 
     @staticmethod
     def backward(ctx, grad_a):
-        dirs, alpha = ctx.saved_tensors
-        gw = flow_accum_absorb_adjoint(dirs, alpha, grad_a.contiguous(), tile=ctx.tile)
-        return gw, None, None, None
+        dirs, alpha, A = ctx.saved_tensors
+        lam = flow_accum_absorb_adjoint(dirs, alpha, grad_a.contiguous(), tile=ctx.tile)
+        ga = flow_accum_absorb_alpha_grad(dirs, A, lam) if ctx.needs_input_grad[2] else None
+        return (lam if ctx.needs_input_grad[0] else None), None, ga, None
 
 
 # ----------------------------------------------------------------- batches --

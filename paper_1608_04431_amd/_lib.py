@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libd8flow.so")
 # every symbol declared in include/d8flow.h
 EXPORTS = ("d8_directions", "d8_directions_rho8", "d8_workspace_bytes", "flow_accum", "flow_accum_adjoint",
            "d8_absorb_workspace_bytes", "flow_accum_absorb", "flow_accum_absorb_adjoint",
+           "flow_accum_absorb_alpha_grad",
            "d8_stream_workspace_bytes", "flow_accum_streamed",
            "d8_batch_workspace_bytes", "flow_accum_batched", "d8_graph_create",
            "d8_graph_launch", "d8_graph_destroy",
@@ -74,6 +75,8 @@ def load() -> ctypes.CDLL:
     lib.flow_accum_absorb.restype = i32
     lib.flow_accum_absorb_adjoint.argtypes = [vp, vp, vp, vp, i64, i64, i32, i32, vp, sz, vp]
     lib.flow_accum_absorb_adjoint.restype = i32
+    lib.flow_accum_absorb_alpha_grad.argtypes = [vp, vp, vp, vp, i64, i64, vp]
+    lib.flow_accum_absorb_alpha_grad.restype = i32
     lib.d8_stream_workspace_bytes.argtypes = [i64, i64, i32, i32, i64]
     lib.d8_stream_workspace_bytes.restype = sz
     lib.flow_accum_streamed.argtypes = [vp, vp, i64, i64, i32, i32, i64, vp, sz, vp]

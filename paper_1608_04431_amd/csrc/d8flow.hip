@@ -1013,6 +1013,20 @@ int flow_accum_absorb_adjoint(const uint8_t *dirs, const float *alpha, const flo
     return last_error();
 }
 
+int flow_accum_absorb_alpha_grad(const uint8_t *dirs, const float *acc, const float *grad_lam,
+                                 float *grad_alpha, int64_t rows, int64_t cols, void *stream)
+{
+    if (rows < 0 || cols < 0 || rows > INT_MAX || cols > INT_MAX) return D8_EINVAL;
+    if (rows == 0 || cols == 0) return D8_OK;
+    if (!dirs || !acc || !grad_lam || !grad_alpha) return D8_EINVAL;
+    begin_call();
+    hipStream_t st = as_stream(stream);
+    const dim3 grid((unsigned)((cols + kGradBlock - 1) / kGradBlock), (unsigned)std::min<int64_t>(rows, 65535));
+    D8_LAUNCH("absorb_alpha_grad", st,
+              (absorb_alpha_grad<<<grid, kGradBlock, 0, st>>>(dirs, acc, grad_lam, grad_alpha, rows, cols)));
+    return last_error();
+}
+
 size_t d8_stream_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols,
                                  int64_t band_rows)
 {

@@ -702,6 +702,34 @@ adj_jump_round_absorb(const uint32_t *__restrict__ nexit, uint4 *w_in, uint4 *__
     if (__ballot(alive) != 0 && (threadIdx.x & 63) == 0) live[round % 3] = 1;
 }
 
+// Derivative of <c, A> with respect to the absorption fractions: alpha(n)
+// scales only the edge n -> receiver(n) of Eq. (1), so it is
+// A(n) lambda(receiver(n)) with lambda the absorbing adjoint of c; 0 where n
+// has no data receiver (NoFlow, NoData, off the raster, invalid codes).  One
+// lane per cell of a row, blocks stride over the rows (gridDim.y).
+constexpr int kGradBlock = 256;
+
+__global__ void __launch_bounds__(kGradBlock)
+absorb_alpha_grad(const uint8_t *__restrict__ dirs, const float *__restrict__ A,
+                  const float *__restrict__ lam, float *__restrict__ out, int64_t rows, int64_t cols)
+{
+    const int64_t c = (int64_t)blockIdx.x * kGradBlock + threadIdx.x;
+    if (c >= cols) return;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const int64_t i = r * cols + c;
+        const uint32_t k = dirs[i];
+        float v = 0.0f;
+        if (k < (uint32_t)kNoFlow) {
+            const int64_t nr = r + dir_dr((int)k), nc = c + dir_dc((int)k);
+            if (nr >= 0 && nr < rows && nc >= 0 && nc < cols) {
+                const int64_t j = nr * cols + nc;
+                if (dirs[j] < (uint8_t)kNoData) v = A[i] * lam[j];
+            }
+        }
+        out[i] = v;
+    }
+}
+
 // After the last round: if no round found convergence, the final buffer is
 // rounds&1, and pointers still live mean a cycle.
 __global__ void adj_jump_finish(uint32_t *state, int rounds, uint32_t *status)

@@ -119,6 +119,11 @@ def test_absorb_workspace_and_argument_errors():
     assert adj(fake, fake, fake, fake, 1000, 300, 64, -1, fake, n, None) == EINVAL
     assert adj(fake, fake, fake, fake, 1000, 300, 64, 48, fake, n - 1, None) == EWS
     assert adj(fake, fake, fake, fake, 1000, 300, 64, 48, odd, n, None) == EWS
+    ag = lib.flow_accum_absorb_alpha_grad
+    assert ag(None, fake, fake, fake, 10, 10, None) == EINVAL
+    assert ag(fake, fake, None, fake, 10, 10, None) == EINVAL
+    assert ag(fake, fake, fake, fake, -1, 10, None) == EINVAL
+    assert ag(None, None, None, None, 0, 10, None) == _lib.D8_OK      # empty: nothing to do
 
 
 def test_batch_argument_errors_return_before_launch():

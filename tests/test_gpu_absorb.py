@@ -138,3 +138,39 @@ def test_absorb_autograd(d8m):
     loss.backward()
     assert_rel(A.detach().cpu().numpy(), oracle.accum_absorb_f64(d, alpha, w.detach().cpu().numpy()), d != 9)
     assert_rel(w.grad.cpu().numpy(), oracle.transpose_absorb_f64(d, alpha, c), d != 9)
+
+
+def test_alpha_grad_kernel_exact(d8m):
+    # the kernel's only arithmetic is one float32 product A(n) * lambda(receiver(n)):
+    # fed the oracle's A and lambda rounded to float32, it must match bit for bit
+    for shape, seed in (((97, 131), 31), ((1, 300), 32), ((300, 1), 33)):
+        d = random_acyclic_dirs(*shape, seed=seed)
+        d[0, 0] = 200                                   # an invalid code: no receiver
+        alpha = synth.uniform(d.shape, seed + 1)
+        A32 = oracle.accum_absorb_f64(np.where(d == 200, 9, d).astype(np.uint8), alpha).astype(np.float32)
+        lam32 = synth.uniform(d.shape, seed + 2)
+        r = oracle.receivers(np.where(d == 200, 9, d).astype(np.uint8))
+        want = np.zeros(d.shape, np.float32)
+        has = r >= 0
+        want[has] = A32[has] * lam32.reshape(-1)[r[has]]
+        got = d8m.flow_accum_absorb_alpha_grad(dev(d), dev(A32), dev(lam32)).cpu().numpy()
+        np.testing.assert_array_equal(got, want)
+
+
+def test_absorb_autograd_alpha(d8m):
+    # A and lambda are each within 1e-4 relative of the oracle, so their
+    # product is within (1 + 1e-4)^2 - 1 < 2.1e-4 of the oracle's gradient
+    d = oracle.d8(synth.dem(140, 190, seed=23, lambda0=32, ocean=True))
+    alpha_np = (0.5 + 0.5 * synth.uniform(d.shape, 14)).astype(np.float32)
+    w_np, c = synth.uniform(d.shape, 15), synth.uniform(d.shape, 16)
+    w = torch.from_numpy(w_np).cuda().requires_grad_(True)
+    alpha = torch.from_numpy(alpha_np).cuda().requires_grad_(True)
+    A = d8m.FlowAccumAbsorb.apply(w, dev(d), alpha, (32, 48))
+    (A * dev(c)).sum().backward()
+    want = oracle.absorb_alpha_grad_f64(d, alpha_np, w_np, c)
+    got = alpha.grad.double().cpu().numpy()
+    nz = want != 0
+    assert (got[~nz] == 0).all()
+    rel = np.abs(got[nz] - want[nz]) / np.abs(want[nz])
+    assert rel.max() <= 2.1e-4, rel.max()
+    assert_rel(w.grad.cpu().numpy(), oracle.transpose_absorb_f64(d, alpha_np, c), d != 9)
