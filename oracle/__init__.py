@@ -13,6 +13,8 @@ Functions (each follows one passage of the paper; see ``oracle.c``):
   accum_absorb_f64 / transpose_absorb_f64  Eq. (1) with absorption alpha per
                 cell, and its transpose
   absorb_alpha_grad_f64  derivative of <c, A> with respect to alpha
+  upstream_sum_absorb / downstream_sum_absorb  one value of A / lambda with
+                absorption from its definition
   brute_*       path walking, independent of the Kahn order (small inputs)
   upstream_sum  one value of A from its definition (catchment search)
   downstream_sum one value of the adjoint from its definition (path walk)
@@ -80,6 +82,10 @@ def _load():
     lib.orc_upstream_sum.restype = ctypes.c_double
     lib.orc_downstream_sum.argtypes = [vp, i64, i64, vp, i64, i64]
     lib.orc_downstream_sum.restype = ctypes.c_double
+    lib.orc_upstream_sum_absorb.argtypes = [vp, i64, i64, vp, vp, i64, i64]
+    lib.orc_upstream_sum_absorb.restype = ctypes.c_double
+    lib.orc_downstream_sum_absorb.argtypes = [vp, i64, i64, vp, vp, i64, i64]
+    lib.orc_downstream_sum_absorb.restype = ctypes.c_double
     lib.orc_tiled.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp, vp]
     lib.orc_path_stats.argtypes = [vp, i64, i64, i64, i64, vp]
     for name in ("orc_d8", "orc_receivers", "orc_accum_u64", "orc_accum_f64", "orc_accum_f64d",
@@ -257,6 +263,35 @@ def downstream_sum(dirs: np.ndarray, r: int, c: int, g: np.ndarray,
     g = np.ascontiguousarray(g, dtype=np.float32)
     v = _load().orc_downstream_sum(_p(dirs), dirs.shape[0], dirs.shape[1], _p(g),
                                    r * dirs.shape[1] + c, max_steps)
+    if v < 0:
+        raise OracleError(-5)
+    return v
+
+
+def upstream_sum_absorb(dirs: np.ndarray, r: int, c: int, alpha: np.ndarray,
+                        w: np.ndarray | None = None, max_cells: int = 1 << 40) -> float:
+    """A at (r, c) with absorption, from its definition: the catchment's w,
+    each scaled by the product of alpha along its path to (r, c)."""
+    dirs = _dirs(dirs)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float32)
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+    v = _load().orc_upstream_sum_absorb(_p(dirs), dirs.shape[0], dirs.shape[1], _p(w), _p(alpha),
+                                        r * dirs.shape[1] + c, max_cells)
+    if v < 0:
+        raise OracleError(-5)
+    return v
+
+
+def downstream_sum_absorb(dirs: np.ndarray, r: int, c: int, g: np.ndarray, alpha: np.ndarray,
+                          max_steps: int = 1 << 40) -> float:
+    """lambda at (r, c) with absorption: g along the downstream path, each term
+    scaled by the product of alpha over the cells before it."""
+    dirs = _dirs(dirs)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float32)
+    v = _load().orc_downstream_sum_absorb(_p(dirs), dirs.shape[0], dirs.shape[1], _p(g), _p(alpha),
+                                          r * dirs.shape[1] + c, max_steps)
     if v < 0:
         raise OracleError(-5)
     return v

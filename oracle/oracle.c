@@ -409,6 +409,74 @@ double orc_downstream_sum(const uint8_t *dirs, int64_t rows, int64_t cols, const
     return s;
 }
 
+/*
+ * The same two per-cell definitions with absorption (Eq. (1) with alpha per
+ * cell): A(x) is the sum over the cells y of x's catchment of w(y) times the
+ * product of alpha over y's path up to x (x excluded), so the catchment
+ * search carries that product; lambda(x) sums g along x's downstream path,
+ * each term scaled by the product of alpha over the cells before it.
+ */
+double orc_upstream_sum_absorb(const uint8_t *dirs, int64_t rows, int64_t cols, const float *w,
+                               const float *alpha, int64_t x, int64_t max_cells)
+{
+    if (dirs[x] >= OR_NODATA) return dirs[x] == OR_NODATA ? 0.0 : -1.0;
+    int64_t cap = 1024, head = 0, tail = 0;
+    int64_t *q = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    double *pr = (double *)malloc((size_t)cap * sizeof(double));
+    if (!q || !pr) { free(q); free(pr); return -1.0; }
+    double s = 0.0;
+    q[tail] = x;
+    pr[tail++] = 1.0;
+    while (head < tail) {
+        int64_t c = q[head];
+        double p = pr[head++];
+        s += p * (w ? (double)w[c] : 1.0);
+        if (head > max_cells) { free(q); free(pr); return -1.0; }
+        int64_t r = c / cols, cc = c % cols;
+        for (int k = 0; k < 8; ++k) {
+            int64_t nr = r + OR_DR[k], nc = cc + OR_DC[k];
+            if (nr < 0 || nr >= rows || nc < 0 || nc >= cols) continue;
+            int64_t d = nr * cols + nc;
+            if (dirs[d] == OR_NODATA) continue;
+            if (receiver(dirs, rows, cols, d) != c) continue;
+            if (tail == cap) {
+                memmove(q, q + head, (size_t)(tail - head) * sizeof(int64_t));
+                memmove(pr, pr + head, (size_t)(tail - head) * sizeof(double));
+                tail -= head; head = 0;
+                if (tail == cap) {
+                    cap *= 2;
+                    int64_t *q2 = (int64_t *)realloc(q, (size_t)cap * sizeof(int64_t));
+                    if (!q2) { free(q); free(pr); return -1.0; }
+                    q = q2;
+                    double *p2 = (double *)realloc(pr, (size_t)cap * sizeof(double));
+                    if (!p2) { free(q); free(pr); return -1.0; }
+                    pr = p2;
+                }
+            }
+            q[tail] = d;
+            pr[tail++] = p * (double)alpha[d];
+        }
+    }
+    free(q);
+    free(pr);
+    return s;
+}
+
+double orc_downstream_sum_absorb(const uint8_t *dirs, int64_t rows, int64_t cols, const float *g,
+                                 const float *alpha, int64_t x, int64_t max_steps)
+{
+    if (dirs[x] >= OR_NODATA) return dirs[x] == OR_NODATA ? 0.0 : -1.0;
+    double s = 0.0, p = 1.0;
+    for (int64_t steps = 0; x >= 0; ++steps) {
+        if (steps > max_steps) return -1.0;
+        s += p * (double)g[x];
+        p *= (double)alpha[x];
+        x = receiver(dirs, rows, cols, x);
+        if (x == -2) return -1.0;
+    }
+    return s;
+}
+
 /* --------------------------------------------- tiled scheme, literally --- */
 /*
  * The paper's tiled method (Algorithms 1-3), written out literally, for small

@@ -563,3 +563,19 @@ def test_absorb_alpha_grad_chain_closed_form():
         Ak = sum(af ** j for j in range(k + 1))
         assert abs(grad[k] - Ak * af ** (n - 2 - k)) < 1e-14
     assert grad[-1] == 0
+
+
+def test_absorb_per_cell_definitions():
+    # catchment search with alpha products / downstream path sum with alpha
+    # prefixes, independent of the Kahn order, at every cell
+    d = random_acyclic_dirs(19, 23, 31)
+    alpha = synth.uniform(d.shape, 32)
+    w, g = synth.uniform(d.shape, 33), synth.uniform(d.shape, 34)
+    A = oracle.accum_absorb_f64(d, alpha, w)
+    lam = oracle.transpose_absorb_f64(d, alpha, g)
+    A1 = oracle.accum_absorb_f64(d, alpha)
+    for r in range(d.shape[0]):
+        for c in range(d.shape[1]):
+            assert abs(oracle.upstream_sum_absorb(d, r, c, alpha, w) - A[r, c]) <= 1e-12 * max(1.0, A[r, c])
+            assert abs(oracle.upstream_sum_absorb(d, r, c, alpha) - A1[r, c]) <= 1e-12 * max(1.0, A1[r, c])
+            assert abs(oracle.downstream_sum_absorb(d, r, c, g, alpha) - lam[r, c]) <= 1e-12 * max(1.0, lam[r, c])
