@@ -43,9 +43,15 @@ def receivers(dirs: torch.Tensor) -> torch.Tensor:
     return torch.where(ok, idx, torch.full_like(idx, -1)).view(-1)
 
 
-def test_dem32768_full_size(d8m):
-    wl = synth.WORKLOADS["dem32768"]
+@pytest.fixture(scope="module")
+def dem32768():
     z = synth.workload_dem("dem32768")
+    return z
+
+
+def test_dem32768_full_size(d8m, dem32768):
+    wl = synth.WORKLOADS["dem32768"]
+    z = dem32768
     rows, cols = z.shape
     dirs = d8m.d8_directions(torch.from_numpy(z).cuda())
     # D8 on sampled windows (with a one-cell halo) against the oracle
@@ -55,7 +61,6 @@ def test_dem32768_full_size(d8m):
         want = oracle.d8(z[r0 - 1:r0 + 257, c0 - 1:c0 + 257])[1:-1, 1:-1]
         np.testing.assert_array_equal(d_host[r0:r0 + 256, c0:c0 + 256], want)
     np.testing.assert_array_equal(d_host[:2, :300], oracle.d8(z[:3, :301])[:2, :300])
-    del z
 
     tile = (64, 64)
     A = d8m.flow_accum(dirs, acc_type="u32", tile=tile)
@@ -106,3 +111,62 @@ def test_dem32768_full_size(d8m):
         assert oracle.upstream_sum(d_host, r, c) == A_host[r, c], (r, c)
         want = oracle.downstream_sum(d_host, r, c, g_host)
         assert abs(L_host[r, c] - want) <= 1e-4 * max(want, 1.0), (r, c, L_host[r, c], want)
+
+
+def test_dem32768_absorb_full_size(d8m, dem32768):
+    """Absorption at full size in the benchmark's configuration (32 x 48 tiles,
+    alpha ~ U[0.5, 1), U[0, 1) weights and cotangents): local balance
+    A(c) = w(c) + sum of alpha(n) A(n) over c's donors and the recurrence
+    lambda(c) = g(c) + alpha(c) lambda(receiver) at every cell (float32
+    tolerance, as for the plain path), the alpha gradient A(n) lambda(receiver)
+    bit for bit, and sampled cells against the oracle's per-cell definitions."""
+    wl = synth.WORKLOADS["dem32768"]
+    rows, cols = dem32768.shape
+    dirs = d8m.d8_directions(torch.from_numpy(dem32768).cuda())
+    tile = (32, 48)
+    w_host = synth.uniform((rows, cols), wl["seed_g"])
+    alpha_host = (0.5 + 0.5 * synth.uniform((rows, cols), wl["seed_g"] + 1)).astype(np.float32)
+    w, alpha = torch.from_numpy(w_host).cuda(), torch.from_numpy(alpha_host).cuda()
+    A = d8m.flow_accum_absorb(dirs, alpha, w, tile=tile)
+    lam = d8m.flow_accum_absorb_adjoint(dirs, alpha, w, tile=tile)
+    ga = d8m.flow_accum_absorb_alpha_grad(dirs, A, lam)
+    torch.cuda.synchronize()
+
+    recv = receivers(dirs)
+    data = dirs.view(-1) != 9
+    has = recv >= 0
+    Ad, Wd, Al = A.view(-1).double(), w.view(-1).double(), alpha.view(-1).double()
+    inflow = torch.zeros_like(Ad)
+    inflow.index_add_(0, recv[has], Al[has] * Ad[has])
+    res = (Ad - Wd - inflow)[data].abs()
+    scale = (Ad.abs() + inflow.abs())[data]
+    assert (res <= 1e-4 * scale + 1e-6).all(), float((res / (scale + 1e-30)).max())
+    assert (Ad[~data] == 0).all()
+    del inflow, res, scale
+
+    L = lam.view(-1).double()
+    down = torch.zeros_like(L)
+    down[has] = Al[has] * L[recv[has]]
+    res = (L - Wd - down)[data].abs()
+    scale = (L.abs() + down.abs())[data]
+    assert (res <= 1e-4 * scale + 1e-6).all(), float((res / (scale + 1e-30)).max())
+    assert (L[~data] == 0).all()
+    del down, res, scale, Ad, Wd, L
+
+    # dL/dalpha(n) = A(n) lambda(receiver(n)): one float32 product
+    want = torch.zeros_like(A.view(-1))
+    want[has] = A.view(-1)[has] * lam.view(-1)[recv[has]]
+    assert torch.equal(ga.view(-1), want)
+    del want, ga
+
+    gen = torch.Generator(device="cuda").manual_seed(12)
+    cand = torch.randint(0, rows * cols, (4096,), device="cuda", generator=gen)
+    picks = cand[data[cand]][:30].tolist()
+    d_host = dirs.cpu().numpy()
+    A_host, L_host = A.cpu().numpy(), lam.cpu().numpy()
+    for i in picks:
+        r, c = divmod(int(i), cols)
+        want = oracle.upstream_sum_absorb(d_host, r, c, alpha_host, w_host)
+        assert abs(A_host[r, c] - want) <= 1e-4 * max(want, 1e-6), (r, c, A_host[r, c], want)
+        want = oracle.downstream_sum_absorb(d_host, r, c, w_host, alpha_host)
+        assert abs(L_host[r, c] - want) <= 1e-4 * max(want, 1e-6), (r, c, L_host[r, c], want)
