@@ -117,7 +117,14 @@ def cpu_baseline(z: np.ndarray, seed_g: int, rows: int) -> dict:
     oracle.transpose_f64(d, g, order)
     t2 = time.perf_counter()
     n = band.size
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n / (t2 - t0), "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_threads": os.cpu_count(),
             "sample": f"rows 0..{rows - 1} of the {z.shape[0]}x{z.shape[1]} raster "
                       f"({n} cells): Kahn forward in uint64 ({t1 - t0:.2f}s) + reverse-order "
                       f"adjoint in float64 ({t2 - t1:.2f}s), serial C"}
@@ -498,6 +505,23 @@ def run(args, bd):
         torch.cuda.synchronize()
         log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
         del src, dst
+    # achievable HBM bandwidth on this device: a plain 4 GiB device copy
+    # (bytes read + written over the copy's time, best of 3)
+    src = torch.empty(1 << 30, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_ms.append(e0.elapsed_time(e1))
+    copy_gbps = 2 * src.numel() * 4 / (min(copy_ms) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
     torch.cuda.synchronize()
     log(f"inputs resident: {rows}x{cols}, tile {tile}, workspace {ws.nbytes / 2**30:.2f} GiB")
 
@@ -514,14 +538,23 @@ def run(args, bd):
     d8.timing_enable(True)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
+    # events between the two calls of every step (no synchronisation inside)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
     torch.cuda.synchronize()
     start.record()
-    for _ in range(args.steps):
-        step()
+    marks[0].record()
+    for i in range(args.steps):
+        d8.flow_accum(dirs, acc_type="u32", tile=tile, ws=ws, out=A)
+        marks[2 * i + 1].record()
+        d8.flow_accum_adjoint(dirs, g, tile=tile, ws=ws, out=lam)
+        marks[2 * i + 2].record()
     stop.record()
     torch.cuda.synchronize()
     d8.timing_enable(False)
     ms_total = start.elapsed_time(stop)
+    t_fwd = [marks[2 * i].elapsed_time(marks[2 * i + 1]) for i in range(args.steps)]
+    t_adj = [marks[2 * i + 1].elapsed_time(marks[2 * i + 2]) for i in range(args.steps)]
+    t_step = [a + b for a, b in zip(t_fwd, t_adj)]
     kernels = d8.timing_report()
     d8.check_status(ws)
     ms_step = ms_total / args.steps
@@ -574,6 +607,11 @@ def run(args, bd):
                                f"weights uint32 forward + dense U[0,1) float32 adjoint",
                    "cells": n_cells, "rows": rows, "cols": cols, "tile": list(tile),
                    "parallelism": "single GPU"},
+        "ms_per_step_median": float(np.median(t_step)),
+        "ms_per_step_min": float(np.min(t_step)),
+        "t_fwd_ms_median": float(np.median(t_fwd)),
+        "t_adj_ms_median": float(np.median(t_adj)),
+        "hbm_copy_GBps": copy_gbps,
         "step_hbm_GBps_algorithmic": step_gbps,
         "step_frac_hbm_peak": step_gbps / HBM_PEAK_GBPS,
         "kernels_ms_per_step": {k: round(ms / args.steps, 4) for k, (ms, n) in kernels.items()},
