@@ -315,8 +315,11 @@ int d8_graph_destroy(void *graph_exec);
 int d8_check_status(const void *ws, void *stream);
 
 /*
- * Kernel timing, a profiling aid.  While enabled, every kernel launched by the
- * calls above is bracketed by two HIP events recorded on its launch stream.
+ * Kernel timing, a profiling aid.  on = 1: every kernel launched by the calls
+ * above is bracketed by two HIP events recorded on its launch stream; on = 2:
+ * only the per-tile passes (labels containing "pass"), which keeps the events
+ * out of the small kernels between them; on = 0: off (other values:
+ * D8_EINVAL).
  * d8_timing_report waits for the recorded events, writes up to max_entries
  * (kernel name, summed milliseconds, launch count) triples -- names are static
  * strings owned by the library -- forgets the records, and returns the number

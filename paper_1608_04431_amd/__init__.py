@@ -261,9 +261,10 @@ def check_status(ws: Workspace) -> None:
     _lib.check(rc, "status")
 
 
-def timing_enable(on: bool = True) -> None:
-    """Bracket every library kernel launch with HIP events (profiling aid)."""
-    _lib.load().d8_timing_enable(1 if on else 0)
+def timing_enable(on: bool = True, passes_only: bool = False) -> None:
+    """Bracket library kernel launches with HIP events (profiling aid): every
+    launch, or with passes_only the per-tile passes alone."""
+    _lib.check(_lib.load().d8_timing_enable((2 if passes_only else 1) if on else 0), "d8_timing_enable")
 
 
 def timing_report(max_entries: int = 64) -> dict:

@@ -84,7 +84,7 @@ struct TimedLaunch {
     hipEvent_t start, stop;
 };
 std::mutex g_timing_mu;
-bool g_timing_on = false;
+int g_timing_on = 0;  // 0 off, 1 every launch, 2 the per-tile passes only
 std::vector<TimedLaunch> g_timed;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -110,7 +110,7 @@ struct LaunchTimer {
     LaunchTimer(const char *n, hipStream_t s) : name(n), st(s)
     {
         std::lock_guard<std::mutex> lk(g_timing_mu);
-        if (g_timing_on && !g_capturing) {
+        if (g_timing_on != 0 && !g_capturing && (g_timing_on == 1 || std::strstr(n, "pass") != nullptr)) {
             a = pooled_event();
             (void)hipEventRecord(a, st);
         }
@@ -1144,8 +1144,9 @@ const char *d8_last_error_message(void) { return g_last_error.c_str(); }
 
 int d8_timing_enable(int on)
 {
+    if (on < 0 || on > 2) return D8_EINVAL;
     std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timing_on = on != 0;
+    g_timing_on = on;
     return D8_OK;
 }
 

@@ -32,6 +32,9 @@ def test_strerror_and_version():
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.d8_strerror(code)
     assert b"unknown" in lib.d8_strerror(42)
+    assert lib.d8_timing_enable(3) == _lib.D8_EINVAL
+    assert lib.d8_timing_enable(-1) == _lib.D8_EINVAL
+    assert lib.d8_timing_enable(0) == _lib.D8_OK
 
 
 def test_workspace_bytes():

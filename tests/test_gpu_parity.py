@@ -307,3 +307,22 @@ def test_empty_raster(d8m):
     assert d8m.flow_accum(d).shape == (0, 7)
     g = torch.empty((0, 7), dtype=torch.float32, device="cuda")
     assert d8m.flow_accum_adjoint(d, g).shape == (0, 7)
+
+
+def test_timing_modes(d8m):
+    d = dev(random_acyclic_dirs(200, 150, 4))
+    g = dev(synth.uniform((200, 150), 5))
+    d8m.timing_report()
+    d8m.timing_enable(True)
+    d8m.flow_accum(d, tile=(32, 32))
+    d8m.flow_accum_adjoint(d, g, tile=(32, 32))
+    d8m.timing_enable(False)
+    every = d8m.timing_report()
+    d8m.timing_enable(True, passes_only=True)
+    d8m.flow_accum(d, tile=(32, 32))
+    d8m.flow_accum_adjoint(d, g, tile=(32, 32))
+    d8m.timing_enable(False)
+    passes = d8m.timing_report()
+    assert set(passes) == {"fwd_pass1", "fwd_pass2", "adj_pass1", "adj_pass2"}
+    assert set(passes) < set(every) and "resolve_fwd" in every
+    assert all(n == 1 for _, n in passes.values())
