@@ -41,7 +41,8 @@ KERNEL_BYTES_PER_CELL = {
     "flow_accum_absorb_adjoint": 13.0,  # code 1 + alpha 4 + g 4 read, lambda 4 written
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
-SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (56, 48), (48, 64), (48, 48), (32, 64))
+SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (64, 32), (56, 48), (48, 64), (48, 48),
+               (32, 64))
 
 
 ABSORB_TILE = (32, 48)  # the absorption entry points' default shape
@@ -319,7 +320,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dem32768")
     ap.add_argument("--tile", type=int, nargs=2, default=None,
-                    help="tile shape of the timed run (default: the autotuner's table)")
+                    help="tile shape of both calls of the timed run (default: the autotuner's "
+                         "table, which holds one shape per call)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the tile-shape sweep")
     ap.add_argument("--cache-dir", default=os.environ.get("D8_CACHE_DIR"))
     ap.add_argument("--cpu-rows", type=int, default=6144,
@@ -440,7 +442,10 @@ def run(args, bd):
     n_cells = rows * cols
     dev = torch.device("cuda:0")
     from paper_1608_04431_amd.autotune import Tuner
-    tile = tuple(args.tile) if args.tile else Tuner().tile_for(rows, cols)
+    tuner = Tuner()
+    tile_f = tuple(args.tile) if args.tile else tuner.tile_for(rows, cols, kind="fwd")
+    tile_a = tuple(args.tile) if args.tile else tuner.tile_for(rows, cols, kind="adj")
+    tile = tile_f  # the forward's shape also serves the streamed leg
 
     # inputs resident in HBM before timing
     dem = torch.from_numpy(z).to(dev)
@@ -475,27 +480,29 @@ def run(args, bd):
     A = torch.empty((rows, cols), dtype=torch.int32, device=dev)
     lam = torch.empty((rows, cols), dtype=torch.float32, device=dev)
 
-    # tile-shape sweep: a few steps per candidate (the timed run below uses
-    # the autotuner's choice, or --tile)
-    sweep = {}
+    # tile-shape sweep: each call on its own, 3 runs per candidate after a
+    # warm one (the timed run below uses the autotuner's choices, or --tile)
+    sweep, sweep_f, sweep_a = {}, {}, {}
     if not args.no_sweep:
         for cand in SWEEP_TILES:
             wsc = d8.Workspace(rows, cols, cand, dev)
-            d8.flow_accum(dirs, acc_type="u32", tile=cand, ws=wsc, out=A)
-            d8.flow_accum_adjoint(dirs, g, tile=cand, ws=wsc, out=lam)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(3):
-                d8.flow_accum(dirs, acc_type="u32", tile=cand, ws=wsc, out=A)
-                d8.flow_accum_adjoint(dirs, g, tile=cand, ws=wsc, out=lam)
-            e1.record()
-            torch.cuda.synchronize()
+            key = f"{cand[0]}x{cand[1]}"
+            for out, call in ((sweep_f, lambda: d8.flow_accum(dirs, acc_type="u32", tile=cand, ws=wsc, out=A)),
+                              (sweep_a, lambda: d8.flow_accum_adjoint(dirs, g, tile=cand, ws=wsc, out=lam))):
+                call()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(3):
+                    call()
+                e1.record()
+                torch.cuda.synchronize()
+                out[key] = round(e0.elapsed_time(e1) / 3, 3)
             d8.check_status(wsc)
-            sweep[f"{cand[0]}x{cand[1]}"] = round(e0.elapsed_time(e1) / 3, 3)
+            sweep[key] = round(sweep_f[key] + sweep_a[key], 3)
             del wsc
-        log(f"tile sweep (ms/step): {sweep}")
-    ws = d8.Workspace(rows, cols, tile, dev)
+        log(f"tile sweep (ms): forward {sweep_f}, adjoint {sweep_a}")
+    ws = d8.Workspace(rows, cols, tile_f, dev, also=(tile_a,))
     if args.calibrate_copy > 0:
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -523,11 +530,12 @@ def run(args, bd):
     torch.cuda.empty_cache()
     log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
     torch.cuda.synchronize()
-    log(f"inputs resident: {rows}x{cols}, tile {tile}, workspace {ws.nbytes / 2**30:.2f} GiB")
+    log(f"inputs resident: {rows}x{cols}, tiles {tile_f} (forward) and {tile_a} (adjoint), "
+        f"workspace {ws.nbytes / 2**30:.2f} GiB")
 
     def step():
-        d8.flow_accum(dirs, acc_type="u32", tile=tile, ws=ws, out=A)
-        d8.flow_accum_adjoint(dirs, g, tile=tile, ws=ws, out=lam)
+        d8.flow_accum(dirs, acc_type="u32", tile=tile_f, ws=ws, out=A)
+        d8.flow_accum_adjoint(dirs, g, tile=tile_a, ws=ws, out=lam)
 
     for _ in range(args.warmup):
         step()
@@ -546,9 +554,9 @@ def run(args, bd):
     start.record()
     marks[0].record()
     for i in range(args.steps):
-        d8.flow_accum(dirs, acc_type="u32", tile=tile, ws=ws, out=A)
+        d8.flow_accum(dirs, acc_type="u32", tile=tile_f, ws=ws, out=A)
         marks[2 * i + 1].record()
-        d8.flow_accum_adjoint(dirs, g, tile=tile, ws=ws, out=lam)
+        d8.flow_accum_adjoint(dirs, g, tile=tile_a, ws=ws, out=lam)
         marks[2 * i + 2].record()
     stop.record()
     torch.cuda.synchronize()
@@ -574,10 +582,11 @@ def run(args, bd):
     # dominant kernel: the one with the largest share of the step
     per_launch = {k: (ms / n, n / args.steps) for k, (ms, n) in kernels.items()}
     dom = max(kernels, key=lambda k: kernels[k][0])
+    dom_tile = tile_a if dom.startswith("adj") else tile_f
     dom_ms = per_launch[dom][0]
     dom_bytes = KERNEL_BYTES_PER_CELL.get(dom)
     roofline = {"bound": "hbm", "kernel": dom, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "traffic": measured_traffic(dom, f"{args.workload}_{tile[0]}x{tile[1]}")}
+                "traffic": measured_traffic(dom, f"{args.workload}_{dom_tile[0]}x{dom_tile[1]}")}
     if dom_bytes is not None:
         achieved = dom_bytes * n_cells / (dom_ms * 1e-3) / 1e9
         roofline.update(achieved=achieved, frac=achieved / HBM_PEAK_GBPS,
@@ -616,7 +625,8 @@ def run(args, bd):
         "config": {"workload": f"{args.workload}: {rows}x{cols} uint8 D8 directions of a filled "
                                f"6-octave value-noise DEM (wavelength {wl['lambda0']}), unit "
                                f"weights uint32 forward + dense U[0,1) float32 adjoint",
-                   "cells": n_cells, "rows": rows, "cols": cols, "tile": list(tile),
+                   "cells": n_cells, "rows": rows, "cols": cols, "tile_fwd": list(tile_f),
+                   "tile_adj": list(tile_a),
                    "parallelism": "single GPU"},
         "ms_per_step_median": float(np.median(t_step)),
         "ms_per_step_min": float(np.min(t_step)),
@@ -628,6 +638,8 @@ def run(args, bd):
         "kernels_ms_per_step": {k: round(ms / n_break, 4) for k, (ms, n) in breakdown.items()},
         "passes_ms_per_step_timed": {k: round(ms / args.steps, 4) for k, (ms, n) in kernels.items()},
         "tile_sweep_ms_per_step": sweep,
+        "tile_sweep_ms_fwd": sweep_f,
+        "tile_sweep_ms_adj": sweep_a,
         "tuner_device_key": __import__("paper_1608_04431_amd.autotune", fromlist=["x"]).device_key(),
         "roofline": roofline,
         "d8_directions": {"ms": round(d8_ms, 4), "bytes_per_cell": KERNEL_BYTES_PER_CELL["d8_directions"],

@@ -49,9 +49,12 @@ def workspace_bytes(rows: int, cols: int, tile: tuple[int, int] = (0, 0)) -> int
 class Workspace:
     """Caller-owned device scratch for flow_accum / flow_accum_adjoint."""
 
-    def __init__(self, rows: int, cols: int, tile: tuple[int, int] = (0, 0), device=None):
+    def __init__(self, rows: int, cols: int, tile: tuple[int, int] = (0, 0), device=None,
+                 also: tuple[tuple[int, int], ...] = ()):
+        """Sized for `tile` and every shape in `also` (e.g. the forward's and
+        the adjoint's tiles when they differ)."""
         self.rows, self.cols, self.tile = rows, cols, tuple(tile)
-        self.nbytes = workspace_bytes(rows, cols, self.tile)
+        self.nbytes = max(workspace_bytes(rows, cols, tuple(t)) for t in (self.tile, *also))
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device or "cuda")
 
     def fits(self, rows: int, cols: int, tile) -> bool:

@@ -1,8 +1,10 @@
 """Tile-shape autotuner.
 
 Times candidate tile shapes on a sample raster of a size class (forward in
-float32 plus the adjoint, events on the current stream) and keeps the
-fastest per (device, size class) in a JSON cache.  The paper leaves the tile
+float32 and the adjoint, each on its own, events on the current stream) and
+keeps the fastest per (device, size class) in a JSON cache: one shape for
+both calls ("tile") and the fastest for each call ("tile_fwd", "tile_adj");
+the two calls need not share a shape.  The paper leaves the tile
 size free (Section "The Algorithm": equal tiles are a convenience); on the GPU
 it trades LDS per tile (resident tiles per CU) against the number of
 perimeter cells in the global graph.
@@ -67,9 +69,10 @@ class Tuner:
     def _key(self, batch: bool) -> str:
         return self.key + ("|batch" if batch else "")
 
-    def lookup(self, rows: int, cols: int, batch: bool = False):
+    def lookup(self, rows: int, cols: int, batch: bool = False, kind: str | None = None):
         """The cached tile for the size class: this device's entry, else one
-        for its architecture (the packaged table is keyed by architecture)."""
+        for its architecture (the packaged table is keyed by architecture).
+        kind "fwd" / "adj" takes that call's own shape where one is stored."""
         cls = size_class(rows, cols)
         arch = self.key.split("|")[-1]
         keys = (self._key(batch), arch + ("|batch" if batch else ""))
@@ -77,17 +80,19 @@ class Tuner:
             for key in keys:
                 entry = table.get(key, {}).get(cls)
                 if entry:
-                    return tuple(int(v) for v in entry["tile"])
+                    t = entry.get(f"tile_{kind}") if kind else None
+                    return tuple(int(v) for v in (t or entry["tile"]))
         return None
 
-    def tile_for(self, rows: int, cols: int, batch: bool = False) -> tuple[int, int]:
+    def tile_for(self, rows: int, cols: int, batch: bool = False, kind: str | None = None) -> tuple[int, int]:
         """Tile shape for a raster run on its own, or (batch=True) as one of
-        many rasters in a batch; a batch lookup falls back to the single one."""
+        many rasters in a batch (a batch lookup falls back to the single one);
+        kind "fwd" or "adj" for the forward or the adjoint call alone."""
         if batch:
             t = self.lookup(rows, cols, True)
             if t:
                 return t
-        return self.lookup(rows, cols) or DEFAULT_TILE
+        return self.lookup(rows, cols, kind=kind) or DEFAULT_TILE
 
     def tune(self, dirs: torch.Tensor, weights: torch.Tensor | None = None,
              grad_acc: torch.Tensor | None = None, candidates=CANDIDATES, reps: int = 3,
@@ -103,33 +108,35 @@ class Tuner:
             grad_acc = torch.ones(dirs.shape, dtype=torch.float32, device=dirs.device)
         acc = torch.empty(dirs.shape, dtype=torch.float32, device=dirs.device)
         lam = torch.empty_like(acc)
-        times = {}
+        fwd, adj = {}, {}
         for tile in candidates:
             th, tw = min(tile[0], rows), min(tile[1], cols)
-            if (th, tw) in times:
+            if (th, tw) in fwd:
                 continue
             ws = Workspace(rows, cols, (th, tw), dirs.device)
-
-            def step():
-                flow_accum(dirs, weights, "f32", (th, tw), ws, acc)
-                flow_accum_adjoint(dirs, grad_acc, (th, tw), ws, lam)
-
-            step()
-            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            best = None
-            for _ in range(reps):
-                start.record()
-                step()
-                stop.record()
-                stop.synchronize()
-                ms = start.elapsed_time(stop)
-                best = ms if best is None else min(best, ms)
-            times[(th, tw)] = best
+            for out, call in ((fwd, lambda: flow_accum(dirs, weights, "f32", (th, tw), ws, acc)),
+                              (adj, lambda: flow_accum_adjoint(dirs, grad_acc, (th, tw), ws, lam))):
+                call()
+                start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                best = None
+                for _ in range(reps):
+                    start.record()
+                    call()
+                    stop.record()
+                    stop.synchronize()
+                    ms = start.elapsed_time(stop)
+                    best = ms if best is None else min(best, ms)
+                out[(th, tw)] = best
+        times = {t: fwd[t] + adj[t] for t in fwd}
         tile = min(times, key=times.get)
+        tf, ta = min(fwd, key=fwd.get), min(adj, key=adj.get)
         cls = size_class(rows, cols)
         self.user.setdefault(self.key, {})[cls] = {
             "tile": list(tile), "ms": round(times[tile], 4), "sample": [rows, cols],
-            "candidates": {f"{a}x{b}": round(v, 4) for (a, b), v in times.items()}}
+            "tile_fwd": list(tf), "tile_adj": list(ta), "ms_split": round(fwd[tf] + adj[ta], 4),
+            "candidates": {f"{a}x{b}": round(v, 4) for (a, b), v in times.items()},
+            "candidates_fwd": {f"{a}x{b}": round(v, 4) for (a, b), v in fwd.items()},
+            "candidates_adj": {f"{a}x{b}": round(v, 4) for (a, b), v in adj.items()}}
         if save:
             self.save()
         return times
@@ -197,8 +204,14 @@ def table_from_bench(bench: dict, arch: str) -> dict:
     if sweep:
         rows, cols = bench["config"]["rows"], bench["config"]["cols"]
         best = min(sweep, key=sweep.get)
-        single[size_class(rows, cols)] = {"tile": [int(v) for v in best.split("x")],
-                                          "ms": sweep[best], "candidates": sweep}
+        entry = {"tile": [int(v) for v in best.split("x")], "ms": sweep[best], "candidates": sweep}
+        for kind in ("fwd", "adj"):
+            split = bench.get(f"tile_sweep_ms_{kind}") or {}
+            if split:
+                b = min(split, key=split.get)
+                entry[f"tile_{kind}"] = [int(v) for v in b.split("x")]
+                entry[f"candidates_{kind}"] = split
+        single[size_class(rows, cols)] = entry
     return {arch: single, arch + "|batch": batch}
 
 

@@ -35,6 +35,13 @@ def test_lookup_order_and_fallback(tmp_path, monkeypatch):
     assert t.tile_for(300, 500, batch=True) == (48, 64)    # batch keeps its own entry
     t.save()
     assert json.loads(user.read_text()) == t.user
+    # per-call shapes where an entry has them; the shared shape otherwise
+    t.user = {"Some GPU|gfx950": {"512": {"tile": [64, 32], "tile_fwd": [64, 44], "tile_adj": [48, 48]}}}
+    assert t.tile_for(300, 500, kind="fwd") == (64, 44)
+    assert t.tile_for(300, 500, kind="adj") == (48, 48)
+    assert t.tile_for(300, 500) == (64, 32)
+    t.user = {"Some GPU|gfx950": {"512": {"tile": [64, 32]}}}
+    assert t.tile_for(300, 500, kind="fwd") == (64, 32)
     t.key = "Other|gfx942"
     assert t.tile_for(300, 500) == autotune.DEFAULT_TILE
 
@@ -42,10 +49,14 @@ def test_lookup_order_and_fallback(tmp_path, monkeypatch):
 def test_table_from_bench():
     bench = {"config": {"rows": 32768, "cols": 32768},
              "tile_sweep_ms_per_step": {"64x64": 30.0, "64x48": 29.0},
+             "tile_sweep_ms_fwd": {"64x64": 16.0, "64x48": 17.0},
+             "tile_sweep_ms_adj": {"64x64": 14.0, "64x48": 12.0},
              "batched": {"tuning_ms": {"256": {"64x64": 2.0, "32x32": 1.5}},
                          "tuning_single_ms": {"256": {"64x64": 0.5, "32x32": 0.4}}}}
     t = autotune.table_from_bench(bench, "gfx950")
     assert t["gfx950"]["32768"]["tile"] == [64, 48]
+    assert t["gfx950"]["32768"]["tile_fwd"] == [64, 64]
+    assert t["gfx950"]["32768"]["tile_adj"] == [64, 48]
     assert t["gfx950"]["256"]["tile"] == [32, 32]
     assert t["gfx950|batch"]["256"]["tile"] == [32, 32]
 
@@ -56,8 +67,10 @@ def test_packaged_table_is_valid():
         if key == "source":
             continue
         for cls, entry in table.items():
-            th, tw = entry["tile"]
-            assert 1 <= th <= 64 and 1 <= tw <= 64, (key, cls)
+            for k in ("tile", "tile_fwd", "tile_adj"):
+                if k in entry:
+                    th, tw = entry[k]
+                    assert 1 <= th <= 64 and 1 <= tw <= 64, (key, cls, k)
 
 
 @pytest.mark.gpu
@@ -75,7 +88,9 @@ def test_tune_on_device(tmp_path):
     times = t.tune(dirs, w, w, candidates=((64, 64), (32, 32)), reps=1)
     assert set(times) == {(64, 64), (32, 32)} and all(v > 0 for v in times.values())
     assert t.tile_for(300, 200) == min(times, key=times.get)
-    assert json.load(open(tmp_path / "tiles.json"))[t.key]["512"]["tile"]
+    entry = json.load(open(tmp_path / "tiles.json"))[t.key]["512"]
+    assert entry["tile"] and tuple(entry["tile_fwd"]) in times and tuple(entry["tile_adj"]) in times
+    assert t.tile_for(300, 200, kind="adj") == tuple(entry["tile_adj"])
     samples = [(dirs, w, w), (dirs[:100].contiguous(), w[:100].contiguous(), w[:100].contiguous())]
     bt = t.tune_batch(samples, candidates=((64, 64), (32, 32)), reps=1)
     assert set(bt) == {(64, 64), (32, 32)}

@@ -1,5 +1,6 @@
 """The 32768 x 32768 workload in the launch configuration the benchmark
-times (64 x 64 tiles): D8 on sampled windows, then unit-count accumulation
+times (the autotuner's tile shapes for the forward and the adjoint call of
+this size class): D8 on sampled windows, then unit-count accumulation
 and the float32 adjoint checked at every cell through properties that
 determine them (local balance against the donors, the adjoint recurrence
 along receivers; both are computed here with plain tensor ops, independently
@@ -62,13 +63,15 @@ def test_dem32768_full_size(d8m, dem32768):
         np.testing.assert_array_equal(d_host[r0:r0 + 256, c0:c0 + 256], want)
     np.testing.assert_array_equal(d_host[:2, :300], oracle.d8(z[:3, :301])[:2, :300])
 
-    tile = (64, 64)
-    A = d8m.flow_accum(dirs, acc_type="u32", tile=tile)
+    from paper_1608_04431_amd.autotune import Tuner
+    tuner = Tuner()
+    tile_f, tile_a = tuner.tile_for(rows, cols, kind="fwd"), tuner.tile_for(rows, cols, kind="adj")
+    A = d8m.flow_accum(dirs, acc_type="u32", tile=tile_f)
     g = torch.from_numpy(synth.uniform((rows, cols), wl["seed_g"])).cuda()
-    lam = d8m.flow_accum_adjoint(dirs, g, tile=tile)
+    lam = d8m.flow_accum_adjoint(dirs, g, tile=tile_a)
     torch.cuda.synchronize()
     # the same forward with the raster in host memory, streamed in bands
-    As = d8m.flow_accum_streamed(dirs.cpu().pin_memory(), tile=tile)
+    As = d8m.flow_accum_streamed(dirs.cpu().pin_memory(), tile=tile_f)
     assert torch.equal(As, A.cpu())
     del As
 
