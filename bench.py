@@ -343,8 +343,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the method would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(row bands of tiles per GPU with one exchange of band-boundary records "
+              "would shard it; not built).", file=sys.stderr)
         sys.exit(2)
 
     # the batch is generated by forked workers before anything touches the GPU
