@@ -170,6 +170,9 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
  * the values, so smaller tiles keep more of them resident per CU.
  */
 size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols);
+int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *alpha, float *acc,
+                      int64_t rows, int64_t cols, int tile_rows, int tile_cols, void *ws, size_t ws_bytes,
+                      void *stream);
 
 /*
  * Adjoint of flow_accum_absorb with respect to the weights:
@@ -187,9 +190,6 @@ size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int 
 int flow_accum_absorb_adjoint(const uint8_t *dirs, const float *alpha, const float *grad_acc,
                               float *grad_weights, int64_t rows, int64_t cols, int tile_rows, int tile_cols,
                               void *ws, size_t ws_bytes, void *stream);
-int flow_accum_absorb(const uint8_t *dirs, const float *weights, const float *alpha, float *acc,
-                      int64_t rows, int64_t cols, int tile_rows, int tile_cols, void *ws, size_t ws_bytes,
-                      void *stream);
 
 /*
  * Gradient with respect to the absorption fractions: for a loss with
