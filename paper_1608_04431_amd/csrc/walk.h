@@ -623,7 +623,7 @@ __device__ inline int fwd_walks(const WTile &Tl, uint8_t *lds8, uint8_t *cb8, ui
 // or to the end of its flow inside the tile (kLlTerm), or kLlCycle after more
 // steps than the tile has cells.  Only the low nibble (the code) of each
 // cell byte is read.  Offsets as in fwd_walks; an idle lane steps to frame
-// cell 0 and writes ll[ll_dummy].
+// cell 0 (ll_dummy is the ring index of no walk).
 // ABS: also the product of alpha over each entry's path up to (without) its
 // exit, stored to pathp[node] (global) for the entry's node.
 template <bool ABS = false>
@@ -675,7 +675,8 @@ __device__ inline void link_walks(const WTile &Tl, const uint8_t *cb8, uint32_t 
         ++steps;
         const bool stop = nk >= (uint32_t)kNoFlow || steps > max_steps;
         const uint16_t v = steps > max_steps ? kLlCycle : (nk == kFrameTile ? (uint16_t)cur : kLlTerm);
-        ll[(act && stop) ? ring : ll_dummy] = v;
+        // only finishing walks store (the others would all hit one dummy slot)
+        if (act && stop) ll[ring] = v;
         if constexpr (ABS) {
             if (act && stop) pathp[Tl.base + ring] = p;
             p *= al;
