@@ -48,7 +48,7 @@ def gpu_loss_grad(d8m, d, w, gauges, t, tile=(0, 0)):
     tt = torch.from_numpy(t.astype(np.float32)).cuda()
     loss = ((A.reshape(-1)[gi] - tt) ** 2).sum()
     loss.backward()
-    return A.detach().cpu().numpy(), float(loss), wt.grad.cpu().numpy()
+    return A.detach().cpu().numpy(), float(loss.detach()), wt.grad.cpu().numpy()
 
 
 def test_gauge_loss_gradient_8192(d8m):
