@@ -316,7 +316,7 @@ def batch_leg(bd: BatchData, reps: int) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dem32768")
     ap.add_argument("--tile", type=int, nargs=2, default=None,
