@@ -192,6 +192,53 @@ class BatchData:
         self.shm = {}
 
 
+def _oracle_worker(job):
+    """One DEM of the batch through the CPU oracle: D8 (not timed), then the
+    Kahn forward in float64 and the reverse-order adjoint, timed."""
+    import oracle
+    i, rows, cols, off = job
+    n = rows * cols
+    view = lambda key: np.ndarray((rows, cols), dtype=np.float32, buffer=_SHM[key].buf, offset=4 * off)
+    d = oracle.d8(view("dem"))
+    w, g = view("w"), view("g")
+    t0 = time.perf_counter()
+    _, order = oracle.accum_f64(d, w, want_order=True)
+    oracle.transpose_f64(d, g, order)
+    return n, time.perf_counter() - t0
+
+
+def oracle_batch_baseline(bd: BatchData, workers: int, max_cells: float = 1.5e9) -> dict | None:
+    """The CPU oracle over the batch's first DEMs (up to max_cells cells), one
+    DEM per task on `workers` host processes (the paper's delegation of tiles
+    to workers): aggregate cells/s = the sum over processes of their cells
+    over their summed accumulate + adjoint time.  Runs before anything
+    touches the GPU."""
+    jobs, cells = [], 0
+    for i, (rows, cols, *_rest) in enumerate(bd.shapes):
+        if cells >= max_cells:
+            break
+        jobs.append((i, rows, cols, int(bd.off[i])))
+        cells += rows * cols
+    jobs.sort(key=lambda j: -(j[1] * j[2]))
+    names = {k: v.name for k, v in bd.shm.items()}
+    per_worker = {}
+    with mp.get_context("fork").Pool(workers, _batch_worker_init, (names,)) as pool:
+        for (n, t), pid in pool.imap_unordered(_oracle_worker_pid, jobs, chunksize=1):
+            c, tt = per_worker.get(pid, (0, 0.0))
+            per_worker[pid] = (c + n, tt + t)
+    slowest = max(tt for _, tt in per_worker.values())
+    rate = sum(c / tt for c, tt in per_worker.values() if tt > 0)
+    return {"value": rate, "unit": "cells/s", "cores": len(per_worker), "kind": "oracle",
+            "sample": f"the first {len(jobs)} of the batch's {len(bd.shapes)} DEMs ({cells} cells): float64 "
+                      f"Kahn forward + reverse-order adjoint per DEM (D8 not timed), one DEM per task on "
+                      f"{workers} host processes; value = the sum of the processes' own rates; "
+                      f"slowest process {slowest:.2f}s ({cells / slowest:.3e} cells/s by it)"}
+
+
+def _oracle_worker_pid(job):
+    return _oracle_worker(job), os.getpid()
+
+
 def batch_leg(bd: BatchData, reps: int) -> dict:
     import torch
     import paper_1608_04431_amd as d8
@@ -355,8 +402,18 @@ def main():
         bd = BatchData(args.batch, args.workers)
         log(f"generated batch of {args.batch} DEMs ({bd.cells:.3e} cells) in {time.time() - t:.1f}s "
             f"with {args.workers} workers")
+    cpu_batch = None
+    if bd is not None and args.cpu_rows > 0:
+        # the oracle on all host workers, before anything touches the GPU
+        try:
+            cpu_batch = oracle_batch_baseline(bd, args.workers)
+            log(f"oracle over the batch: {cpu_batch['value']:.3e} cells/s on {cpu_batch['cores']} processes")
+        except Exception as e:  # reported, never fatal to the bench line
+            cpu_batch = {"error": repr(e)}
     try:
         out = run(args, bd)
+        if cpu_batch is not None and out.get("batched") is not None:
+            out["batched"]["cpu_baseline"] = cpu_batch
     finally:
         if bd is not None:
             bd.close()
