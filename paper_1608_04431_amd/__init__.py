@@ -284,20 +284,22 @@ def timing_report(max_entries: int = 64) -> dict:
 
 
 class FlowAccum(torch.autograd.Function):
-    """A = FlowAccum.apply(w, dirs[, tile]): differentiable in the weights w;
-    the backward pass is flow_accum_adjoint."""
+    """A = FlowAccum.apply(w, dirs[, tile[, tile_adj]]): differentiable in the
+    weights w; the backward pass is flow_accum_adjoint, on tile_adj when given
+    (the two calls need not share a tile shape)."""
 
     @staticmethod
-    def forward(ctx, w, dirs, tile=(0, 0)):
+    def forward(ctx, w, dirs, tile=(0, 0), tile_adj=None):
         ctx.save_for_backward(dirs)
         ctx.tile = tuple(tile)
+        ctx.tile_adj = tuple(tile_adj) if tile_adj is not None else ctx.tile
         return flow_accum(dirs, w.contiguous(), acc_type="f32", tile=ctx.tile)
 
     @staticmethod
     def backward(ctx, grad_a):
         (dirs,) = ctx.saved_tensors
-        gw = flow_accum_adjoint(dirs, grad_a.contiguous(), tile=ctx.tile)
-        return gw, None, None
+        gw = flow_accum_adjoint(dirs, grad_a.contiguous(), tile=ctx.tile_adj)
+        return gw, None, None, None
 
 
 class FlowAccumAbsorb(torch.autograd.Function):

@@ -103,3 +103,16 @@ def test_flowaccum_forward_matches_flow_accum(d8m):
     a = d8m.FlowAccum.apply(w, d)
     b = d8m.flow_accum(d, w, acc_type="f32")
     assert torch.equal(a, b)
+
+
+def test_flowaccum_separate_adjoint_tile(d8m):
+    # the backward may run on another tile shape than the forward: the same
+    # gradient as flow_accum_adjoint on that shape, bit for bit
+    z = synth.dem(300, 400, seed=10, lambda0=64, ocean=True)
+    d = torch.from_numpy(oracle.d8(z)).cuda()
+    w = torch.from_numpy(synth.uniform(z.shape, 11)).cuda().requires_grad_(True)
+    c = torch.from_numpy(synth.uniform(z.shape, 12)).cuda()
+    a = d8m.FlowAccum.apply(w, d, (64, 44), (64, 32))
+    (a * c).sum().backward()
+    assert torch.equal(a.detach(), d8m.flow_accum(d, w.detach(), acc_type="f32", tile=(64, 44)))
+    assert torch.equal(w.grad, d8m.flow_accum_adjoint(d, c, tile=(64, 32)))
