@@ -56,6 +56,12 @@ def test_gauge_loss_gradient_8192(d8m):
     assert gauges.size == 64
     A, loss, grad = gpu_loss_grad(d8m, d, w, gauges, t)
     A_ref = oracle.accum_f64(d, w)
+    # the forward at every cell, not only through the loss
+    valid = d != 9
+    pos = valid & (A_ref > 0)
+    rel = np.abs(A[pos].astype(np.float64) - A_ref[pos]) / A_ref[pos]
+    assert rel.max() <= 1e-4, f"forward max rel err {rel.max():.3e}"
+    assert (A[valid & (A_ref == 0)] == 0).all() and (A[~valid] == 0).all()
     res = A_ref.ravel()[gauges] - t
     loss_ref = float((res ** 2).sum())
     assert abs(loss - loss_ref) <= 1e-4 * loss_ref

@@ -65,16 +65,20 @@ def test_batch_equals_single_calls_and_oracle(d8m):
         a1, l1 = single(d8m, d, w, g, t)
         np.testing.assert_array_equal(r.acc.cpu().numpy(), a1, err_msg=f"acc {d.shape} {t}")
         np.testing.assert_array_equal(r.grad_weights.cpu().numpy(), l1, err_msg=f"lam {d.shape} {t}")
-    # two of them against the oracle as well
-    for k in (0, 5):
-        d, w, g, t = data[k]
-        want = oracle.accum_f64(d, w)
-        got = rasters[k].acc.cpu().numpy().astype(np.float64)
+    # every raster against the oracle, per cell: float32 forward within 1e-4
+    # relative of the float64 sums (exactly 0 where they are 0), the adjoint of
+    # the dense cotangent U[0, 1) likewise
+    for (d, w, g, t), r in zip(data, rasters):
+        if d.size == 0:
+            continue
         valid = d != 9
-        assert np.abs(got[valid] - want[valid]).max() <= 1e-4 * np.abs(want[valid]).max()
-        lam = oracle.transpose_f64(d, g)
-        gotl = rasters[k].grad_weights.cpu().numpy().astype(np.float64)
-        assert np.abs(gotl[valid] - lam[valid]).max() <= 1e-4 * np.abs(lam[valid]).max()
+        for got, want, what in ((r.acc, oracle.accum_f64(d, w), "acc"),
+                                (r.grad_weights, oracle.transpose_f64(d, g), "lam")):
+            got = got.cpu().numpy().astype(np.float64)
+            pos = valid & (want > 0)
+            rel = np.abs(got[pos] - want[pos]) / want[pos]
+            assert rel.size == 0 or rel.max() <= 1e-4, f"{what} {d.shape} {t}: {rel.max():.3e}"
+            assert (got[valid & (want == 0)] == 0).all() and (got[~valid] == 0).all()
 
 
 def test_batch_modes_separately(d8m):
