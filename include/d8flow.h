@@ -307,6 +307,28 @@ int d8_graph_launch(void *graph_exec, void *stream);
 int d8_graph_destroy(void *graph_exec);
 
 /*
+ * flow_accum for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same computation and results as flow_accum with the same arguments, but the
+ * workspace is the library's own device array of D8_NOALLOC_SCRATCH_BYTES,
+ * one per GPU, held from the library's load until the process ends.  The
+ * caller passes inputs and outputs only.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).
+ * status: NULL, or a caller-owned device uint32 that receives the call's data
+ * status when its kernels have run: 0 ok, 4 an invalid direction code, 5 a
+ * cycle (outputs are then undefined).
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU (other streams, other threads) race; calls on one stream are ordered.
+ * Returns D8_EWORKSPACE when the raster needs a workspace larger than the array
+ * (d8_workspace_bytes(rows, cols, tile_rows, tile_cols) >
+ * D8_NOALLOC_SCRATCH_BYTES: about 2e7 cells at 64 x 64 tiles), otherwise what
+ * flow_accum returns.
+ */
+#define D8_NOALLOC_SCRATCH_BYTES (64u << 20)
+int flow_accum_noalloc(const uint8_t *dirs, const float *weights, void *acc, int acc_type, int64_t rows,
+                       int64_t cols, int tile_rows, int tile_cols, uint32_t *status, void *stream);
+
+/*
  * Waits for `stream`, then returns the data-dependent status recorded in
  * `ws` by the last flow_accum / flow_accum_adjoint / batch call on it: D8_OK,
  * D8_EDIRCODE or D8_ECYCLE (or D8_EHIP if the wait itself fails, D8_EINVAL for

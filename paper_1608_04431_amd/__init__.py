@@ -19,7 +19,7 @@ NODATA = 9
 __all__ = ["d8_directions", "d8_directions_rho8", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
            "check_status", "FlowAccum", "FlowAccumAbsorb", "D8Error", "Raster", "Batch", "BatchGraph",
            "stream_workspace_bytes", "flow_accum_streamed", "flow_accum_absorb",
-           "flow_accum_absorb_adjoint", "flow_accum_absorb_alpha_grad"]
+           "flow_accum_absorb_adjoint", "flow_accum_absorb_alpha_grad", "flow_accum_noalloc"]
 
 
 def _stream(device: torch.device) -> int:
@@ -121,6 +121,36 @@ def flow_accum(dirs: torch.Tensor, weights: torch.Tensor | None = None, acc_type
                                 D8_ACC_U32 if acc_type == "u32" else D8_ACC_F32, rows, cols,
                                 tile[0], tile[1], _ptr(ws.buf), ws.nbytes, _stream(dirs.device))
     _lib.check(rc, "flow_accum")
+    return out
+
+
+def flow_accum_noalloc(dirs: torch.Tensor, weights: torch.Tensor | None = None, acc_type: str = "auto",
+                       tile: tuple[int, int] = (0, 0), out: torch.Tensor | None = None,
+                       status: torch.Tensor | None = None) -> torch.Tensor:
+    """flow_accum on the library's own per-GPU scratch array (no workspace, no
+    device allocation in the call when `out` is given).  `status`: optional
+    int32 device tensor of one element that receives the data status (0 ok,
+    4 invalid code, 5 cycle).  Overlapping calls on one GPU race."""
+    _check_raster(dirs, torch.uint8, "dirs")
+    if acc_type == "auto":
+        acc_type = "u32" if weights is None else "f32"
+    if acc_type not in ("u32", "f32"):
+        raise ValueError("acc_type must be 'u32' or 'f32'")
+    if weights is not None:
+        _check_raster(weights, torch.float32, "weights")
+        if weights.shape != dirs.shape:
+            raise ValueError("weights and dirs differ in shape")
+    rows, cols = dirs.shape
+    dt = torch.int32 if acc_type == "u32" else torch.float32
+    if out is None:
+        out = torch.empty((rows, cols), dtype=dt, device=dirs.device)
+    _check_raster(out, dt, "out")
+    if status is not None and (status.dtype != torch.int32 or not status.is_cuda or status.numel() != 1):
+        raise ValueError("status must be a one-element int32 device tensor")
+    rc = _lib.load().flow_accum_noalloc(_ptr(dirs), _ptr(weights), _ptr(out),
+                                        D8_ACC_U32 if acc_type == "u32" else D8_ACC_F32, rows, cols,
+                                        tile[0], tile[1], _ptr(status), _stream(dirs.device))
+    _lib.check(rc, "flow_accum_noalloc")
     return out
 
 

@@ -799,6 +799,35 @@ int launch_d8(const float *dem, const float *rnd, uint8_t *dirs, int64_t rows, i
     return last_error();
 }
 
+// ---- flow_accum without allocation: the workspace is a file-scope device
+// array, one copy per GPU.  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address comes from hipGetSymbolAddress, once
+// per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[D8_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device id; null until looked up
+
+int scratch_address(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return D8_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[(size_t)dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return D8_EHIP;
+        }
+        g_scratch_ptr[(size_t)dev] = ptr;
+    }
+    *out = g_scratch_ptr[(size_t)dev];
+    return D8_OK;
+}
+
+__global__ void copy_status(const uint32_t *status, uint32_t *out) { out[0] = status[0]; }
+
 }  // namespace
 
 extern "C" {
@@ -914,6 +943,23 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
               (adj_finish<<<ntiles, thr, 0, st>>>(g, root8, cmap, jw[0], jw[1], jstate, grad_weights)));
     (void)rounds;
     return last_error();
+}
+
+int flow_accum_noalloc(const uint8_t *dirs, const float *weights, void *acc, int acc_type, int64_t rows,
+                       int64_t cols, int tile_rows, int tile_cols, uint32_t *status, void *stream)
+{
+    const size_t need = d8_workspace_bytes(rows, cols, tile_rows, tile_cols);
+    if (need == 0) return D8_EINVAL;
+    if (need > (size_t)D8_NOALLOC_SCRATCH_BYTES) return D8_EWORKSPACE;
+    void *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc != D8_OK) return rc;
+    rc = flow_accum(dirs, weights, acc, acc_type, rows, cols, tile_rows, tile_cols, ws,
+                    (size_t)D8_NOALLOC_SCRATCH_BYTES, stream);
+    if (rc != D8_OK || !status) return rc;
+    hipStream_t st = as_stream(stream);
+    copy_status<<<1, 1, 0, st>>>(reinterpret_cast<const uint32_t *>(ws), status);
+    return hipGetLastError() == hipSuccess ? D8_OK : D8_EHIP;
 }
 
 // ----------------------------------------------------------- absorption --
