@@ -33,9 +33,22 @@ constexpr int kNodeBlock = 256;
 
 struct Layout {
     size_t status, jstate, link, entry, succ, indeg, val32, acc64, ext64, ptr2, root8, total;
+    size_t off, kids, bsum;  // the float forward's children lists, where root8 lies (adjoint only)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Children lists of the float forward's resolve, placed over an area the
+// forward does not otherwise use (the adjoint's root labels): offsets and
+// children (a word per node each) and one word per 4096 nodes for the scan.
+// Returns the end of the lists.
+size_t csr_place(size_t at, size_t N, size_t &off, size_t &kids, size_t &bsum)
+{
+    off = at;
+    kids = align256(off + N * sizeof(uint32_t));
+    bsum = align256(kids + N * sizeof(uint32_t));
+    return align256(bsum + (N / (size_t)kCompactNodes + 2) * sizeof(uint32_t));
+}
 
 Layout layout_for(const Geo &g)
 {
@@ -53,7 +66,7 @@ Layout layout_for(const Geo &g)
     L.acc64 = off;  off = align256(off + N * sizeof(double));
     L.ext64 = off;  off = align256(off + N * sizeof(double));
     L.root8 = off;  off = align256(off + (size_t)g.rows * (size_t)g.cols);  // adjoint root labels
-    L.total = off;
+    L.total = std::max(off, csr_place(L.root8, N, L.off, L.kids, L.bsum));
     return L;
 }
 
@@ -233,6 +246,32 @@ int allow_lds(K kernel, size_t bytes)
     return D8_OK;
 }
 
+// The float resolve in a fixed order (kernels.h): children lists, walkers
+// from the leaves, the cycle check.  V ends in vn (one double per node);
+// ext is gathered afterwards by the caller (it needs the rasters' geometry).
+// The timing labels are literals: the batch's carry their own.
+template <bool ABS>
+void resolve_float(hipStream_t st, bool batch, int64_t N, const uint16_t *link, const float *aloc,
+                   const uint32_t *succ, const uint32_t *indeg, uint32_t *cnt, uint32_t *off, uint32_t *kids,
+                   uint32_t *bsum, uint32_t *total, double *vn, uint32_t *status,
+                   const uint32_t *entry = nullptr, const float *anode = nullptr, const float *pathp = nullptr)
+{
+    const unsigned nb = blocks_for(N, kNodeBlock);
+    const int64_t ncb = (N + kCompactNodes - 1) / kCompactNodes;
+    unsigned long long *vw = reinterpret_cast<unsigned long long *>(vn);
+    const char *lists = batch ? "batch_resolve_lists" : "resolve_lists";
+    D8_LAUNCH(lists, st, (csr_count<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, indeg, bsum)));
+    D8_LAUNCH(lists, st, (adj_compact_scan<<<1, 1024, 0, st>>>(ncb, bsum, total)));
+    D8_LAUNCH(lists, st, (csr_offsets<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, indeg, bsum, off, cnt)));
+    D8_LAUNCH(lists, st, (csr_fill<<<nb, kNodeBlock, 0, st>>>(N, link, succ, off, cnt, kids)));
+    D8_LAUNCH(lists, st, (csr_sort<<<nb, kNodeBlock, 0, st>>>(N, indeg, off, kids)));
+    D8_LAUNCH(batch ? "batch_resolve_fwd" : "resolve_fwd", st,
+              (resolve_fwd_det<float, ABS><<<nb, kNodeBlock, 0, st>>>(N, link, aloc, succ, indeg, off, kids, cnt,
+                                                                      vw, entry, anode, pathp)));
+    D8_LAUNCH(batch ? "batch_resolve_check" : "resolve_check", st,
+              (resolve_det_check<<<nb, kNodeBlock, 0, st>>>(N, link, cnt, status)));
+}
+
 // Unit counts (T = uint32_t): packed 64-bit resolve state, uint32 inflows.
 // Float weights (T = float): double resolve sums with separate counts.
 template <typename T>
@@ -271,15 +310,17 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
         D8_LAUNCH("resolve_fwd", st,
                   (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg, acc,
                                                               ext)));
+        D8_LAUNCH("resolve_check", st,
+                  (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, acc, cnt, status)));
     } else {
-        D8_LAUNCH("resolve_fwd", st,
-                  (resolve_fwd_f64<T><<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg,
-                                                                 cnt, acc, ext)));
+        uint32_t *off = reinterpret_cast<uint32_t *>(ws + L.off);
+        uint32_t *kids = reinterpret_cast<uint32_t *>(ws + L.kids);
+        uint32_t *bsum = reinterpret_cast<uint32_t *>(ws + L.bsum);
+        resolve_float<false>(st, false, g.nnodes, link, aloc, succ, indeg, cnt, off, kids, bsum, jstate + 8, acc,
+                             status);
+        D8_LAUNCH("resolve_ext", st,
+                  (resolve_ext<false><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext)));
     }
-    unsigned long long *packed = nullptr;
-    if constexpr (kCounts) packed = acc;
-    D8_LAUNCH("resolve_check", st,
-              (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, packed, cnt, status)));
     D8_LAUNCH("fwd_pass2", st,
               (fwd_walk<2, T, V, E><<<ntiles, thr, lds2, st>>>(dirs, w, g, link, aloc, indeg, cnt,
                                                                acc, ext, out, status, 0)));
@@ -339,11 +380,11 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
                                                                       pathp)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, 0, g.nnodes)));
-    D8_LAUNCH("absorb_resolve", st,
-              (resolve_fwd_f64<float, true><<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg,
-                                                                      cnt, acc, ext, anode, pathp)));
-    D8_LAUNCH("resolve_check", st,
-              (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, nullptr, cnt, status)));
+    resolve_float<true>(st, false, g.nnodes, link, aloc, succ, indeg, cnt,
+                        reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.kids),
+                        reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8, acc, status, entry, anode, pathp);
+    D8_LAUNCH("resolve_ext", st,
+              (resolve_ext<true><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, anode)));
     D8_LAUNCH("absorb_pass2", st,
               (fwd_walk_absorb<2><<<ntiles, kTileThreads, lds2, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt,
                                                                       acc, ext, out, status, anode, pathp)));
@@ -358,6 +399,7 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
 struct BatchLayout {
     size_t status, jstate, desc, tile_dem, chunk_dem;
     size_t link, entry, succ, indeg, cnt, val32, acc64, ext64, root8, total;
+    size_t off, kids, bsum;  // the forward's children lists, over the root labels
 };
 
 // Rasters of one tile shape: a contiguous range of the batch's tiles, run by
@@ -460,7 +502,7 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
     L.acc64 = off; off = align256(off + N * sizeof(double));
     L.ext64 = off; off = align256(off + N * sizeof(double));
     L.root8 = off; off = align256(off + (size_t)P.ncells);
-    L.total = off;
+    L.total = std::max(off, csr_place(L.root8, N, L.off, L.kids, L.bsum));
     return D8_OK;
 }
 
@@ -544,11 +586,11 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
         D8_LAUNCH("batch_graph_build", st,
                   (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
                                                                 succ, indeg)));
-        D8_LAUNCH("batch_resolve_fwd", st,
-                  (resolve_fwd_f64<float><<<nb, kNodeBlock, 0, st>>>(N, link, val32, entry, succ, indeg,
-                                                                     cnt, acc, ext)));
-        D8_LAUNCH("batch_resolve_check", st,
-                  (resolve_check<<<nb, kNodeBlock, 0, st>>>(N, link, indeg, nullptr, cnt, status)));
+        resolve_float<false>(st, true, N, link, val32, succ, indeg, cnt,
+                             reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.kids),
+                             reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8, acc, status);
+        D8_LAUNCH("batch_resolve_ext", st,
+                  (resolve_ext_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, acc, ext)));
         if (tiles(1, fwd_walk_batch<2>, "batch_fwd_pass2", link, val32, indeg, cnt, acc, ext, status))
             return D8_EHIP;
     }

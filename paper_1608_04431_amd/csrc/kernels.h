@@ -340,45 +340,6 @@ __global__ void resolve_fwd_u32(int64_t nnodes, const uint16_t *__restrict__ lin
     }
 }
 
-// Float weights: inflow sums in double, arrivals counted separately.  Every
-// access to acc and cnt is an atomic (performed where all XCDs see it), and
-// a child counts its arrival only after its add has returned, so the last
-// child's atomic read of acc sees every child's sum -- no cache-wide fences.
-// ABS (absorption): exit u sends alpha(u) A(u) into its entry n, and that
-// reaches n's exit s multiplied by the path product of n (anode, pathp).
-template <typename T, bool ABS = false>
-__global__ void resolve_fwd_f64(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
-                                const uint32_t *__restrict__ entry, const uint32_t *__restrict__ succ,
-                                const uint32_t *__restrict__ indeg, uint32_t *cnt, double *acc,
-                                double *ext, const float *__restrict__ anode = nullptr,
-                                const float *__restrict__ pathp = nullptr)
-{
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nnodes) return;
-    if (link[id] != kLinkExt || indeg[id] != 0) return;
-    double v = (double)aloc[id];
-    uint32_t n = entry[id], s = succ[id];
-    float au = ABS ? anode[id] : 1.0f;
-    for (;;) {
-        if (n == kNone) break;
-        const double o = ABS ? (double)au * v : v;
-        atomicAdd(&ext[n], o);
-        if (s == kNone) break;
-        const double as = (double)aloc[s];
-        const uint32_t is = indeg[s], ns = entry[s], ss = succ[s];
-        const double c = ABS ? o * (double)pathp[n] : o;
-        if constexpr (ABS) au = anode[s];
-        const double before = atomicAdd(&acc[s], c);
-        uint32_t one = 1u;
-        asm volatile("" : "+v"(one) : "v"(before));  // the count waits for the add
-        const uint32_t old = atomicAdd(&cnt[s], one);
-        if (old + 1u != is) break;
-        v = as + atomicAdd(&acc[s], 0.0);
-        n = ns;
-        s = ss;
-    }
-}
-
 // After the resolve: an exit whose children did not all arrive lies on, or
 // below, a cycle of exits.  Arrivals are the low word of `packed` (unit
 // counts) or `cnt` (float weights).
@@ -738,6 +699,192 @@ __global__ void adj_jump_finish(uint32_t *state, int rounds, uint32_t *status)
         if (state[1 + (rounds + 2) % 3] != 0) set_status(status, kStatusCycle);
         state[0] = (uint32_t)(rounds & 1);
     }
+}
+
+// ------------------------------------------- float resolve, fixed order ----
+// The modified Algorithm 1 on the exit forest for float weights, with every
+// sum taken in an order fixed by the input, so the result repeats bit for
+// bit run to run and equals between a batch and single-raster calls:
+//   V(e) = A_loc(e) + the sum of V(u) over e's children u (exits whose flow
+//          reaches e) in increasing node id, in double;
+//   ext(n) = the sum of V(u) over the exits u flowing into perimeter cell n,
+//          in direction order (a gather, after the resolve).
+// Children lists (CSR): offsets = exclusive scan of the child counts, each
+// list filled by atomics and then sorted.  Walkers start at leaves; a node
+// is summed by the child that arrives last (arrival counter counted down
+// from the child count), reading its children's V with atomics (they may
+// have been written on another XCD).  Absorption (ABS): a child u contributes
+// alpha(u) V(u) times the path product of the cell it enters, and ext(n)
+// sums alpha(u) V(u).
+
+// Child counts per block of 4096 nodes.
+__global__ void __launch_bounds__(kCompactBlock)
+csr_count(int64_t nnodes, const uint32_t *__restrict__ indeg, uint32_t *__restrict__ bsum)
+{
+    const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
+    uint32_t c = 0;
+    for (int j = 0; j < kCompactPer; ++j)
+        if (n0 + j < nnodes) c += indeg[n0 + j];
+    uint32_t total;
+    block_excl_scan(c, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// off[n] = first slot of n's children; cnt[n] = 0 (fill position).
+__global__ void __launch_bounds__(kCompactBlock)
+csr_offsets(int64_t nnodes, const uint32_t *__restrict__ indeg, const uint32_t *__restrict__ bsum,
+            uint32_t *__restrict__ off, uint32_t *__restrict__ cnt)
+{
+    const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
+    uint32_t v[kCompactPer], c = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+        v[j] = n0 + j < nnodes ? indeg[n0 + j] : 0u;
+        c += v[j];
+    }
+    uint32_t total;
+    uint32_t run = bsum[blockIdx.x] + block_excl_scan(c, &total);
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+        if (n0 + j < nnodes) {
+            off[n0 + j] = run;
+            cnt[n0 + j] = 0;
+        }
+        run += v[j];
+    }
+}
+
+__global__ void csr_fill(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_t *__restrict__ succ,
+                         const uint32_t *__restrict__ off, uint32_t *cnt, uint32_t *__restrict__ kids)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nnodes || link[id] != kLinkExt) return;
+    const uint32_t s = succ[id];
+    if (s == kNone) return;
+    kids[off[s] + atomicAdd(&cnt[s], 1u)] = (uint32_t)id;
+}
+
+// Each list in increasing id (insertion sort; lists are short).
+__global__ void csr_sort(int64_t nnodes, const uint32_t *__restrict__ indeg, const uint32_t *__restrict__ off,
+                         uint32_t *__restrict__ kids)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nnodes) return;
+    const uint32_t k = indeg[id];
+    if (k < 2) return;
+    uint32_t *a = kids + off[id];
+    for (uint32_t i = 1; i < k; ++i) {
+        const uint32_t x = a[i];
+        uint32_t j = i;
+        while (j > 0 && a[j - 1] > x) {
+            a[j] = a[j - 1];
+            --j;
+        }
+        a[j] = x;
+    }
+}
+
+__device__ inline double v_read(unsigned long long *vn, uint32_t u)
+{
+    return __longlong_as_double((long long)atomicOr(&vn[u], 0ull));
+}
+
+// Walkers from the leaves of the exit forest.  cnt holds each node's child
+// count (left by csr_fill) and is counted down by arrivals.
+template <typename T, bool ABS>
+__global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
+                                const uint32_t *__restrict__ succ, const uint32_t *__restrict__ indeg,
+                                const uint32_t *__restrict__ off, const uint32_t *__restrict__ kids,
+                                uint32_t *cnt, unsigned long long *vn,
+                                const uint32_t *__restrict__ entry = nullptr,
+                                const float *__restrict__ anode = nullptr,
+                                const float *__restrict__ pathp = nullptr)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nnodes) return;
+    if (link[id] != kLinkExt || indeg[id] != 0) return;
+    uint32_t u = (uint32_t)id;
+    double v = (double)aloc[u];
+    for (;;) {
+        const unsigned long long prev = atomicExch(&vn[u], (unsigned long long)__double_as_longlong(v));
+        const uint32_t s = succ[u];
+        if (s == kNone) break;
+        uint32_t one = 1u;
+        asm volatile("" : "+v"(one) : "v"(prev));  // the count waits for the store
+        if (atomicSub(&cnt[s], one) != 1u) break;
+        // last child to arrive: s's sum in the order of its sorted list
+        const uint32_t k = indeg[s], o = off[s];
+        double sum = (double)aloc[s];
+        for (uint32_t i = 0; i < k; ++i) {
+            const uint32_t c = kids[o + i];
+            double vc = v_read(vn, c);
+            if constexpr (ABS) vc = ((double)anode[c] * vc) * (double)pathp[entry[c]];
+            sum += vc;
+        }
+        u = s;
+        v = sum;
+    }
+}
+
+// Exits whose children did not all arrive lie on or below a cycle.
+__global__ void resolve_det_check(int64_t nnodes, const uint16_t *__restrict__ link,
+                                  const uint32_t *__restrict__ cnt, uint32_t *status)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = id < nnodes && link[id] == kLinkExt && cnt[id] != 0;
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) set_status(status, kStatusCycle);
+}
+
+// ext(n) of one perimeter node (id within a raster whose nodes start at
+// node0): the V of each neighbour in another tile that flows into n, in
+// direction order.
+template <bool ABS>
+__device__ inline double ext_gather(const uint8_t *__restrict__ dirs, const Geo &g, int64_t node0, int64_t id,
+                                    const uint16_t *__restrict__ link, const double *__restrict__ vn,
+                                    const float *__restrict__ anode)
+{
+    if (link[node0 + id] == kLinkNoData) return 0.0;
+    int ty, tx, p, r, c;
+    node_tile(g, id, ty, tx, p);
+    const int h = tile_h(g, ty), w = tile_w(g, tx);
+    ring_cell(p, h, w, r, c);
+    const int64_t gr = (int64_t)ty * g.th + r, gc = (int64_t)tx * g.tw + c;
+    double e = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const int lr = r + dir_dr(k), lc = c + dir_dc(k);
+        if (lr >= 0 && lr < h && lc >= 0 && lc < w) continue;  // same tile
+        const int64_t nr = gr + dir_dr(k), nc = gc + dir_dc(k);
+        if (nr < 0 || nr >= g.rows || nc < 0 || nc >= g.cols) continue;
+        if (dirs[nr * g.cols + nc] != (uint8_t)(7 - k)) continue;
+        const int uty = (int)(nr / g.th), utx = (int)(nc / g.tw);
+        const int ur = (int)(nr - (int64_t)uty * g.th), uc = (int)(nc - (int64_t)utx * g.tw);
+        const int64_t u = node0 + node_base(g, uty, utx) +
+                          ring_index(ur, uc, tile_h(g, uty), tile_w(g, utx));
+        double vu = vn[u];  // final: written by the resolve, an earlier kernel
+        if constexpr (ABS) vu = (double)anode[u] * vu;
+        e += vu;
+    }
+    return e;
+}
+
+template <bool ABS>
+__global__ void resolve_ext(const uint8_t *__restrict__ dirs, Geo g, const uint16_t *__restrict__ link,
+                            const double *__restrict__ vn, double *__restrict__ ext,
+                            const float *__restrict__ anode = nullptr)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    ext[id] = ext_gather<ABS>(dirs, g, 0, id, link, vn, anode);
+}
+
+__global__ void resolve_ext_batch(const DemDesc *__restrict__ dems, int ndem, const uint32_t *__restrict__ chunk_dem,
+                                  int64_t nnodes, const uint16_t *__restrict__ link,
+                                  const double *__restrict__ vn, double *__restrict__ ext)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nnodes) return;
+    const DemDesc &D = dems[dem_of(dems, ndem, chunk_dem, id)];
+    ext[id] = ext_gather<false>(D.dirs, D.g, D.node0, id - D.node0, link, vn, nullptr);
 }
 
 }  // namespace d8

@@ -74,3 +74,15 @@ def test_c2_weighted_f32_per_cell(d8m, c2, tile):
     got1 = d8m.flow_accum(d, None, acc_type="f32", tile=tile).cpu().numpy().astype(np.float64)
     small = valid & (c2["A_u"] < 2 ** 24)
     np.testing.assert_array_equal(got1[small], c2["A_u"][small].astype(np.float64))
+
+
+def test_c2_weighted_f32_repeats_bit_for_bit(d8m, c2):
+    """Float32 sums are taken in an order fixed by the input (within tiles by
+    the one wavefront's LDS order, across tiles by node id and direction), so
+    repeated calls agree bit for bit, on two tile shapes."""
+    d = torch.from_numpy(c2["d"]).cuda()
+    w = torch.from_numpy(c2["w"]).cuda()
+    for tile in ((0, 0), (16, 16)):
+        a = d8m.flow_accum(d, w, acc_type="f32", tile=tile)
+        for _ in range(3):
+            assert torch.equal(a, d8m.flow_accum(d, w, acc_type="f32", tile=tile)), tile
