@@ -131,6 +131,28 @@ def cpu_baseline(z: np.ndarray, seed_g: int, rows: int) -> dict:
                       f"adjoint in float64 ({t2 - t1:.2f}s), serial C"}
 
 
+def cpu_oracle_configs() -> dict:
+    """The CPU oracle (serial C, one thread) on the two smaller workloads,
+    whole rasters: dem512 (unit counts) and dem8192_ocean (unit counts, then
+    float64 sums of the float32 weights of seed 21).  D8 is not timed."""
+    import oracle
+    out = {}
+    for name in ("dem512", "dem8192_ocean"):
+        wl = synth.WORKLOADS[name]
+        d = oracle.d8(synth.workload_dem(name))
+        t0 = time.perf_counter()
+        oracle.accum_u64(d)
+        t1 = time.perf_counter()
+        rec = {"cells": int(d.size), "u32_cells_per_s": d.size / (t1 - t0), "cores": 1, "kind": "oracle"}
+        if "seed_w" in wl:
+            w = synth.uniform(d.shape, wl["seed_w"])
+            t2 = time.perf_counter()
+            oracle.accum_f64(d, w)
+            rec["f32_weighted_cells_per_s"] = d.size / (time.perf_counter() - t2)
+        out[name] = rec
+    return out
+
+
 # ------------------------------------------------------------ batched leg --
 # 2000 DEMs of uneven sizes (side log-uniform in [64, 4096], aspect uniform in
 # [0.5, 2]), float32 weights and cotangents: forward + adjoint for all of
@@ -666,6 +688,7 @@ def run(args, bd):
     if args.cpu_rows > 0:
         log("timing the CPU oracle sample")
         cpu = cpu_baseline(z, wl.get("seed_g", 31), min(args.cpu_rows, rows))
+        cpu["other_workloads"] = cpu_oracle_configs()
 
     out = {
         "metric": METRIC,

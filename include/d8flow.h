@@ -283,8 +283,10 @@ size_t d8_batch_workspace_bytes(const d8_batch_item *items, int n);
 
 /*
  * Runs a batch on `stream`.  The descriptor tables are copied into `ws`
- * first and the call waits for that copy (one synchronisation of `stream`);
- * the stages are then enqueued without further waits.  Returns D8_OK,
+ * first, from a pinned host buffer of the library's own (a ring of four,
+ * allocated on first use and grown when a batch needs more; the host waits
+ * for a buffer only if its copy from four calls back has not run yet), then
+ * the stages are enqueued; the call does not synchronise `stream`.  Returns D8_OK,
  * D8_EINVAL (bad item, mode, or a missing pointer the mode needs),
  * D8_EWORKSPACE or D8_EHIP; data errors via d8_check_status(ws, stream).
  */
@@ -293,7 +295,8 @@ int flow_accum_batched(const d8_batch_item *items, int n, int mode, void *ws, si
 
 /*
  * The same batch recorded once as a HIP graph: d8_graph_create copies the
- * descriptor tables into `ws` (waiting on `stream`), records every stage on
+ * descriptor tables into `ws` on `stream` and waits for that copy (a setup
+ * call: the graph may then be launched on any stream), records every stage on
  * a private stream and returns an executable graph in *graph_exec.
  * d8_graph_launch replays it on `stream` -- one launch for the whole batch;
  * it reads and writes the items' arrays and `ws` as they are at replay time

@@ -98,10 +98,13 @@ def d8_directions_rho8(dem: torch.Tensor, rnd: torch.Tensor, nodata: float = -99
 
 def flow_accum(dirs: torch.Tensor, weights: torch.Tensor | None = None, acc_type: str = "auto",
                tile: tuple[int, int] = (0, 0), ws: Workspace | None = None,
-               out: torch.Tensor | None = None) -> torch.Tensor:
+               out: torch.Tensor | None = None, check: bool = False) -> torch.Tensor:
     """Flow accumulation A (Eq. (1)).  acc_type 'u32' (unit weights, returned
     as int32 storage holding uint32 bits) or 'f32'; 'auto' = u32 without
-    weights, f32 with."""
+    weights, f32 with.  Asynchronous: data errors (an invalid code, a cycle)
+    are recorded in the workspace and raised by check_status(ws), or here with
+    check=True (which synchronises the stream); without either, and with no
+    workspace passed, they go unreported."""
     _check_raster(dirs, torch.uint8, "dirs")
     if acc_type == "auto":
         acc_type = "u32" if weights is None else "f32"
@@ -121,6 +124,8 @@ def flow_accum(dirs: torch.Tensor, weights: torch.Tensor | None = None, acc_type
                                 D8_ACC_U32 if acc_type == "u32" else D8_ACC_F32, rows, cols,
                                 tile[0], tile[1], _ptr(ws.buf), ws.nbytes, _stream(dirs.device))
     _lib.check(rc, "flow_accum")
+    if check:
+        check_status(ws)
     return out
 
 
@@ -155,8 +160,10 @@ def flow_accum_noalloc(dirs: torch.Tensor, weights: torch.Tensor | None = None, 
 
 
 def flow_accum_adjoint(dirs: torch.Tensor, grad_acc: torch.Tensor, tile=(0, 0),
-                       ws: Workspace | None = None, out: torch.Tensor | None = None):
-    """lambda = (I-P)^-T g: the sum of grad_acc along each cell's downstream path."""
+                       ws: Workspace | None = None, out: torch.Tensor | None = None,
+                       check: bool = False):
+    """lambda = (I-P)^-T g: the sum of grad_acc along each cell's downstream
+    path.  Data errors as for flow_accum (check_status(ws) or check=True)."""
     _check_raster(dirs, torch.uint8, "dirs")
     _check_raster(grad_acc, torch.float32, "grad_acc")
     if grad_acc.shape != dirs.shape:
@@ -170,15 +177,18 @@ def flow_accum_adjoint(dirs: torch.Tensor, grad_acc: torch.Tensor, tile=(0, 0),
                                         tile[0], tile[1], _ptr(ws.buf), ws.nbytes,
                                         _stream(dirs.device))
     _lib.check(rc, "flow_accum_adjoint")
+    if check:
+        check_status(ws)
     return out
 
 
 def flow_accum_absorb(dirs: torch.Tensor, alpha: torch.Tensor, weights: torch.Tensor | None = None,
                       tile: tuple[int, int] = (0, 0), ws: torch.Tensor | None = None,
-                      out: torch.Tensor | None = None) -> torch.Tensor:
+                      out: torch.Tensor | None = None, check: bool = False) -> torch.Tensor:
     """A(p) = w(p) + sum over donors n of alpha(n) A(n), float32 (see
     flow_accum_absorb in d8flow.h).  ws: a device uint8 tensor of at least
-    d8_absorb_workspace_bytes, or None."""
+    d8_absorb_workspace_bytes, or None.  Asynchronous; check=True synchronises
+    and raises on a data error recorded in ws."""
     _check_raster(dirs, torch.uint8, "dirs")
     _check_raster(alpha, torch.float32, "alpha")
     if alpha.shape != dirs.shape:
@@ -199,15 +209,17 @@ def flow_accum_absorb(dirs: torch.Tensor, alpha: torch.Tensor, weights: torch.Te
     rc = _lib.load().flow_accum_absorb(_ptr(dirs), _ptr(weights), _ptr(alpha), _ptr(out), rows, cols,
                                        tile[0], tile[1], _ptr(ws), ws.numel(), _stream(dirs.device))
     _lib.check(rc, "flow_accum_absorb")
-    _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(dirs.device)), "status")
+    if check:
+        _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(dirs.device)), "status")
     return out
 
 
 def flow_accum_absorb_adjoint(dirs: torch.Tensor, alpha: torch.Tensor, grad: torch.Tensor,
                               tile: tuple[int, int] = (0, 0), ws: torch.Tensor | None = None,
-                              out: torch.Tensor | None = None) -> torch.Tensor:
+                              out: torch.Tensor | None = None, check: bool = False) -> torch.Tensor:
     """lambda(c) = g(c) + alpha(c) lambda(receiver(c)), float32 (see
-    flow_accum_absorb_adjoint in d8flow.h)."""
+    flow_accum_absorb_adjoint in d8flow.h).  Asynchronous; check=True as for
+    flow_accum_absorb."""
     _check_raster(dirs, torch.uint8, "dirs")
     for t, name in ((alpha, "alpha"), (grad, "grad")):
         _check_raster(t, torch.float32, name)
@@ -225,7 +237,8 @@ def flow_accum_absorb_adjoint(dirs: torch.Tensor, alpha: torch.Tensor, grad: tor
     rc = _lib.load().flow_accum_absorb_adjoint(_ptr(dirs), _ptr(alpha), _ptr(grad), _ptr(out), rows, cols,
                                                tile[0], tile[1], _ptr(ws), ws.numel(), _stream(dirs.device))
     _lib.check(rc, "flow_accum_absorb_adjoint")
-    _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(dirs.device)), "status")
+    if check:
+        _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(dirs.device)), "status")
     return out
 
 

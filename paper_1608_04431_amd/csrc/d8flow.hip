@@ -523,24 +523,55 @@ __global__ void reset_jump(uint32_t *jstate)
     jstate[3] = 1;
 }
 
-// Descriptor tables into the workspace; waits for the copies (the host
-// vectors are the plan's).
-int upload_plan(const BatchPlan &P, char *ws, hipStream_t st)
+// Descriptor tables into the workspace without waiting for the stream: the
+// tables are packed into a pinned host buffer of the library's own and copied
+// from there, stream-ordered before the kernels that read them.  A small ring
+// of such buffers is reused; before a buffer is refilled the host waits for
+// the event recorded after its last copy (only the copy, which ran at the
+// start of that earlier call's work).
+struct Staging {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+constexpr int kStagingRing = 4;
+std::mutex g_staging_mu;
+Staging g_staging[kStagingRing];
+int g_staging_next = 0;
+
+int upload_plan(const BatchPlan &P, char *ws, hipStream_t st, bool wait = false)
 {
     const BatchLayout &L = P.L;
+    if (P.dems.empty()) return D8_OK;
     std::vector<DemDesc> dems = P.dems;
     for (size_t i = 0; i < dems.size(); ++i)
         dems[i].root8 = reinterpret_cast<uint8_t *>(ws + L.root8) + P.cell0[i];
-    if (!dems.empty()) {
-        if (hipMemcpyAsync(ws + L.desc, dems.data(), dems.size() * sizeof(DemDesc),
-                           hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(ws + L.tile_dem, P.tile_dem.data(), P.tile_dem.size() * sizeof(uint32_t),
-                           hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(ws + L.chunk_dem, P.chunk_dem.data(),
-                           P.chunk_dem.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess)
-            return D8_EHIP;
+    const size_t b0 = dems.size() * sizeof(DemDesc);
+    const size_t b1 = P.tile_dem.size() * sizeof(uint32_t);
+    const size_t b2 = P.chunk_dem.size() * sizeof(uint32_t);
+    const size_t need = b0 + b1 + b2;
+    std::lock_guard<std::mutex> lk(g_staging_mu);
+    Staging &S = g_staging[g_staging_next];
+    g_staging_next = (g_staging_next + 1) % kStagingRing;
+    if (S.done && hipEventSynchronize(S.done) != hipSuccess) return D8_EHIP;
+    if (!S.done && hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess) return D8_EHIP;
+    if (S.cap < need) {
+        if (S.host) (void)hipHostFree(S.host);
+        S.host = nullptr;
+        S.cap = 0;
+        if (hipHostMalloc(&S.host, need, hipHostMallocDefault) != hipSuccess) return D8_EHIP;
+        S.cap = need;
     }
-    if (hipStreamSynchronize(st) != hipSuccess) return D8_EHIP;
+    char *h = reinterpret_cast<char *>(S.host);
+    std::memcpy(h, dems.data(), b0);
+    std::memcpy(h + b0, P.tile_dem.data(), b1);
+    std::memcpy(h + b0 + b1, P.chunk_dem.data(), b2);
+    if (hipMemcpyAsync(ws + L.desc, h, b0, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(ws + L.tile_dem, h + b0, b1, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(ws + L.chunk_dem, h + b0 + b1, b2, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(S.done, st) != hipSuccess)
+        return D8_EHIP;
+    if (wait && hipEventSynchronize(S.done) != hipSuccess) return D8_EHIP;
     return D8_OK;
 }
 
@@ -1179,7 +1210,9 @@ int d8_graph_create(const d8_batch_item *items, int n, int mode, void *ws, size_
     if (rc != D8_OK) return rc;
     begin_call();
     char *w8 = reinterpret_cast<char *>(ws);
-    rc = upload_plan(P, w8, as_stream(stream));
+    // a setup call: the tables are in the workspace when it returns, so the
+    // graph may be launched on any stream
+    rc = upload_plan(P, w8, as_stream(stream), true);
     if (rc != D8_OK) return rc;
     // record on a stream of our own (the caller's may be the legacy default
     // stream, which cannot be captured)
