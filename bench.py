@@ -477,39 +477,68 @@ def absorb_leg(d8, dirs, w, tile, seed, reps=3):
     return res
 
 
-def streamed_leg(d8, dirs, A, tile, band_rows, reps=3):
-    """The same forward (unit counts) with the raster in pinned host memory:
-    flow_accum_streamed, timed with events around the whole call (host
-    copies included), output compared with the in-memory result."""
+def streamed_leg(d8, dirs, A, g, lam, tile, tile_a, band_rows, reps=3):
+    """The raster in pinned host memory, streamed in bands: the unit-count
+    forward (flow_accum_streamed), the float32 forward with weights in host
+    memory (flow_accum_streamed_f32; the cotangent's U[0, 1) values serve as
+    weights) and the adjoint (flow_accum_adjoint_streamed, the same dense
+    cotangent), each timed with events around the whole call (host copies
+    included) and compared with the in-memory results."""
     import torch
     rows, cols = dirs.shape
-    dirs_h = dirs.cpu().pin_memory()
-    out_h = torch.empty((rows, cols), dtype=torch.int32, pin_memory=True)
-    nbytes = d8.stream_workspace_bytes(rows, cols, tile, band_rows)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dirs.device)
-    d8.flow_accum_streamed(dirs_h, tile=tile, band_rows=band_rows, ws=ws, out=out_h)
-    times = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        d8.flow_accum_streamed(dirs_h, tile=tile, band_rows=band_rows, ws=ws, out=out_h, sync=False)
-        e1.record()
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
-    d8._lib.check(d8._lib.load().d8_check_status(ws.data_ptr(), torch.cuda.current_stream().cuda_stream),
-                  "status")
-    ms = sorted(times)[len(times) // 2]
-    same = bool(torch.equal(out_h, A.cpu()))
     cells = rows * cols
+    dirs_h = dirs.cpu().pin_memory()
+    g_h = g.cpu().pin_memory()
+    nbytes = max(d8.stream_workspace_bytes(rows, cols, t, band_rows) for t in (tile, tile_a))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dirs.device)
+
+    def timed(call, out):
+        call(out, True)
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            call(out, False)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        d8._lib.check(d8._lib.load().d8_check_status(ws.data_ptr(), torch.cuda.current_stream().cuda_stream),
+                      "status")
+        return sorted(times)[len(times) // 2]
+
+    out_u = torch.empty((rows, cols), dtype=torch.int32, pin_memory=True)
+    ms_u = timed(lambda o, sync: d8.flow_accum_streamed(dirs_h, tile=tile, band_rows=band_rows, ws=ws, out=o,
+                                                         sync=sync), out_u)
+    same_u = bool(torch.equal(out_u, A.cpu()))
+    del out_u
+    out_f = torch.empty((rows, cols), dtype=torch.float32, pin_memory=True)
+    ms_f = timed(lambda o, sync: d8.flow_accum_streamed_f32(dirs_h, g_h, tile=tile, band_rows=band_rows, ws=ws,
+                                                             out=o, sync=sync), out_f)
+    ref_f = d8.flow_accum(dirs, g, acc_type="f32", tile=tile).cpu()
+    same_f = bool(torch.equal(out_f, ref_f))
+    del out_f, ref_f
+    out_a = torch.empty((rows, cols), dtype=torch.float32, pin_memory=True)
+    ms_a = timed(lambda o, sync: d8.flow_accum_adjoint_streamed(dirs_h, g_h, tile=tile_a, band_rows=band_rows,
+                                                                 ws=ws, out=o, sync=sync), out_a)
+    lam_h = lam.cpu()
+    rel_a = float(((out_a.double() - lam_h.double()).abs() / lam_h.double().abs().clamp_min(1e-30)).max())
+    del out_a, lam_h
     th = min(tile[0], rows)
     band = band_rows or 16 * th
-    log(f"streamed forward (host-resident raster): {ms:.2f} ms, identical to in-memory: {same}")
-    return {"ms": round(ms, 3), "cells_per_s": cells / (ms * 1e-3), "band_rows": band,
-            "host_bytes_per_cell": 6, "host_link_GBps": 6 * cells / (ms * 1e-3) / 1e9,
-            "workspace_GiB": round(nbytes / 2**30, 3), "outputs_identical": same,
-            "what": "flow_accum_streamed: u32 forward of the same raster from pinned host memory "
-                    "(codes copied twice, counts once), median of 3, copies included"}
+    log(f"streamed (host-resident raster): u32 fwd {ms_u:.2f} ms (identical: {same_u}), f32 fwd {ms_f:.2f} ms "
+        f"(identical: {same_f}), adjoint {ms_a:.2f} ms (max rel diff to in-memory {rel_a:.2e})")
+
+    def rec(ms, hb):
+        return {"ms": round(ms, 3), "cells_per_s": cells / (ms * 1e-3), "host_bytes_per_cell": hb,
+                "host_link_GBps": hb * cells / (ms * 1e-3) / 1e9}
+    return {"band_rows": band, "workspace_GiB": round(nbytes / 2**30, 3),
+            "u32_forward": dict(rec(ms_u, 6), outputs_identical=same_u),
+            "f32_forward": dict(rec(ms_f, 14), outputs_identical=same_f),
+            "adjoint": dict(rec(ms_a, 14), max_rel_diff_in_memory=rel_a),
+            "what": "the forward (u32 counts; f32 with host weights) and the adjoint of the same raster from "
+                    "pinned host memory: codes copied twice, a float input twice (f32, adjoint) and the "
+                    "result once; median of 3, copies included"}
 
 
 def run(args, bd):
@@ -682,7 +711,7 @@ def run(args, bd):
 
     streamed = None
     if not args.no_stream:
-        streamed = streamed_leg(d8, dirs, A, tile, args.stream_band)
+        streamed = streamed_leg(d8, dirs, A, g, lam, tile_f, tile_a, args.stream_band)
 
     cpu = None
     if args.cpu_rows > 0:

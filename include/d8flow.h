@@ -230,7 +230,8 @@ int flow_accum_absorb_alpha_grad(const uint8_t *dirs, const float *acc, const fl
  *            cut to the raster (0 = 16 tile rows); cut to the raster.
  * ws, ws_bytes: device workspace (256-byte aligned) of at least
  *            d8_stream_workspace_bytes(...) bytes: the perimeter graph of the
- *            whole raster, three code slots and two count slots of a band.
+ *            whole raster, three code slots, two result slots and two slots
+ *            for a float input of a band.
  * Other arguments and returns as for flow_accum (data errors via
  * d8_check_status(ws, stream)).  Calls that share a workspace, or run at the
  * same time on one device, must be ordered (the library's copy stream and
@@ -241,6 +242,41 @@ size_t d8_stream_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int 
 int flow_accum_streamed(const uint8_t *dirs_host, uint32_t *acc_host, int64_t rows, int64_t cols,
                         int tile_rows, int tile_cols, int64_t band_rows, void *ws, size_t ws_bytes,
                         void *stream);
+
+/*
+ * The same out-of-core scheme for float weights and for the adjoint, so the
+ * whole path runs on rasters larger than device memory (Introduction; EVICT,
+ * Section "Broadcasting & Finalizing").  Both stream one float per cell
+ * (the weights or the cotangent) from host memory in each of the two passes
+ * and copy one float per cell back: host traffic 14 B per cell (codes twice,
+ * the float input twice, the result once).
+ *
+ * flow_accum_streamed_f32: A of Eq. (1) with float32 weights (weights_host
+ * NULL = unit weights, then 6 B per cell), float32 result, NoData cells 0.
+ * The cross-tile sums are the fixed-order float resolve of flow_accum, so the
+ * result equals flow_accum(D8_ACC_F32)'s on the same tile shape bit for bit.
+ *
+ * flow_accum_adjoint_streamed: lambda = (I-P)^-T g (see flow_accum_adjoint),
+ * float32, NoData cells 0.  Pass 1 keeps only the perimeter records; the
+ * exits' edges are stored as the bands pass (the codes do not stay on the
+ * device); pass 2 recomputes each tile's upstream sums with every exit seeded
+ * by the resolved sum of the tile it flows into, so no per-cell state is kept
+ * between the passes.  Agrees with flow_accum_adjoint within float32
+ * rounding (the sums are grouped differently).
+ *
+ * dirs_host: uint8 codes; weights_host / grad_host: float32; acc_host /
+ * grad_weights_host: float32 results -- all [rows*cols] in host memory
+ * (pinned memory lets the copies overlap the kernels).  Other arguments,
+ * workspace (d8_stream_workspace_bytes, which covers all three streamed
+ * calls), ordering rules and returns as for flow_accum_streamed; NULL
+ * grad_host is D8_EINVAL.
+ */
+int flow_accum_streamed_f32(const uint8_t *dirs_host, const float *weights_host, float *acc_host, int64_t rows,
+                            int64_t cols, int tile_rows, int tile_cols, int64_t band_rows, void *ws,
+                            size_t ws_bytes, void *stream);
+int flow_accum_adjoint_streamed(const uint8_t *dirs_host, const float *grad_host, float *grad_weights_host,
+                                int64_t rows, int64_t cols, int tile_rows, int tile_cols, int64_t band_rows,
+                                void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Batches of rasters.  Many rasters of uneven sizes go through the same

@@ -19,7 +19,8 @@ NODATA = 9
 __all__ = ["d8_directions", "d8_directions_rho8", "flow_accum", "flow_accum_adjoint", "workspace_bytes", "Workspace",
            "check_status", "FlowAccum", "FlowAccumAbsorb", "D8Error", "Raster", "Batch", "BatchGraph",
            "stream_workspace_bytes", "flow_accum_streamed", "flow_accum_absorb",
-           "flow_accum_absorb_adjoint", "flow_accum_absorb_alpha_grad", "flow_accum_noalloc"]
+           "flow_accum_absorb_adjoint", "flow_accum_absorb_alpha_grad", "flow_accum_noalloc",
+           "flow_accum_streamed_f32", "flow_accum_adjoint_streamed"]
 
 
 def _stream(device: torch.device) -> int:
@@ -299,6 +300,56 @@ def flow_accum_streamed(dirs_host: torch.Tensor, tile: tuple[int, int] = (0, 0),
     if sync:
         _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(ws.device)), "status")
     return out
+
+
+def _streamed_float(fn: str, dirs_host: torch.Tensor, v_host: torch.Tensor | None, tile, band_rows, ws, out,
+                    device, sync):
+    if dirs_host.dtype != torch.uint8 or dirs_host.is_cuda or dirs_host.dim() != 2 \
+            or not dirs_host.is_contiguous():
+        raise ValueError("dirs_host must be a contiguous 2-D uint8 CPU tensor")
+    rows, cols = dirs_host.shape
+    if v_host is not None and (v_host.dtype != torch.float32 or v_host.is_cuda
+                               or tuple(v_host.shape) != (rows, cols) or not v_host.is_contiguous()):
+        raise ValueError("the float input must be a contiguous float32 CPU tensor of the raster's shape")
+    dev = torch.device(device or "cuda")
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float32, pin_memory=True)
+    if out.dtype != torch.float32 or out.is_cuda or tuple(out.shape) != (rows, cols) \
+            or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 CPU tensor of the raster's shape")
+    nbytes = stream_workspace_bytes(rows, cols, tile, band_rows)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if ws.dtype != torch.uint8 or not ws.is_cuda or ws.numel() < nbytes:
+        raise ValueError(f"ws must be a device uint8 tensor of at least {nbytes} bytes")
+    rc = getattr(_lib.load(), fn)(_ptr(dirs_host), _ptr(v_host), _ptr(out), rows, cols, tile[0], tile[1],
+                                  band_rows, _ptr(ws), ws.numel(), _stream(ws.device))
+    _lib.check(rc, fn)
+    if sync:
+        _lib.check(_lib.load().d8_check_status(_ptr(ws), _stream(ws.device)), "status")
+    return out
+
+
+def flow_accum_streamed_f32(dirs_host: torch.Tensor, weights_host: torch.Tensor | None = None,
+                            tile: tuple[int, int] = (0, 0), band_rows: int = 0, ws: torch.Tensor | None = None,
+                            out: torch.Tensor | None = None, device=None, sync: bool = True) -> torch.Tensor:
+    """Float32 accumulation of a raster and its weights held in host memory
+    (flow_accum_streamed_f32 in d8flow.h); returns a float32 CPU tensor
+    (pinned when allocated here).  sync as for flow_accum_streamed."""
+    return _streamed_float("flow_accum_streamed_f32", dirs_host, weights_host, tile, band_rows, ws, out, device,
+                           sync)
+
+
+def flow_accum_adjoint_streamed(dirs_host: torch.Tensor, grad_host: torch.Tensor, tile: tuple[int, int] = (0, 0),
+                                band_rows: int = 0, ws: torch.Tensor | None = None,
+                                out: torch.Tensor | None = None, device=None, sync: bool = True) -> torch.Tensor:
+    """The adjoint of a raster held in host memory, cotangent grad_host in host
+    memory (flow_accum_adjoint_streamed in d8flow.h); returns a float32 CPU
+    tensor.  sync as for flow_accum_streamed."""
+    if grad_host is None:
+        raise ValueError("grad_host is required")
+    return _streamed_float("flow_accum_adjoint_streamed", dirs_host, grad_host, tile, band_rows, ws, out, device,
+                           sync)
 
 
 def check_status(ws: Workspace) -> None:

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libd8flow.so")
 EXPORTS = ("d8_directions", "d8_directions_rho8", "d8_workspace_bytes", "flow_accum", "flow_accum_adjoint",
            "d8_absorb_workspace_bytes", "flow_accum_absorb", "flow_accum_absorb_adjoint",
            "flow_accum_absorb_alpha_grad",
-           "d8_stream_workspace_bytes", "flow_accum_streamed", "flow_accum_noalloc",
+           "d8_stream_workspace_bytes", "flow_accum_streamed", "flow_accum_streamed_f32",
+           "flow_accum_adjoint_streamed", "flow_accum_noalloc",
            "d8_batch_workspace_bytes", "flow_accum_batched", "d8_graph_create",
            "d8_graph_launch", "d8_graph_destroy",
            "d8_check_status", "d8_strerror", "d8_version", "d8_timing_enable",
@@ -83,6 +84,9 @@ def load() -> ctypes.CDLL:
     lib.d8_stream_workspace_bytes.restype = sz
     lib.flow_accum_streamed.argtypes = [vp, vp, i64, i64, i32, i32, i64, vp, sz, vp]
     lib.flow_accum_streamed.restype = i32
+    for name in ("flow_accum_streamed_f32", "flow_accum_adjoint_streamed"):
+        getattr(lib, name).argtypes = [vp, vp, vp, i64, i64, i32, i32, i64, vp, sz, vp]
+        getattr(lib, name).restype = i32
     items = ctypes.POINTER(BatchItem)
     lib.d8_batch_workspace_bytes.argtypes = [items, i32]
     lib.d8_batch_workspace_bytes.restype = sz

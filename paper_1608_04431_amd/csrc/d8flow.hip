@@ -319,7 +319,7 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
         resolve_float<false>(st, false, g.nnodes, link, aloc, succ, indeg, cnt, off, kids, bsum, jstate + 8, acc,
                              status);
         D8_LAUNCH("resolve_ext", st,
-                  (resolve_ext<false><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext)));
+                  (resolve_ext<false><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, nullptr, 0, g.nnodes)));
     }
     D8_LAUNCH("fwd_pass2", st,
               (fwd_walk<2, T, V, E><<<ntiles, thr, lds2, st>>>(dirs, w, g, link, aloc, indeg, cnt,
@@ -384,7 +384,7 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
                         reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.kids),
                         reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8, acc, status, entry, anode, pathp);
     D8_LAUNCH("resolve_ext", st,
-              (resolve_ext<true><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, anode)));
+              (resolve_ext<true><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, anode, 0, g.nnodes)));
     D8_LAUNCH("absorb_pass2", st,
               (fwd_walk_absorb<2><<<ntiles, kTileThreads, lds2, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt,
                                                                       acc, ext, out, status, anode, pathp)));
@@ -668,7 +668,8 @@ struct GraphHandle {
 struct StreamLayout {
     Layout L;           // perimeter-graph arrays (root8 unused)
     size_t cslot[3];    // codes: (band_rows + 2) x cols bytes each
-    size_t oslot[2];    // counts: band_rows x cols uint32 each
+    size_t oslot[2];    // results: band_rows x cols 4-byte values each
+    size_t vslot[2];    // float inputs (weights or cotangents): band_rows x cols each
     size_t total;
     int64_t band_rows;  // a multiple of the tile height
 };
@@ -694,6 +695,10 @@ int stream_layout(int64_t rows, int64_t cols, int &th, int &tw, int64_t band_row
         S.oslot[i] = off;
         off = align256(off + (size_t)band_rows * (size_t)cols * sizeof(uint32_t));
     }
+    for (int i = 0; i < 2; ++i) {
+        S.vslot[i] = off;
+        off = align256(off + (size_t)band_rows * (size_t)cols * sizeof(float));
+    }
     S.total = off;
     return D8_OK;
 }
@@ -701,10 +706,10 @@ int stream_layout(int64_t rows, int64_t cols, int &th, int &tw, int64_t band_row
 // Per device: the copy streams (in, out) and the events of the pipeline.
 struct StreamRes {
     hipStream_t cs = nullptr, cs2 = nullptr;
-    hipEvent_t ev[16] = {};
+    hipEvent_t ev[20] = {};
 };
 enum { kEvFree = 0, kEvReady = 3, kEvP1 = 6, kEvCFree = 7, kEvCReady = 9, kEvOFree = 11,
-       kEvODone = 13, kEvEnd = 15 };
+       kEvODone = 13, kEvEnd = 15, kEvVFree = 16, kEvVReady = 18 };
 
 int stream_res(StreamRes *&R)
 {
@@ -726,11 +731,14 @@ int stream_res(StreamRes *&R)
     return D8_OK;
 }
 
-int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const StreamLayout &S, char *ws,
-                 hipStream_t st)
+// What a streamed call computes: unit counts, float weighted sums, or the
+// adjoint.  The bands go through the same two-pass pipeline; the float kinds
+// also stream one float input per cell (weights or cotangents) in both passes.
+enum StreamKind { kStreamU32 = 0, kStreamF32 = 1, kStreamAdj = 2 };
+
+int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h, const Geo &g,
+                 const StreamLayout &S, char *ws, hipStream_t st)
 {
-    using V = unsigned long long;
-    using E = uint32_t;
     StreamRes *R = nullptr;
     if (stream_res(R) != D8_OK) return D8_EHIP;
     hipStream_t cs = R->cs, cs2 = R->cs2;
@@ -742,15 +750,19 @@ int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const Str
     uint32_t *entry = reinterpret_cast<uint32_t *>(ws + L.entry);
     uint32_t *succ = reinterpret_cast<uint32_t *>(ws + L.succ);
     uint32_t *indeg = reinterpret_cast<uint32_t *>(ws + L.indeg);
-    uint32_t *aloc = reinterpret_cast<uint32_t *>(ws + L.val32);
-    V *acc = reinterpret_cast<V *>(ws + L.acc64);
-    E *ext = reinterpret_cast<E *>(ws + L.ext64);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + L.ptr2);
     const int64_t cols = g.cols, rows = g.rows;
     const int tb = (int)(S.band_rows / g.th);  // tile rows per band
     const int nband = (g.nty + tb - 1) / tb;
-    const size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1, (int)sizeof(FwdLds<1, uint32_t>));
-    const size_t lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2, (int)sizeof(FwdLds<2, uint32_t>));
-    if (allow_lds(fwd_walk<1, uint32_t, V, E>, lds1) || allow_lds(fwd_walk<2, uint32_t, V, E>, lds2))
+    // float inputs are streamed when given (unit weights need none)
+    const bool f32 = kind == kStreamF32, adj = kind == kStreamAdj, vals = v_h != nullptr;
+    using VU = unsigned long long;
+    const size_t lds1 = adj ? walk_lds_bytes(g.th, g.tw, kWalkAdj1)
+                            : walk_lds_bytes(g.th, g.tw, kWalkFwd1, f32 ? 4 : (int)sizeof(FwdLds<1, uint32_t>));
+    const size_t lds2 = adj ? lds1 : walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4);
+    if (allow_lds(fwd_walk<1, uint32_t, VU, uint32_t>, lds1) || allow_lds(fwd_walk<2, uint32_t, VU, uint32_t>, lds2) ||
+        allow_lds(fwd_walk<1, float, double, double>, lds1) || allow_lds(fwd_walk<2, float, double, double>, lds2) ||
+        allow_lds(adj_walk_band, lds1))
         return D8_EHIP;
     auto band = [&](int b, int &ty0, int &ty1, int64_t &r0, int64_t &r1) {
         ty0 = b * tb;
@@ -762,6 +774,8 @@ int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const Str
     auto codes_ptr = [&](size_t slot, int64_t r0) {
         return reinterpret_cast<const uint8_t *>(ws + slot) - (r0 - 1) * cols;
     };
+    // a band's values or results in slot i: slot row 0 is raster row r0
+    auto band_ptr = [&](size_t slot, int64_t r0) { return reinterpret_cast<float *>(ws + slot) - r0 * cols; };
     auto nodes_of = [&](int ty0, int ty1, int64_t &n0, int64_t &n1) {
         n0 = (int64_t)ty0 * g.row_nodes;
         n1 = ty1 >= g.nty ? g.nnodes : (int64_t)ty1 * g.row_nodes;
@@ -773,8 +787,24 @@ int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const Str
         nodes_of(ty0, ty1, n0, n1);
         D8_LAUNCH("stream_graph_build", st,
                   (graph_build<<<blocks_for(n1 - n0, kNodeBlock), kNodeBlock, 0, st>>>(
-                      codes_ptr(S.cslot[b % 3], r0), g, link, entry, succ, indeg, n0, n1)));
+                      codes_ptr(S.cslot[b % 3], r0), g, link, entry, succ, adj ? nullptr : indeg, n0, n1)));
         (void)hipEventRecord(ev[kEvFree + b % 3], st);
+    };
+    // a band's codes (with its halo rows) into code slot `slot` on cs
+    auto codes_in = [&](int slot, int64_t r0, int64_t r1) {
+        const int64_t h0 = std::max<int64_t>(0, r0 - 1), h1 = std::min(rows, r1 + 1);
+        (void)hipMemcpyAsync(ws + S.cslot[slot] + (h0 - (r0 - 1)) * cols, dirs_h + h0 * cols,
+                             (size_t)(h1 - h0) * cols, hipMemcpyHostToDevice, cs);
+    };
+    // a band's float inputs into value slot b & 1 on cs, after the pass that
+    // last read the slot (band b - 2 of the same pass)
+    auto values_in = [&](int b, int64_t r0, int64_t r1) {
+        const int vs = b & 1;
+        if (b >= 2) (void)hipStreamWaitEvent(cs, ev[kEvVFree + vs], 0);
+        (void)hipMemcpyAsync(ws + S.vslot[vs], v_h + r0 * cols, (size_t)(r1 - r0) * cols * sizeof(float),
+                             hipMemcpyHostToDevice, cs);
+        (void)hipEventRecord(ev[kEvVReady + vs], cs);
+        (void)hipStreamWaitEvent(st, ev[kEvVReady + vs], 0);
     };
 
     init_state<<<1, 1, 0, st>>>(status, jstate);
@@ -788,50 +818,104 @@ int run_streamed(const uint8_t *dirs_h, uint32_t *acc_h, const Geo &g, const Str
         band(b, ty0, ty1, r0, r1);
         const int slot = b % 3;
         if (b >= 3) (void)hipStreamWaitEvent(cs, ev[kEvFree + slot], 0);
-        const int64_t h0 = std::max<int64_t>(0, r0 - 1), h1 = std::min(rows, r1 + 1);
-        (void)hipMemcpyAsync(ws + S.cslot[slot] + (h0 - (r0 - 1)) * cols, dirs_h + h0 * cols,
-                             (size_t)(h1 - h0) * cols, hipMemcpyHostToDevice, cs);
+        codes_in(slot, r0, r1);
         (void)hipEventRecord(ev[kEvReady + slot], cs);
         (void)hipStreamWaitEvent(st, ev[kEvReady + slot], 0);
+        if (vals) values_in(b, r0, r1);
         const int t0 = ty0 * g.ntx, nt = (ty1 - ty0) * g.ntx;
-        D8_LAUNCH("stream_fwd_pass1", st,
-                  (fwd_walk<1, uint32_t, V, E><<<nt, kTileThreads, lds1, st>>>(
-                      codes_ptr(S.cslot[slot], r0), nullptr, g, link, aloc, indeg, nullptr, acc, ext,
-                      nullptr, status, t0)));
+        const uint8_t *dirs = codes_ptr(S.cslot[slot], r0);
+        const float *v = vals ? band_ptr(S.vslot[b & 1], r0) : nullptr;
+        if (adj)
+            D8_LAUNCH("stream_adj_pass1", st,
+                      (adj_walk_band<<<nt, kTileThreads, lds1, st>>>(
+                          dirs, v, g, link, reinterpret_cast<float *>(ws + L.val32), nullptr, status, nullptr,
+                          nullptr, nullptr, jstate, t0)));
+        else if (f32)
+            D8_LAUNCH("stream_fwd_pass1", st,
+                      (fwd_walk<1, float, double, double><<<nt, kTileThreads, lds1, st>>>(
+                          dirs, v, g, link, reinterpret_cast<float *>(ws + L.val32), indeg, cnt,
+                          reinterpret_cast<double *>(ws + L.acc64), reinterpret_cast<double *>(ws + L.ext64),
+                          nullptr, status, t0)));
+        else
+            D8_LAUNCH("stream_fwd_pass1", st,
+                      (fwd_walk<1, uint32_t, VU, uint32_t><<<nt, kTileThreads, lds1, st>>>(
+                          dirs, nullptr, g, link, reinterpret_cast<uint32_t *>(ws + L.val32), indeg, nullptr,
+                          reinterpret_cast<VU *>(ws + L.acc64), reinterpret_cast<uint32_t *>(ws + L.ext64),
+                          nullptr, status, t0)));
+        if (vals) (void)hipEventRecord(ev[kEvVFree + (b & 1)], st);
         if (b >= 1) edges(b - 1);
     }
     edges(nband - 1);
-    D8_LAUNCH("stream_resolve", st,
-              (resolve_fwd_u32<<<blocks_for(g.nnodes, kNodeBlock), kNodeBlock, 0, st>>>(
-                  g.nnodes, link, aloc, entry, succ, indeg, acc, ext)));
-    D8_LAUNCH("stream_resolve_check", st,
-              (resolve_check<<<blocks_for(g.nnodes, kNodeBlock), kNodeBlock, 0, st>>>(
-                  g.nnodes, link, indeg, acc, nullptr, status)));
-    // pass 2 over the bands: code slots 0 and 1, count slots 0 and 1
+    // the resolve over the whole perimeter graph
+    unsigned long long *jw[2] = {reinterpret_cast<unsigned long long *>(ws + L.acc64),
+                                 reinterpret_cast<unsigned long long *>(ws + L.ext64)};
+    const unsigned nbn = blocks_for(g.nnodes, kNodeBlock);
+    if (adj) {
+        JumpGraph G{nullptr, g, nullptr, 0, nullptr};
+        G.entry = entry;
+        G.succ = succ;
+        jump_exits(st, g.nnodes, G, link, reinterpret_cast<float *>(ws + L.val32), indeg, cnt, jw, jstate, status,
+                   false);
+    } else if (f32) {
+        resolve_float<false>(st, false, g.nnodes, link, reinterpret_cast<float *>(ws + L.val32), succ, indeg, cnt,
+                             reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.kids),
+                             reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8,
+                             reinterpret_cast<double *>(ws + L.acc64), status);
+    } else {
+        VU *acc = reinterpret_cast<VU *>(ws + L.acc64);
+        D8_LAUNCH("stream_resolve", st,
+                  (resolve_fwd_u32<<<nbn, kNodeBlock, 0, st>>>(g.nnodes, link,
+                                                              reinterpret_cast<uint32_t *>(ws + L.val32), entry,
+                                                              succ, indeg, acc,
+                                                              reinterpret_cast<uint32_t *>(ws + L.ext64))));
+        D8_LAUNCH("stream_resolve_check", st,
+                  (resolve_check<<<nbn, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, acc, nullptr, status)));
+    }
+    // pass 2 over the bands: code, value and result slots b & 1
     (void)hipEventRecord(ev[kEvP1], st);
     (void)hipStreamWaitEvent(cs, ev[kEvP1], 0);
     for (int b = 0; b < nband; ++b) {
         int ty0, ty1;
-        int64_t r0, r1;
+        int64_t r0, r1, n0, n1;
         band(b, ty0, ty1, r0, r1);
+        nodes_of(ty0, ty1, n0, n1);
         const int cslot = b & 1, oslot = b & 1;
         if (b >= 2) (void)hipStreamWaitEvent(cs, ev[kEvCFree + cslot], 0);
-        (void)hipMemcpyAsync(ws + S.cslot[cslot] + cols, dirs_h + r0 * cols, (size_t)(r1 - r0) * cols,
-                             hipMemcpyHostToDevice, cs);
+        codes_in(cslot, r0, r1);
         (void)hipEventRecord(ev[kEvCReady + cslot], cs);
         (void)hipStreamWaitEvent(st, ev[kEvCReady + cslot], 0);
+        if (vals) values_in(b, r0, r1);
         if (b >= 2) (void)hipStreamWaitEvent(st, ev[kEvOFree + oslot], 0);
-        uint32_t *out = reinterpret_cast<uint32_t *>(ws + S.oslot[oslot]) - r0 * cols;
+        const uint8_t *dirs = codes_ptr(S.cslot[cslot], r0);
+        const float *v = vals ? band_ptr(S.vslot[b & 1], r0) : nullptr;
+        float *outf = band_ptr(S.oslot[oslot], r0);
         const int t0 = ty0 * g.ntx, nt = (ty1 - ty0) * g.ntx;
-        D8_LAUNCH("stream_fwd_pass2", st,
-                  (fwd_walk<2, uint32_t, V, E><<<nt, kTileThreads, lds2, st>>>(
-                      codes_ptr(S.cslot[cslot], r0), nullptr, g, link, aloc, indeg, nullptr, acc, ext,
-                      out, status, t0)));
+        if (adj) {
+            D8_LAUNCH("stream_adj_pass2", st,
+                      (adj_walk_band<<<nt, kTileThreads, lds2, st>>>(dirs, v, g, nullptr, nullptr, outf, status, cnt,
+                                                                      jw[0], jw[1], jstate, t0)));
+        } else if (f32) {
+            double *ext = reinterpret_cast<double *>(ws + L.ext64);
+            D8_LAUNCH("stream_resolve_ext", st,
+                      (resolve_ext<false><<<blocks_for(n1 - n0, kNodeBlock), kNodeBlock, 0, st>>>(
+                          dirs, g, link, reinterpret_cast<double *>(ws + L.acc64), ext, nullptr, n0, n1)));
+            D8_LAUNCH("stream_fwd_pass2", st,
+                      (fwd_walk<2, float, double, double><<<nt, kTileThreads, lds2, st>>>(
+                          dirs, v, g, link, reinterpret_cast<float *>(ws + L.val32), indeg, cnt,
+                          reinterpret_cast<double *>(ws + L.acc64), ext, outf, status, t0)));
+        } else {
+            D8_LAUNCH("stream_fwd_pass2", st,
+                      (fwd_walk<2, uint32_t, VU, uint32_t><<<nt, kTileThreads, lds2, st>>>(
+                          dirs, nullptr, g, link, reinterpret_cast<uint32_t *>(ws + L.val32), indeg, nullptr,
+                          reinterpret_cast<VU *>(ws + L.acc64), reinterpret_cast<uint32_t *>(ws + L.ext64),
+                          reinterpret_cast<uint32_t *>(outf), status, t0)));
+        }
         (void)hipEventRecord(ev[kEvCFree + cslot], st);
+        if (vals) (void)hipEventRecord(ev[kEvVFree + (b & 1)], st);
         (void)hipEventRecord(ev[kEvODone + oslot], st);
         (void)hipStreamWaitEvent(cs2, ev[kEvODone + oslot], 0);
-        (void)hipMemcpyAsync(acc_h + r0 * cols, ws + S.oslot[oslot], (size_t)(r1 - r0) * cols * sizeof(uint32_t),
-                             hipMemcpyDeviceToHost, cs2);
+        (void)hipMemcpyAsync(reinterpret_cast<char *>(out_h) + r0 * cols * 4, ws + S.oslot[oslot],
+                             (size_t)(r1 - r0) * cols * 4, hipMemcpyDeviceToHost, cs2);
         (void)hipEventRecord(ev[kEvOFree + oslot], cs2);
     }
     // the call is complete when `st` is: it waits for the last copy out
@@ -1176,7 +1260,47 @@ int flow_accum_streamed(const uint8_t *dirs_host, uint32_t *acc_host, int64_t ro
     if (!dirs_host || !acc_host) return D8_EINVAL;
     if (ws_bytes < S.total) return D8_EWORKSPACE;
     begin_call();
-    return run_streamed(dirs_host, acc_host, g, S, reinterpret_cast<char *>(ws), as_stream(stream));
+    return run_streamed(kStreamU32, dirs_host, nullptr, acc_host, g, S, reinterpret_cast<char *>(ws),
+                        as_stream(stream));
+}
+
+// The float kinds: weights (NULL = unit) or cotangents in host memory.
+static int streamed_float(int kind, const uint8_t *dirs_host, const float *v_host, float *out_host, int64_t rows,
+                   int64_t cols, int tile_rows, int tile_cols, int64_t band_rows, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    Geo g;
+    bool empty;
+    StreamLayout S;
+    int rc = stream_layout(rows, cols, tile_rows, tile_cols, band_rows, g, empty, S);
+    if (rc != D8_OK) return rc;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return D8_EWORKSPACE;
+    if (empty) {
+        if (ws_bytes < 512) return D8_EWORKSPACE;
+        init_state<<<1, 1, 0, as_stream(stream)>>>(reinterpret_cast<uint32_t *>(ws),
+                                                   reinterpret_cast<uint32_t *>((char *)ws + 256));
+        return last_error();
+    }
+    if (!dirs_host || !out_host || (kind == kStreamAdj && !v_host)) return D8_EINVAL;
+    if (ws_bytes < S.total) return D8_EWORKSPACE;
+    begin_call();
+    return run_streamed(kind, dirs_host, v_host, out_host, g, S, reinterpret_cast<char *>(ws), as_stream(stream));
+}
+
+int flow_accum_streamed_f32(const uint8_t *dirs_host, const float *weights_host, float *acc_host, int64_t rows,
+                            int64_t cols, int tile_rows, int tile_cols, int64_t band_rows, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    return streamed_float(kStreamF32, dirs_host, weights_host, acc_host, rows, cols, tile_rows, tile_cols,
+                          band_rows, ws, ws_bytes, stream);
+}
+
+int flow_accum_adjoint_streamed(const uint8_t *dirs_host, const float *grad_host, float *grad_weights_host,
+                                int64_t rows, int64_t cols, int tile_rows, int tile_cols, int64_t band_rows,
+                                void *ws, size_t ws_bytes, void *stream)
+{
+    return streamed_float(kStreamAdj, dirs_host, grad_host, grad_weights_host, rows, cols, tile_rows, tile_cols,
+                          band_rows, ws, ws_bytes, stream);
 }
 
 size_t d8_batch_workspace_bytes(const d8_batch_item *items, int n)

@@ -515,7 +515,24 @@ struct JumpGraph {
     const DemDesc *dems;
     int ndem;
     const uint32_t *chunk_dem;
+    // edges found earlier (graph_build's entry and succ, for a raster whose
+    // directions are not resident): used when set
+    const uint32_t *entry = nullptr, *succ = nullptr;
 };
+
+__device__ inline void jump_edge(const JumpGraph &G, const uint16_t *__restrict__ link, int64_t id, uint32_t &n,
+                                 uint32_t &s)
+{
+    if (G.entry) {
+        n = G.entry[id];
+        s = G.succ[id];
+    } else if (G.dems) {
+        const DemDesc &D = G.dems[dem_of(G.dems, G.ndem, G.chunk_dem, id)];
+        graph_edge(D.dirs, D.g, D.node0, id - D.node0, link, n, s);
+    } else {
+        graph_edge(G.dirs, G.g, 0, id, link, n, s);
+    }
+}
 
 // Initial words of the exits (a fixed grid strides over them): each exit's
 // edge (as graph_build finds it), pointer = the dense index of the
@@ -531,12 +548,7 @@ adj_jump_init(const uint32_t *__restrict__ nexit, const uint32_t *__restrict__ i
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += stride) {
         const int64_t id = inv[i];
         uint32_t n, s;
-        if (G.dems) {
-            const DemDesc &D = G.dems[dem_of(G.dems, G.ndem, G.chunk_dem, id)];
-            graph_edge(D.dirs, D.g, D.node0, id - D.node0, link, n, s);
-        } else {
-            graph_edge(G.dirs, G.g, 0, id, link, n, s);
-        }
+        jump_edge(G, link, id, n, s);
         buf0[i] = jump_word(s != kNone ? cmap[s] : kNone, n != kNone ? S[n] : 0.0f);
     }
 }
@@ -867,13 +879,15 @@ __device__ inline double ext_gather(const uint8_t *__restrict__ dirs, const Geo 
     return e;
 }
 
+// Nodes id0 .. id1 - 1 (all of them, or one band's when streaming: then
+// dirs holds the band's rows and one halo row above and below).
 template <bool ABS>
 __global__ void resolve_ext(const uint8_t *__restrict__ dirs, Geo g, const uint16_t *__restrict__ link,
                             const double *__restrict__ vn, double *__restrict__ ext,
-                            const float *__restrict__ anode = nullptr)
+                            const float *__restrict__ anode, int64_t id0, int64_t id1)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.nnodes) return;
+    const int64_t id = id0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= id1) return;
     ext[id] = ext_gather<ABS>(dirs, g, 0, id, link, vn, anode);
 }
 

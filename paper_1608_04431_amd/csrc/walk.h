@@ -1188,7 +1188,8 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
                                 float *__restrict__ Sg, float *__restrict__ out,
                                 uint8_t *__restrict__ root8, uint32_t *status, uint8_t *lds8,
                                 const float *__restrict__ alpha = nullptr, float *__restrict__ Pg = nullptr,
-                                float *__restrict__ pout = nullptr)
+                                float *__restrict__ pout = nullptr, const uint32_t *__restrict__ cmap = nullptr,
+                                const unsigned long long *__restrict__ mu = nullptr)
 {
     using namespace wk;
     WTile Tl = wtile_of(g, t);
@@ -1233,11 +1234,25 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
             atomicOr(&exitbits[p >> 5], 1u << (p & 31));
     }
     __syncthreads();
+    if (mu) {
+        // finishing without retained sums (EVICT, for rasters streamed from
+        // host memory): each exit starts from g + mu, the resolved sum of the
+        // tile it flows into, so the walks give lambda itself
+        for (int p = lane; p < Tl.P; p += 64) {
+            const uint32_t cm = cmap[Tl.base + p];
+            if (cm != kNone) {
+                int qr, qc;
+                ring_cell(p, Tl.h, Tl.w, qr, qc);
+                avp[cidx(Tl, qr, qc)] += __uint_as_float((uint32_t)(mu[cm] >> 32));
+            }
+        }
+        __syncthreads();
+    }
     int visited = up_walks<ABS>(Tl, g, dirs, cb8, avp, q, L.qcap, St.root, pend, exitbits, alp);
     if (wave_sum(visited + __popcll(St.root)) != wave_sum(__popcll(St.valid)) && lane == 0)
         set_status(status, kStatusCycle);
     __syncthreads();
-    for (int p = lane; p < Tl.P; p += 64) {
+    for (int p = lane; link && p < Tl.P; p += 64) {
         int qr, qc;
         ring_cell(p, Tl.h, Tl.w, qr, qc);
         const int idx = cidx(Tl, qr, qc);
@@ -1251,8 +1266,8 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
         Sg[Tl.base + p] = lab == kLabelNoData ? 0.0f : avp[idx];
         if constexpr (ABS) Pg[Tl.base + p] = lab == kLabelNoData ? 0.0f : alp[idx];
     }
-    rows_out(Tl, g, avp, St.valid, out);
-    bytes_out(Tl, g, cb8, root8);
+    if (out) rows_out(Tl, g, avp, St.valid, out);
+    if (root8) bytes_out(Tl, g, cb8, root8);
     if constexpr (ABS) rows_out(Tl, g, alp, St.valid, pout);
 }
 
@@ -1397,6 +1412,22 @@ adj_walk(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
 {
     extern __shared__ __align__(16) uint8_t lds8[];
     adj_tile(dirs, gin, g, 0, xcd_tile(blockIdx.x, gridDim.x), link, Sg, out, root8, status, lds8);
+}
+
+// Adjoint over a band of tile rows of a raster streamed from host memory
+// (tiles t0 .. t0 + gridDim.x - 1).  Pass 1 writes the perimeter records
+// only; pass 2 (mu0 / mu1 given: the jump buffers, jstate[0] naming the
+// final one) seeds the exits with mu and writes lambda.
+__global__ void __launch_bounds__(64, 3)
+adj_walk_band(const uint8_t *__restrict__ dirs, const float *__restrict__ gin, Geo g,
+              uint16_t *__restrict__ link, float *__restrict__ Sg, float *__restrict__ out, uint32_t *status,
+              const uint32_t *__restrict__ cmap, const unsigned long long *__restrict__ mu0,
+              const unsigned long long *__restrict__ mu1, const uint32_t *__restrict__ jstate, int t0)
+{
+    extern __shared__ __align__(16) uint8_t lds8[];
+    const unsigned long long *mu = mu0 ? (jstate[0] == 1 ? mu1 : mu0) : nullptr;
+    adj_tile(dirs, gin, g, 0, t0 + xcd_tile(blockIdx.x, gridDim.x), link, Sg, out, nullptr, status, lds8,
+             nullptr, nullptr, nullptr, cmap, mu);
 }
 
 // Adjoint with absorption: pass 1 also writes P per perimeter node (Pg) and

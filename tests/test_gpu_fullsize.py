@@ -101,10 +101,17 @@ def test_dem32768_full_size(d8m, c3):
     g = torch.from_numpy(c3["g_host"]).cuda()
     lam = d8m.flow_accum_adjoint(dirs, g, tile=tile_a)
     torch.cuda.synchronize()
-    # the same forward with the raster in host memory, streamed in bands
-    As = d8m.flow_accum_streamed(dirs.cpu().pin_memory(), tile=tile_f)
+    # the same forward and adjoint with the raster in host memory, streamed
+    # in bands: counts bit for bit, the adjoint (tiles recomputed, exits
+    # seeded) within float32 rounding of the in-memory one
+    dirs_h = dirs.cpu().pin_memory()
+    As = d8m.flow_accum_streamed(dirs_h, tile=tile_f)
     assert torch.equal(As, A.cpu())
     del As
+    Ls = d8m.flow_accum_adjoint_streamed(dirs_h, g.cpu().pin_memory(), tile=tile_a).double()
+    Lm = lam.cpu().double()
+    assert float(((Ls - Lm).abs() / Lm.abs().clamp_min(1e-30)).max()) <= 1e-5
+    del Ls, Lm, dirs_h
 
     recv = receivers(dirs)
     data = dirs.view(-1) != 9
