@@ -48,10 +48,10 @@ SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (64, 32), (56, 
 ABSORB_TILE = (32, 48)  # the absorption entry points' default shape
 
 KERNEL_NAMES = {  # timing label -> kernel symbol prefix in profiler output
-    "fwd_pass1": "void d8::fwd_walk<1, unsigned int",
-    "fwd_pass2": "void d8::fwd_walk<2, unsigned int",
-    "adj_pass1": "d8::adj_walk",
-    "adj_pass2": "d8::adj_finish",
+    "fwd_pass1": "fwd_walk<1, unsigned int",
+    "fwd_pass2": "fwd_walk<2, unsigned int",
+    "adj_pass1": "adj_walk",
+    "adj_pass2": "adj_finish",
 }
 SOURCES = ("paper_1608_04431_amd/csrc/d8flow.hip", "paper_1608_04431_amd/csrc/kernels.h",
            "paper_1608_04431_amd/csrc/walk.h", "paper_1608_04431_amd/csrc/d8_common.h")

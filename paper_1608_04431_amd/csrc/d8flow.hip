@@ -230,6 +230,57 @@ int last_error()
     return g_launch_rc;
 }
 
+// The tile kernels compiled for the narrowest register rows that hold the
+// tile width (walk.h is compiled for rows of 64, 44 and 32 columns).
+inline int row_width(int tw) { return tw <= 32 ? 32 : (tw <= 44 ? 44 : 64); }
+
+template <int PASS, typename T, typename V, typename E>
+decltype(&w64::fwd_walk<PASS, T, V, E>) fwd_walk_k(int tw)
+{
+    switch (row_width(tw)) {
+    case 32: return &w32::fwd_walk<PASS, T, V, E>;
+    case 44: return &w44::fwd_walk<PASS, T, V, E>;
+    default: return &w64::fwd_walk<PASS, T, V, E>;
+    }
+}
+
+decltype(&w64::adj_walk) adj_walk_k(int tw)
+{
+    switch (row_width(tw)) {
+    case 32: return &w32::adj_walk;
+    case 44: return &w44::adj_walk;
+    default: return &w64::adj_walk;
+    }
+}
+
+decltype(&w64::adj_walk_band) adj_walk_band_k(int tw)
+{
+    switch (row_width(tw)) {
+    case 32: return &w32::adj_walk_band;
+    case 44: return &w44::adj_walk_band;
+    default: return &w64::adj_walk_band;
+    }
+}
+
+template <int PASS>
+decltype(&w64::fwd_walk_batch<PASS>) fwd_walk_batch_k(int tw)
+{
+    switch (row_width(tw)) {
+    case 32: return &w32::fwd_walk_batch<PASS>;
+    case 44: return &w44::fwd_walk_batch<PASS>;
+    default: return &w64::fwd_walk_batch<PASS>;
+    }
+}
+
+decltype(&w64::adj_walk_batch) adj_walk_batch_k(int tw)
+{
+    switch (row_width(tw)) {
+    case 32: return &w32::adj_walk_batch;
+    case 44: return &w44::adj_walk_batch;
+    default: return &w64::adj_walk_batch;
+    }
+}
+
 // Dynamic LDS above the default 64 KiB must be allowed per kernel.
 template <typename K>
 int allow_lds(K kernel, size_t bytes)
@@ -296,13 +347,13 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
     const int thr = kTileThreads;
     size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1, (int)sizeof(FwdLds<1, T>));
     size_t lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2, (int)sizeof(FwdLds<2, T>));
-    if (allow_lds(fwd_walk<1, T, V, E>, lds1) || allow_lds(fwd_walk<2, T, V, E>, lds2))
-        return D8_EHIP;
+    const auto pass1 = fwd_walk_k<1, T, V, E>(g.tw), pass2 = fwd_walk_k<2, T, V, E>(g.tw);
+    if (allow_lds(pass1, lds1) || allow_lds(pass2, lds2)) return D8_EHIP;
 
     init_state<<<1, 1, 0, st>>>(status, jstate);
     unsigned nb = blocks_for(g.nnodes, kNodeBlock);
     D8_LAUNCH("fwd_pass1", st,
-              (fwd_walk<1, T, V, E><<<ntiles, thr, lds1, st>>>(dirs, w, g, link, aloc, indeg, cnt,
+              (pass1<<<ntiles, thr, lds1, st>>>(dirs, w, g, link, aloc, indeg, cnt,
                                                                acc, ext, nullptr, status, 0)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, 0, g.nnodes)));
@@ -322,7 +373,7 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
                   (resolve_ext<false><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, nullptr, 0, g.nnodes)));
     }
     D8_LAUNCH("fwd_pass2", st,
-              (fwd_walk<2, T, V, E><<<ntiles, thr, lds2, st>>>(dirs, w, g, link, aloc, indeg, cnt,
+              (pass2<<<ntiles, thr, lds2, st>>>(dirs, w, g, link, aloc, indeg, cnt,
                                                                acc, ext, out, status, 0)));
     return last_error();
 }
@@ -408,6 +459,7 @@ struct TileGroup {
     int th, tw;
     int64_t t_begin, t_end;
     size_t lds[3];  // fwd pass 1, fwd pass 2, adj pass 1
+    int maxw;       // widest tile of the group (selects the kernels' register rows)
 };
 constexpr int kMaxGroups = 16;  // distinct tile shapes in one batch
 
@@ -461,7 +513,7 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
         const int key_th = it.tile_rows, key_tw = it.tile_cols;
         if (P.groups.empty() || P.groups.back().th != key_th || P.groups.back().tw != key_tw) {
             if ((int)P.groups.size() == kMaxGroups) return D8_EINVAL;
-            P.groups.push_back({key_th, key_tw, P.ntiles, P.ntiles, {0, 0, 0}});
+            P.groups.push_back({key_th, key_tw, P.ntiles, P.ntiles, {0, 0, 0}, 0});
         }
         TileGroup &G = P.groups.back();
         for (int64_t t = 0; t < nt; ++t) P.tile_dem.push_back((uint32_t)P.dems.size());
@@ -473,6 +525,7 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
         P.nnodes += g.nnodes;
         G.t_end = P.ntiles;
         if (P.nnodes >= (int64_t)kJumpDone || P.ntiles >= (int64_t)INT_MAX) return D8_EINVAL;
+        G.maxw = std::max(G.maxw, g.tw);
         G.lds[0] = std::max(G.lds[0], walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4));
         G.lds[1] = std::max(G.lds[1], walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4));
         G.lds[2] = std::max(G.lds[2], walk_lds_bytes(g.th, g.tw, kWalkAdj1, 4));
@@ -600,10 +653,11 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
     init_batch<<<1, 1, 0, st>>>(status, jstate);
     if (ndem == 0) return last_error();
     // one launch per tile group and stage, a wavefront per tile of the group
-    auto tiles = [&](int stage, auto kernel, const char *name, auto &&...args) -> int {
+    auto tiles = [&](int stage, auto select, const char *name, auto &&...args) -> int {
         for (size_t k = 0; k < P.groups.size(); ++k) {
             const TileGroup &G = P.groups[k];
             const size_t lds = G.lds[stage];
+            const auto kernel = select(G.maxw);
             if (allow_lds(kernel, lds)) return D8_EHIP;
             D8_LAUNCH(name, st,
                       (kernel<<<(unsigned)(G.t_end - G.t_begin), 64, lds, st>>>(
@@ -612,7 +666,7 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
         return D8_OK;
     };
     if (mode & D8_BATCH_FWD) {
-        if (tiles(0, fwd_walk_batch<1>, "batch_fwd_pass1", link, val32, indeg, cnt, acc, ext, status))
+        if (tiles(0, fwd_walk_batch_k<1>, "batch_fwd_pass1", link, val32, indeg, cnt, acc, ext, status))
             return D8_EHIP;
         D8_LAUNCH("batch_graph_build", st,
                   (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
@@ -622,12 +676,12 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
                              reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8, acc, status);
         D8_LAUNCH("batch_resolve_ext", st,
                   (resolve_ext_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, acc, ext)));
-        if (tiles(1, fwd_walk_batch<2>, "batch_fwd_pass2", link, val32, indeg, cnt, acc, ext, status))
+        if (tiles(1, fwd_walk_batch_k<2>, "batch_fwd_pass2", link, val32, indeg, cnt, acc, ext, status))
             return D8_EHIP;
     }
     if (mode & D8_BATCH_ADJ) {
         reset_jump<<<1, 1, 0, st>>>(jstate);
-        if (tiles(2, adj_walk_batch, "batch_adj_pass1", link, val32, status)) return D8_EHIP;
+        if (tiles(2, adj_walk_batch_k, "batch_adj_pass1", link, val32, status)) return D8_EHIP;
         // the exits' edges are found as their jump words are initialised
         const JumpGraph G{nullptr, Geo{}, dems, ndem, chunk_dem};
         jump_exits(st, N, G, link, val32, indeg, cnt, jw, jstate, status, true);
@@ -760,9 +814,11 @@ int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h,
     const size_t lds1 = adj ? walk_lds_bytes(g.th, g.tw, kWalkAdj1)
                             : walk_lds_bytes(g.th, g.tw, kWalkFwd1, f32 ? 4 : (int)sizeof(FwdLds<1, uint32_t>));
     const size_t lds2 = adj ? lds1 : walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4);
-    if (allow_lds(fwd_walk<1, uint32_t, VU, uint32_t>, lds1) || allow_lds(fwd_walk<2, uint32_t, VU, uint32_t>, lds2) ||
-        allow_lds(fwd_walk<1, float, double, double>, lds1) || allow_lds(fwd_walk<2, float, double, double>, lds2) ||
-        allow_lds(adj_walk_band, lds1))
+    const auto u1 = fwd_walk_k<1, uint32_t, VU, uint32_t>(g.tw), u2 = fwd_walk_k<2, uint32_t, VU, uint32_t>(g.tw);
+    const auto f1 = fwd_walk_k<1, float, double, double>(g.tw), f2 = fwd_walk_k<2, float, double, double>(g.tw);
+    const auto ab = adj_walk_band_k(g.tw);
+    if (allow_lds(u1, lds1) || allow_lds(u2, lds2) || allow_lds(f1, lds1) || allow_lds(f2, lds2) ||
+        allow_lds(ab, lds1))
         return D8_EHIP;
     auto band = [&](int b, int &ty0, int &ty1, int64_t &r0, int64_t &r1) {
         ty0 = b * tb;
@@ -827,18 +883,18 @@ int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h,
         const float *v = vals ? band_ptr(S.vslot[b & 1], r0) : nullptr;
         if (adj)
             D8_LAUNCH("stream_adj_pass1", st,
-                      (adj_walk_band<<<nt, kTileThreads, lds1, st>>>(
+                      (ab<<<nt, kTileThreads, lds1, st>>>(
                           dirs, v, g, link, reinterpret_cast<float *>(ws + L.val32), nullptr, status, nullptr,
                           nullptr, nullptr, jstate, t0)));
         else if (f32)
             D8_LAUNCH("stream_fwd_pass1", st,
-                      (fwd_walk<1, float, double, double><<<nt, kTileThreads, lds1, st>>>(
+                      (f1<<<nt, kTileThreads, lds1, st>>>(
                           dirs, v, g, link, reinterpret_cast<float *>(ws + L.val32), indeg, cnt,
                           reinterpret_cast<double *>(ws + L.acc64), reinterpret_cast<double *>(ws + L.ext64),
                           nullptr, status, t0)));
         else
             D8_LAUNCH("stream_fwd_pass1", st,
-                      (fwd_walk<1, uint32_t, VU, uint32_t><<<nt, kTileThreads, lds1, st>>>(
+                      (u1<<<nt, kTileThreads, lds1, st>>>(
                           dirs, nullptr, g, link, reinterpret_cast<uint32_t *>(ws + L.val32), indeg, nullptr,
                           reinterpret_cast<VU *>(ws + L.acc64), reinterpret_cast<uint32_t *>(ws + L.ext64),
                           nullptr, status, t0)));
@@ -892,7 +948,7 @@ int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h,
         const int t0 = ty0 * g.ntx, nt = (ty1 - ty0) * g.ntx;
         if (adj) {
             D8_LAUNCH("stream_adj_pass2", st,
-                      (adj_walk_band<<<nt, kTileThreads, lds2, st>>>(dirs, v, g, nullptr, nullptr, outf, status, cnt,
+                      (ab<<<nt, kTileThreads, lds2, st>>>(dirs, v, g, nullptr, nullptr, outf, status, cnt,
                                                                       jw[0], jw[1], jstate, t0)));
         } else if (f32) {
             double *ext = reinterpret_cast<double *>(ws + L.ext64);
@@ -900,12 +956,12 @@ int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h,
                       (resolve_ext<false><<<blocks_for(n1 - n0, kNodeBlock), kNodeBlock, 0, st>>>(
                           dirs, g, link, reinterpret_cast<double *>(ws + L.acc64), ext, nullptr, n0, n1)));
             D8_LAUNCH("stream_fwd_pass2", st,
-                      (fwd_walk<2, float, double, double><<<nt, kTileThreads, lds2, st>>>(
+                      (f2<<<nt, kTileThreads, lds2, st>>>(
                           dirs, v, g, link, reinterpret_cast<float *>(ws + L.val32), indeg, cnt,
                           reinterpret_cast<double *>(ws + L.acc64), ext, outf, status, t0)));
         } else {
             D8_LAUNCH("stream_fwd_pass2", st,
-                      (fwd_walk<2, uint32_t, VU, uint32_t><<<nt, kTileThreads, lds2, st>>>(
+                      (u2<<<nt, kTileThreads, lds2, st>>>(
                           dirs, nullptr, g, link, reinterpret_cast<uint32_t *>(ws + L.val32), indeg, nullptr,
                           reinterpret_cast<VU *>(ws + L.acc64), reinterpret_cast<uint32_t *>(ws + L.ext64),
                           reinterpret_cast<uint32_t *>(outf), status, t0)));
@@ -1087,10 +1143,11 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
     const int thr = kTileThreads;
     size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1);
     begin_call();
-    if (allow_lds(adj_walk, lds1)) return D8_EHIP;
+    const auto pass1 = adj_walk_k(g.tw);
+    if (allow_lds(pass1, lds1)) return D8_EHIP;
     init_state<<<1, 1, 0, st>>>(status, jstate);
     D8_LAUNCH("adj_pass1", st,
-              (adj_walk<<<ntiles, thr, lds1, st>>>(dirs, grad_acc, g, link, S, grad_weights, root8,
+              (pass1<<<ntiles, thr, lds1, st>>>(dirs, grad_acc, g, link, S, grad_weights, root8,
                                                    status)));
     // the exits' edges are found as their jump words are initialised
     const JumpGraph G{dirs, g, nullptr, 0, nullptr};

@@ -26,7 +26,20 @@
 // D8 directions (and rho8's): d8_kernel.
 #pragma once
 #include "d8_common.h"
+// the tile kernels for tiles up to 64 columns (namespace w64), and the same
+// kernels with register rows of 44 and 32 columns for narrower tiles: less
+// work in every per-row loop of the setup
 #include "walk.h"
+#define D8_WALK_KW 44
+#define D8_WALK_NS w44
+#include "walk.h"
+#define D8_WALK_KW 32
+#define D8_WALK_NS w32
+#include "walk.h"
+
+namespace d8 {
+using namespace w64;
+}
 
 namespace d8 {
 

@@ -26,16 +26,28 @@
 // the flow; side donors of a branching cell are finished on the spot and
 // queued.  All walks of a tile run in one wavefront, so the order of LDS
 // operations is fixed by the input.
-#pragma once
+//
+// Register rows.  Lane r holds tile row r in ceil(kW / 4) words, so the row
+// width kW bounds the tile width and sets the work of every per-row loop.
+// This file is included once per width: without D8_WALK_KW it defines the
+// general kernels (kW = 64) in namespace d8::w64; the includer may define
+// D8_WALK_KW and D8_WALK_NS to compile the same kernels for narrower tiles in
+// a namespace of their own.
+
+#ifndef D8_WALK_KW
+#define D8_WALK_KW 64
+#define D8_WALK_NS w64
+#endif
 
 #include <type_traits>
 
 #include "d8_common.h"
 
 namespace d8 {
+namespace D8_WALK_NS {
 namespace wk {
 
-constexpr int kW = 64;          // max tile width (columns)
+constexpr int kW = D8_WALK_KW;  // max tile width (columns)
 constexpr int kH = 64;          // max tile height (rows) = lanes
 constexpr int kWords = kW / 4;  // code words per row
 
@@ -1518,4 +1530,8 @@ __host__ inline size_t walk_lds_bytes(int th, int tw, int kind, int vbytes = 4, 
 }
 
 
+}  // namespace D8_WALK_NS
 }  // namespace d8
+
+#undef D8_WALK_KW
+#undef D8_WALK_NS
