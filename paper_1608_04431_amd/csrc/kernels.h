@@ -127,18 +127,55 @@ __device__ inline float d8_at(const D8Row &row, int i)  // i in -1 .. 4
     return i < 0 ? row.l : (i > 3 ? row.r : row.v[i]);
 }
 
-__device__ inline void d8_consider(float zc, float zn, int k, float &best, int &code)
+// The largest strictly positive drop among four neighbours (0 when there is
+// none) and the lowest code that has it.  A NaN drop (NoData or off-grid
+// neighbour) is skipped by the maximum (IEEE maxNum) and equals nothing.
+__device__ inline float d8_best4(float zc, float z0, float z1, float z2, float z3, int k0, int k1, int k2,
+                                 int k3, int &code)
 {
-    const float d = __fsub_rn(zc, zn);
-    if (d > best) {
-        best = d;
-        code = k;
+    const float d0 = __fsub_rn(zc, z0), d1 = __fsub_rn(zc, z1);
+    const float d2 = __fsub_rn(zc, z2), d3 = __fsub_rn(zc, z3);
+    const float m = fmaxf(fmaxf(fmaxf(0.0f, d0), d1), fmaxf(d2, d3));
+    // selects from the last to the first (no branches)
+    int k = k3;
+    k = d2 == m ? k2 : k;
+    k = d1 == m ? k1 : k;
+    k = d0 == m ? k0 : k;
+    code = k;
+    return m;
+}
+
+// Cardinal (best drop bc, code kc) against diagonal (bd, kd): the diagonal
+// wins when bd / s > bc with s its distance (sqrt 2 for D8: bd^2 > 2 bc^2;
+// t = fl32(2 - r) for rho8: bd > bc t); equal slopes keep the lower code.
+// The float products decide when both are normal numbers (or infinite) and
+// differ by more than their rounding (each is within 2^-23 of its exact
+// value; the margin is 2^-20); otherwise, rarely, the exact double compare.
+template <bool RHO>
+__device__ inline int d8_pick(float bc, int kc, float bd, int kd, float t)
+{
+    constexpr float kUp = 1.0f + 0x1p-20f;
+    constexpr float kMin = 0x1p-126f;  // smallest normal float
+    const bool cpos = bc > 0.0f, dpos = bd > 0.0f;
+    const float x = RHO ? bd : bd * bd;
+    const float y = RHO ? bc * t : 2.0f * (bc * bc);
+    const bool normal = x >= kMin && y >= kMin;
+    const bool dwin = normal && x > y * kUp, cwin = normal && y > x * kUp;
+    // straight-line selects; the exact compare only where the floats cannot decide
+    int code = cwin ? kc : kd;
+    code = cpos ? code : kd;
+    code = dpos ? code : (cpos ? kc : kNoFlow);
+    if (cpos && dpos && !dwin && !cwin) {
+        const double dc = bc, dd = bd;
+        const double keyc = RHO ? dc * (double)t : 2.0 * (dc * dc);
+        const double keyd = RHO ? dd : dd * dd;
+        code = keyd > keyc ? kd : (keyc > keyd ? kc : (kc < kd ? kc : kd));
     }
+    return code;
 }
 
 // RHO: rho8 (Fairfield and Leymarie) -- the diagonal distance of cell i is
-// t[i] = fl32(2 - r) for its random r in [0, 1) instead of sqrt 2; the
-// diagonal wins when bd / t > bc, compared exactly as bd > bc * t in double.
+// t[i] = fl32(2 - r) for its random r in [0, 1) instead of sqrt 2.
 template <bool RHO = false>
 __device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8Row &dn,
                                      const float *t = nullptr)
@@ -149,26 +186,12 @@ __device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8
         const float zc = mid.v[i];
         int code = kNoData;
         if (zc == zc) {
-            float bc = 0.0f, bd = 0.0f;
-            int kc = kNoFlow, kd = kNoFlow;
-            d8_consider(zc, d8_at(up, i - 1), 0, bd, kd);
-            d8_consider(zc, d8_at(up, i), 1, bc, kc);
-            d8_consider(zc, d8_at(up, i + 1), 2, bd, kd);
-            d8_consider(zc, d8_at(mid, i - 1), 3, bc, kc);
-            d8_consider(zc, d8_at(mid, i + 1), 4, bc, kc);
-            d8_consider(zc, d8_at(dn, i - 1), 5, bd, kd);
-            d8_consider(zc, d8_at(dn, i), 6, bc, kc);
-            d8_consider(zc, d8_at(dn, i + 1), 7, bd, kd);
-            const double dc = bc, dd = bd;
-            double keyc, keyd;
-            if constexpr (RHO) {
-                keyc = dc * (double)t[i];
-                keyd = dd;
-            } else {
-                keyc = 2.0 * (dc * dc);
-                keyd = dd * dd;
-            }
-            code = keyd > keyc ? kd : (keyc > keyd ? kc : (kc < kd ? kc : kd));
+            int kc, kd;
+            const float bc = d8_best4(zc, d8_at(up, i), d8_at(mid, i - 1), d8_at(mid, i + 1), d8_at(dn, i),
+                                      1, 3, 4, 6, kc);
+            const float bd = d8_best4(zc, d8_at(up, i - 1), d8_at(up, i + 1), d8_at(dn, i - 1),
+                                      d8_at(dn, i + 1), 0, 2, 5, 7, kd);
+            code = d8_pick<RHO>(bc, kc, bd, kd, RHO ? t[i] : 0.0f);
         }
         out |= (uint32_t)code << (8 * i);
     }
