@@ -81,16 +81,29 @@ __host__ __device__ inline int64_t node_base(const Geo &g, int ty, int tx)
     return (int64_t)ty * g.row_nodes + (int64_t)tx * ring_size(tile_h(g, ty), g.tw);
 }
 
-// Inverse of node_base + ring index.
+// Inverse of node_base + ring index (node ids and the nodes of one tile row
+// fit 32 bits: the callers check nnodes < 2^32 - 1).
 __host__ __device__ inline void node_tile(const Geo &g, int64_t id, int &ty, int &tx, int &p)
 {
-    int64_t a = id / g.row_nodes;
-    ty = (int)(a < g.nty - 1 ? a : g.nty - 1);
-    int64_t rem = id - (int64_t)ty * g.row_nodes;
-    int P = ring_size(tile_h(g, ty), g.tw);
-    int64_t b = rem / P;
-    tx = (int)(b < g.ntx - 1 ? b : g.ntx - 1);
-    p = (int)(rem - (int64_t)tx * P);
+    const uint32_t a = (uint32_t)id / (uint32_t)g.row_nodes;
+    ty = (int)(a < (uint32_t)(g.nty - 1) ? a : (uint32_t)(g.nty - 1));
+    const uint32_t rem = (uint32_t)id - (uint32_t)ty * (uint32_t)g.row_nodes;
+    const uint32_t P = (uint32_t)ring_size(tile_h(g, ty), g.tw);
+    const uint32_t b = rem / P;
+    tx = (int)(b < (uint32_t)(g.ntx - 1) ? b : (uint32_t)(g.ntx - 1));
+    p = (int)(rem - (uint32_t)tx * P);
+}
+
+// The tile (uty, utx) and tile-local cell (ur, uc) of the cell at local
+// (r, c) of tile (ty, tx) of height h and width w, for a cell at most one
+// step outside the tile (no division).
+__host__ __device__ inline void step_tile(const Geo &g, int ty, int tx, int h, int w, int r, int c, int &uty,
+                                          int &utx, int &ur, int &uc)
+{
+    uty = r < 0 ? ty - 1 : (r >= h ? ty + 1 : ty);
+    utx = c < 0 ? tx - 1 : (c >= w ? tx + 1 : tx);
+    ur = r < 0 ? tile_h(g, uty) - 1 : (r >= h ? 0 : r);
+    uc = c < 0 ? tile_w(g, utx) - 1 : (c >= w ? 0 : c);
 }
 
 inline Geo make_geo(int64_t rows, int64_t cols, int th, int tw)

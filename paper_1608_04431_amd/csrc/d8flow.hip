@@ -33,20 +33,21 @@ constexpr int kNodeBlock = 256;
 
 struct Layout {
     size_t status, jstate, link, entry, succ, indeg, val32, acc64, ext64, ptr2, root8, total;
-    size_t off, kids, bsum;  // the float forward's children lists, where root8 lies (adjoint only)
+    size_t off, kids, srt, bsum;  // the float forward's children lists, where root8 lies (adjoint only)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Children lists of the float forward's resolve, placed over an area the
-// forward does not otherwise use (the adjoint's root labels): offsets and
-// children (a word per node each) and one word per 4096 nodes for the scan.
-// Returns the end of the lists.
-size_t csr_place(size_t at, size_t N, size_t &off, size_t &kids, size_t &bsum)
+// forward does not otherwise use (the adjoint's root labels): offsets,
+// children as filled and children in order (a word per node each), and one
+// word per 4096 nodes for the scan.  Returns the end of the lists.
+size_t csr_place(size_t at, size_t N, size_t &off, size_t &kids, size_t &srt, size_t &bsum)
 {
     off = at;
     kids = align256(off + N * sizeof(uint32_t));
-    bsum = align256(kids + N * sizeof(uint32_t));
+    srt = align256(kids + N * sizeof(uint32_t));
+    bsum = align256(srt + N * sizeof(uint32_t));
     return align256(bsum + (N / (size_t)kCompactNodes + 2) * sizeof(uint32_t));
 }
 
@@ -66,7 +67,7 @@ Layout layout_for(const Geo &g)
     L.acc64 = off;  off = align256(off + N * sizeof(double));
     L.ext64 = off;  off = align256(off + N * sizeof(double));
     L.root8 = off;  off = align256(off + (size_t)g.rows * (size_t)g.cols);  // adjoint root labels
-    L.total = std::max(off, csr_place(L.root8, N, L.off, L.kids, L.bsum));
+    L.total = std::max(off, csr_place(L.root8, N, L.off, L.kids, L.srt, L.bsum));
     return L;
 }
 
@@ -303,21 +304,29 @@ int allow_lds(K kernel, size_t bytes)
 // The timing labels are literals: the batch's carry their own.
 template <bool ABS>
 void resolve_float(hipStream_t st, bool batch, int64_t N, const uint16_t *link, const float *aloc,
-                   const uint32_t *succ, const uint32_t *indeg, uint32_t *cnt, uint32_t *off, uint32_t *kids,
-                   uint32_t *bsum, uint32_t *total, double *vn, uint32_t *status,
+                   const uint32_t *succ, const uint32_t *indeg, uint32_t *cnt, char *ws, size_t off_at,
+                   size_t kids_at, size_t srt_at, size_t bsum_at, uint32_t *total, double *vn, uint32_t *status,
                    const uint32_t *entry = nullptr, const float *anode = nullptr, const float *pathp = nullptr)
 {
+    uint32_t *off = reinterpret_cast<uint32_t *>(ws + off_at);
+    uint32_t *kids = reinterpret_cast<uint32_t *>(ws + kids_at);
+    uint32_t *srt = reinterpret_cast<uint32_t *>(ws + srt_at);
+    uint32_t *bsum = reinterpret_cast<uint32_t *>(ws + bsum_at);
     const unsigned nb = blocks_for(N, kNodeBlock);
     const int64_t ncb = (N + kCompactNodes - 1) / kCompactNodes;
     unsigned long long *vw = reinterpret_cast<unsigned long long *>(vn);
-    const char *lists = batch ? "batch_resolve_lists" : "resolve_lists";
-    D8_LAUNCH(lists, st, (csr_count<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, indeg, bsum)));
-    D8_LAUNCH(lists, st, (adj_compact_scan<<<1, 1024, 0, st>>>(ncb, bsum, total)));
-    D8_LAUNCH(lists, st, (csr_offsets<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, indeg, bsum, off, cnt)));
-    D8_LAUNCH(lists, st, (csr_fill<<<nb, kNodeBlock, 0, st>>>(N, link, succ, off, cnt, kids)));
-    D8_LAUNCH(lists, st, (csr_sort<<<nb, kNodeBlock, 0, st>>>(N, indeg, off, kids)));
+    D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_count", st,
+              (csr_count<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, indeg, bsum)));
+    D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_scan", st,
+              (adj_compact_scan<<<1, 1024, 0, st>>>(ncb, bsum, total)));
+    D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_offsets", st,
+              (csr_offsets<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, indeg, bsum, off, cnt)));
+    D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_fill", st,
+              (csr_fill<<<nb, kNodeBlock, 0, st>>>(N, link, succ, indeg, off, cnt, kids)));
+    D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_rank", st,
+              (csr_rank<<<nb, kNodeBlock, 0, st>>>(N, link, succ, indeg, off, kids, srt)));
     D8_LAUNCH(batch ? "batch_resolve_fwd" : "resolve_fwd", st,
-              (resolve_fwd_det<float, ABS><<<nb, kNodeBlock, 0, st>>>(N, link, aloc, succ, indeg, off, kids, cnt,
+              (resolve_fwd_det<float, ABS><<<nb, kNodeBlock, 0, st>>>(N, link, aloc, succ, indeg, off, srt, cnt,
                                                                       vw, entry, anode, pathp)));
     D8_LAUNCH(batch ? "batch_resolve_check" : "resolve_check", st,
               (resolve_det_check<<<nb, kNodeBlock, 0, st>>>(N, link, cnt, status)));
@@ -338,7 +347,8 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
     uint32_t *entry = reinterpret_cast<uint32_t *>(ws + L.entry);
     uint32_t *succ = reinterpret_cast<uint32_t *>(ws + L.succ);
     uint32_t *indeg = reinterpret_cast<uint32_t *>(ws + L.indeg);
-    uint32_t *cnt = kCounts ? nullptr : reinterpret_cast<uint32_t *>(ws + L.ptr2);
+    // float weights: arrival counts; unit counts: donors of each entered node
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + L.ptr2);
     T *aloc = reinterpret_cast<T *>(ws + L.val32);
     V *acc = reinterpret_cast<V *>(ws + L.acc64);
     E *ext = reinterpret_cast<E *>(ws + L.ext64);
@@ -362,13 +372,10 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
                   (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg, acc,
                                                               ext)));
         D8_LAUNCH("resolve_check", st,
-                  (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, acc, cnt, status)));
+                  (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, acc, nullptr, status)));
     } else {
-        uint32_t *off = reinterpret_cast<uint32_t *>(ws + L.off);
-        uint32_t *kids = reinterpret_cast<uint32_t *>(ws + L.kids);
-        uint32_t *bsum = reinterpret_cast<uint32_t *>(ws + L.bsum);
-        resolve_float<false>(st, false, g.nnodes, link, aloc, succ, indeg, cnt, off, kids, bsum, jstate + 8, acc,
-                             status);
+        resolve_float<false>(st, false, g.nnodes, link, aloc, succ, indeg, cnt, ws, L.off, L.kids, L.srt, L.bsum,
+                             jstate + 8, acc, status);
         D8_LAUNCH("resolve_ext", st,
                   (resolve_ext<false><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, nullptr, 0, g.nnodes)));
     }
@@ -431,9 +438,8 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
                                                                       pathp)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, 0, g.nnodes)));
-    resolve_float<true>(st, false, g.nnodes, link, aloc, succ, indeg, cnt,
-                        reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.kids),
-                        reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8, acc, status, entry, anode, pathp);
+    resolve_float<true>(st, false, g.nnodes, link, aloc, succ, indeg, cnt, ws, L.off, L.kids, L.srt, L.bsum,
+                        jstate + 8, acc, status, entry, anode, pathp);
     D8_LAUNCH("resolve_ext", st,
               (resolve_ext<true><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, anode, 0, g.nnodes)));
     D8_LAUNCH("absorb_pass2", st,
@@ -450,7 +456,7 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
 struct BatchLayout {
     size_t status, jstate, desc, tile_dem, chunk_dem;
     size_t link, entry, succ, indeg, cnt, val32, acc64, ext64, root8, total;
-    size_t off, kids, bsum;  // the forward's children lists, over the root labels
+    size_t off, kids, srt, bsum;  // the forward's children lists, over the root labels
 };
 
 // Rasters of one tile shape: a contiguous range of the batch's tiles, run by
@@ -555,7 +561,7 @@ int make_plan(const d8_batch_item *items, int n, BatchPlan &P)
     L.acc64 = off; off = align256(off + N * sizeof(double));
     L.ext64 = off; off = align256(off + N * sizeof(double));
     L.root8 = off; off = align256(off + (size_t)P.ncells);
-    L.total = std::max(off, csr_place(L.root8, N, L.off, L.kids, L.bsum));
+    L.total = std::max(off, csr_place(L.root8, N, L.off, L.kids, L.srt, L.bsum));
     return D8_OK;
 }
 
@@ -671,9 +677,8 @@ int enqueue_batch(const BatchPlan &P, int mode, char *ws, hipStream_t st)
         D8_LAUNCH("batch_graph_build", st,
                   (graph_build_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, entry,
                                                                 succ, indeg)));
-        resolve_float<false>(st, true, N, link, val32, succ, indeg, cnt,
-                             reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.kids),
-                             reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8, acc, status);
+        resolve_float<false>(st, true, N, link, val32, succ, indeg, cnt, ws, L.off, L.kids, L.srt, L.bsum,
+                             jstate + 8, acc, status);
         D8_LAUNCH("batch_resolve_ext", st,
                   (resolve_ext_batch<<<nb, kNodeBlock, 0, st>>>(dems, ndem, chunk_dem, N, link, acc, ext)));
         if (tiles(1, fwd_walk_batch_k<2>, "batch_fwd_pass2", link, val32, indeg, cnt, acc, ext, status))
@@ -753,7 +758,9 @@ int stream_layout(int64_t rows, int64_t cols, int &th, int &tw, int64_t band_row
         S.vslot[i] = off;
         off = align256(off + (size_t)band_rows * (size_t)cols * sizeof(float));
     }
-    S.total = off;
+    // the float resolve's children lists lie over the slots (they are used
+    // between the passes only) and may reach beyond them
+    S.total = std::max(off, csr_place(S.L.root8, (size_t)g.nnodes, S.L.off, S.L.kids, S.L.srt, S.L.bsum));
     return D8_OK;
 }
 
@@ -895,7 +902,7 @@ int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h,
         else
             D8_LAUNCH("stream_fwd_pass1", st,
                       (u1<<<nt, kTileThreads, lds1, st>>>(
-                          dirs, nullptr, g, link, reinterpret_cast<uint32_t *>(ws + L.val32), indeg, nullptr,
+                          dirs, nullptr, g, link, reinterpret_cast<uint32_t *>(ws + L.val32), indeg, cnt,
                           reinterpret_cast<VU *>(ws + L.acc64), reinterpret_cast<uint32_t *>(ws + L.ext64),
                           nullptr, status, t0)));
         if (vals) (void)hipEventRecord(ev[kEvVFree + (b & 1)], st);
@@ -914,9 +921,8 @@ int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h,
                    false);
     } else if (f32) {
         resolve_float<false>(st, false, g.nnodes, link, reinterpret_cast<float *>(ws + L.val32), succ, indeg, cnt,
-                             reinterpret_cast<uint32_t *>(ws + L.off), reinterpret_cast<uint32_t *>(ws + L.kids),
-                             reinterpret_cast<uint32_t *>(ws + L.bsum), jstate + 8,
-                             reinterpret_cast<double *>(ws + L.acc64), status);
+                             ws, L.off, L.kids, L.srt, L.bsum, jstate + 8, reinterpret_cast<double *>(ws + L.acc64),
+                             status);
     } else {
         VU *acc = reinterpret_cast<VU *>(ws + L.acc64);
         D8_LAUNCH("stream_resolve", st,

@@ -280,12 +280,13 @@ __device__ inline void graph_edge(const uint8_t *__restrict__ dirs, const Geo &g
     e = s = kNone;
     int ty, tx, p, r, c;
     node_tile(g, id, ty, tx, p);
-    ring_cell(p, tile_h(g, ty), tile_w(g, tx), r, c);
+    const int h = tile_h(g, ty), w = tile_w(g, tx);
+    ring_cell(p, h, w, r, c);
     int64_t gr = (int64_t)ty * g.th + r, gc = (int64_t)tx * g.tw + c;
     int k = dirs[gr * g.cols + gc];
-    int64_t nr = gr + dir_dr(k), nc = gc + dir_dc(k);
-    int uty = (int)(nr / g.th), utx = (int)(nc / g.tw);
-    int lr = (int)(nr - (int64_t)uty * g.th), lc = (int)(nc - (int64_t)utx * g.tw);
+    // an exit's flow leaves its tile by one step (edge or corner)
+    int uty, utx, lr, lc;
+    step_tile(g, ty, tx, h, w, r + dir_dr(k), c + dir_dc(k), uty, utx, lr, lc);
     int64_t ub = node0 + node_base(g, uty, utx);
     int q = ring_index(lr, lc, tile_h(g, uty), tile_w(g, utx));  // >= 0: borders a tile edge
     int64_t n = ub + (q < 0 ? 0 : q);
@@ -765,14 +766,18 @@ __global__ void adj_jump_finish(uint32_t *state, int rounds, uint32_t *status)
 // alpha(u) V(u) times the path product of the cell it enters, and ext(n)
 // sums alpha(u) V(u).
 
-// Child counts per block of 4096 nodes.
+// Only nodes with two children or more get a list: the walker that reaches
+// a node's only child goes on without reading it.
+__device__ inline uint32_t csr_len(uint32_t k) { return k >= 2u ? k : 0u; }
+
+// Listed children per block of 4096 nodes.
 __global__ void __launch_bounds__(kCompactBlock)
 csr_count(int64_t nnodes, const uint32_t *__restrict__ indeg, uint32_t *__restrict__ bsum)
 {
     const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
     uint32_t c = 0;
     for (int j = 0; j < kCompactPer; ++j)
-        if (n0 + j < nnodes) c += indeg[n0 + j];
+        if (n0 + j < nnodes) c += csr_len(indeg[n0 + j]);
     uint32_t total;
     block_excl_scan(c, &total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
@@ -787,7 +792,7 @@ csr_offsets(int64_t nnodes, const uint32_t *__restrict__ indeg, const uint32_t *
     uint32_t v[kCompactPer], c = 0;
 #pragma unroll
     for (int j = 0; j < kCompactPer; ++j) {
-        v[j] = n0 + j < nnodes ? indeg[n0 + j] : 0u;
+        v[j] = n0 + j < nnodes ? csr_len(indeg[n0 + j]) : 0u;
         c += v[j];
     }
     uint32_t total;
@@ -802,43 +807,57 @@ csr_offsets(int64_t nnodes, const uint32_t *__restrict__ indeg, const uint32_t *
     }
 }
 
+// cnt[s] ends as s's child count (the arrivals the resolve counts down).
 __global__ void csr_fill(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_t *__restrict__ succ,
-                         const uint32_t *__restrict__ off, uint32_t *cnt, uint32_t *__restrict__ kids)
+                         const uint32_t *__restrict__ indeg, const uint32_t *__restrict__ off, uint32_t *cnt,
+                         uint32_t *__restrict__ kids)
 {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nnodes || link[id] != kLinkExt) return;
     const uint32_t s = succ[id];
     if (s == kNone) return;
+    if (indeg[s] < 2u) {
+        cnt[s] = 1u;  // the only child
+        return;
+    }
     kids[off[s] + atomicAdd(&cnt[s], 1u)] = (uint32_t)id;
 }
 
-// Each list in increasing id (insertion sort; lists are short).
-__global__ void csr_sort(int64_t nnodes, const uint32_t *__restrict__ indeg, const uint32_t *__restrict__ off,
-                         uint32_t *__restrict__ kids)
+// Each child's place in its parent's list, in increasing node id: its rank
+// among the (unordered, atomically filled) siblings in kids, written to
+// sorted.  A child reads its parent's k siblings, so the work per parent is
+// k^2 but spread over its k children (lists are short: a parent's children
+// lie on the borders of the tiles around it, at most 2 (h + w) + 4).
+__global__ void csr_rank(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_t *__restrict__ succ,
+                         const uint32_t *__restrict__ indeg, const uint32_t *__restrict__ off,
+                         const uint32_t *__restrict__ kids, uint32_t *__restrict__ sorted)
 {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nnodes) return;
-    const uint32_t k = indeg[id];
-    if (k < 2) return;
-    uint32_t *a = kids + off[id];
-    for (uint32_t i = 1; i < k; ++i) {
-        const uint32_t x = a[i];
-        uint32_t j = i;
-        while (j > 0 && a[j - 1] > x) {
-            a[j] = a[j - 1];
-            --j;
-        }
-        a[j] = x;
-    }
+    if (id >= nnodes || link[id] != kLinkExt) return;
+    const uint32_t s = succ[id];
+    if (s == kNone) return;
+    const uint32_t k = indeg[s], o = off[s], u = (uint32_t)id;
+    if (k < 2u) return;
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < k; ++i) r += kids[o + i] < u ? 1u : 0u;
+    sorted[o + r] = u;
 }
 
+// A value another lane may have written during this kernel (on any XCD).
 __device__ inline double v_read(unsigned long long *vn, uint32_t u)
 {
-    return __longlong_as_double((long long)atomicOr(&vn[u], 0ull));
+    return __longlong_as_double((long long)__hip_atomic_load(&vn[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 // Walkers from the leaves of the exit forest.  cnt holds each node's child
-// count (left by csr_fill) and is counted down by arrivals.
+// count (left by csr_fill) and is counted down by arrivals.  At a node with
+// one child the walker goes on at once (V of the child and the arrival have
+// one writer: plain stores, read by later kernels).  Otherwise it publishes
+// V(u) with an atomic exchange and counts its arrival only once the exchange
+// has returned; the last child to arrive reads its siblings' V (its own is
+// in hand), eight at a time with every load in flight together (indices
+// clamped to the list, so the loads take no branches), and adds them in list
+// order.
 template <typename T, bool ABS>
 __global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
                                 const uint32_t *__restrict__ succ, const uint32_t *__restrict__ indeg,
@@ -853,24 +872,53 @@ __global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ lin
     if (link[id] != kLinkExt || indeg[id] != 0) return;
     uint32_t u = (uint32_t)id;
     double v = (double)aloc[u];
+    uint32_t s = succ[u];
     for (;;) {
+        if (s == kNone) {
+            vn[u] = (unsigned long long)__double_as_longlong(v);  // read by a later kernel only
+            break;
+        }
+        const uint32_t k = indeg[s], o = off[s], s2 = succ[s];
+        const double as = (double)aloc[s];
+        if (k == 1u) {
+            vn[u] = (unsigned long long)__double_as_longlong(v);
+            cnt[s] = 0u;
+            v = as + (ABS ? ((double)anode[u] * v) * (double)pathp[entry[u]] : v);
+            u = s;
+            s = s2;
+            continue;
+        }
         const unsigned long long prev = atomicExch(&vn[u], (unsigned long long)__double_as_longlong(v));
-        const uint32_t s = succ[u];
-        if (s == kNone) break;
+        uint32_t c0[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c0[j] = kids[o + ((uint32_t)j < k ? (uint32_t)j : k - 1u)];
         uint32_t one = 1u;
-        asm volatile("" : "+v"(one) : "v"(prev));  // the count waits for the store
+        // the count waits for the store; the children's ids are fetched
+        // while the exchange is in flight
+        asm volatile("" : "+v"(one) : "v"(prev), "v"(c0[0]), "v"(c0[1]), "v"(c0[2]), "v"(c0[3]), "v"(c0[4]),
+                     "v"(c0[5]), "v"(c0[6]), "v"(c0[7]));
         if (atomicSub(&cnt[s], one) != 1u) break;
-        // last child to arrive: s's sum in the order of its sorted list
-        const uint32_t k = indeg[s], o = off[s];
-        double sum = (double)aloc[s];
-        for (uint32_t i = 0; i < k; ++i) {
-            const uint32_t c = kids[o + i];
-            double vc = v_read(vn, c);
-            if constexpr (ABS) vc = ((double)anode[c] * vc) * (double)pathp[entry[c]];
-            sum += vc;
+        double sum = as;
+        for (uint32_t i0 = 0; i0 < k; i0 += 8) {
+            uint32_t c[8];
+            double vc[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t i = i0 + (uint32_t)j < k ? i0 + (uint32_t)j : k - 1u;
+                c[j] = i0 == 0 ? c0[j] : kids[o + i];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) vc[j] = v_read(vn, c[j]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                double x = c[j] == u ? v : vc[j];
+                if constexpr (ABS) x = ((double)anode[c[j]] * x) * (double)pathp[entry[c[j]]];
+                sum += i0 + (uint32_t)j < k ? x : 0.0;
+            }
         }
         u = s;
         v = sum;
+        s = s2;
     }
 }
 
@@ -904,8 +952,8 @@ __device__ inline double ext_gather(const uint8_t *__restrict__ dirs, const Geo 
         const int64_t nr = gr + dir_dr(k), nc = gc + dir_dc(k);
         if (nr < 0 || nr >= g.rows || nc < 0 || nc >= g.cols) continue;
         if (dirs[nr * g.cols + nc] != (uint8_t)(7 - k)) continue;
-        const int uty = (int)(nr / g.th), utx = (int)(nc / g.tw);
-        const int ur = (int)(nr - (int64_t)uty * g.th), uc = (int)(nc - (int64_t)utx * g.tw);
+        int uty, utx, ur, uc;
+        step_tile(g, ty, tx, h, w, lr, lc, uty, utx, ur, uc);
         const int64_t u = node0 + node_base(g, uty, utx) +
                           ring_index(ur, uc, tile_h(g, uty), tile_w(g, utx));
         double vu = vn[u];  // final: written by the resolve, an earlier kernel

@@ -167,3 +167,29 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         _lib.load()
+
+
+def _nnodes(rows, cols, th, tw):
+    """Perimeter cells of all tiles (every tile's ring, edge tiles smaller)."""
+    def ring(h, w):
+        return h * w if h <= 2 or w <= 2 else 2 * (h + w) - 4
+    n = 0
+    for r0 in range(0, rows, th):
+        for c0 in range(0, cols, tw):
+            n += ring(min(th, rows - r0), min(tw, cols - c0))
+    return n
+
+
+@pytest.mark.parametrize("rows,cols,th,tw,band", [(32768, 32768, 64, 44, 1024), (4096, 4096, 16, 16, 64),
+                                                   (3000, 2000, 8, 8, 8)])
+def test_workspaces_hold_the_float_resolve_lists(rows, cols, th, tw, band):
+    """Every workspace the float forward can run in holds its per-node arrays
+    (link 2, entry/succ/indeg/counts/A_loc 4 each, two 8-byte words) and the
+    resolve's children lists (three words per node) that lie over the
+    adjoint's labels or the streamed slots."""
+    lib = _lib.load()
+    N = _nnodes(rows, cols, th, tw)
+    need = 512 + N * (2 + 5 * 4 + 2 * 8) + 3 * N * 4
+    assert lib.d8_workspace_bytes(rows, cols, th, tw) >= need
+    assert lib.d8_stream_workspace_bytes(rows, cols, th, tw, band) >= need
+    assert lib.d8_absorb_workspace_bytes(rows, cols, th, tw) >= need
