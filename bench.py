@@ -41,8 +41,8 @@ KERNEL_BYTES_PER_CELL = {
     "flow_accum_absorb_adjoint": 13.0,  # code 1 + alpha 4 + g 4 read, lambda 4 written
 }
 STEP_BYTES_PER_CELL = 14.0  # forward 1 + 4, adjoint 1 + 4 + 4
-SWEEP_TILES = ((64, 64), (64, 56), (64, 48), (64, 44), (64, 40), (64, 32), (56, 48), (48, 64), (48, 48),
-               (32, 64))
+SWEEP_TILES = ((64, 64), (64, 48), (64, 44), (64, 40), (64, 36), (64, 32), (64, 28), (60, 32), (56, 32),
+               (56, 48), (48, 48), (48, 32))
 
 
 ABSORB_TILE = (32, 48)  # the absorption entry points' default shape
