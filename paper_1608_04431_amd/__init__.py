@@ -352,9 +352,11 @@ def flow_accum_adjoint_streamed(dirs_host: torch.Tensor, grad_host: torch.Tensor
                            sync)
 
 
-def check_status(ws: Workspace) -> None:
-    """Synchronise the current stream and raise on a recorded data error."""
-    rc = _lib.load().d8_check_status(_ptr(ws.buf), _stream(ws.buf.device))
+def check_status(ws: Workspace | torch.Tensor) -> None:
+    """Synchronise the current stream and raise on a data error recorded in
+    ws (a Workspace or a workspace tensor)."""
+    buf = ws.buf if isinstance(ws, Workspace) else ws
+    rc = _lib.load().d8_check_status(_ptr(buf), _stream(buf.device))
     _lib.check(rc, "status")
 
 

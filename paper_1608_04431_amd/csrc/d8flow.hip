@@ -306,7 +306,8 @@ template <bool ABS>
 void resolve_float(hipStream_t st, bool batch, int64_t N, const uint16_t *link, const float *aloc,
                    const uint32_t *succ, const uint32_t *indeg, uint32_t *cnt, char *ws, size_t off_at,
                    size_t kids_at, size_t srt_at, size_t bsum_at, uint32_t *total, double *vn, uint32_t *status,
-                   const uint32_t *entry = nullptr, const float *anode = nullptr, const float *pathp = nullptr)
+                   const uint32_t *entry = nullptr, const float *anode = nullptr, const float *pathp = nullptr,
+                   double *coef = nullptr)
 {
     uint32_t *off = reinterpret_cast<uint32_t *>(ws + off_at);
     uint32_t *kids = reinterpret_cast<uint32_t *>(ws + kids_at);
@@ -322,14 +323,13 @@ void resolve_float(hipStream_t st, bool batch, int64_t N, const uint16_t *link, 
     D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_offsets", st,
               (csr_offsets<<<(unsigned)ncb, kCompactBlock, 0, st>>>(N, indeg, bsum, off, cnt)));
     D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_fill", st,
-              (csr_fill<<<nb, kNodeBlock, 0, st>>>(N, link, succ, indeg, off, cnt, kids)));
+              (csr_fill<ABS><<<nb, kNodeBlock, 0, st>>>(N, link, succ, indeg, off, cnt, kids, entry, anode, pathp,
+                                                        coef)));
     D8_LAUNCH(batch ? "batch_resolve_lists" : "resolve_lists_rank", st,
               (csr_rank<<<nb, kNodeBlock, 0, st>>>(N, link, succ, indeg, off, kids, srt)));
     D8_LAUNCH(batch ? "batch_resolve_fwd" : "resolve_fwd", st,
               (resolve_fwd_det<float, ABS><<<nb, kNodeBlock, 0, st>>>(N, link, aloc, succ, indeg, off, srt, cnt,
-                                                                      vw, entry, anode, pathp)));
-    D8_LAUNCH(batch ? "batch_resolve_check" : "resolve_check", st,
-              (resolve_det_check<<<nb, kNodeBlock, 0, st>>>(N, link, cnt, status)));
+                                                                      vw, coef)));
 }
 
 // Unit counts (T = uint32_t): packed 64-bit resolve state, uint32 inflows.
@@ -371,8 +371,6 @@ int run_forward(const uint8_t *dirs, const float *w, T *out, const Geo &g, char 
         D8_LAUNCH("resolve_fwd", st,
                   (resolve_fwd_u32<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, aloc, entry, succ, indeg, acc,
                                                               ext)));
-        D8_LAUNCH("resolve_check", st,
-                  (resolve_check<<<nb, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, acc, nullptr, status)));
     } else {
         resolve_float<false>(st, false, g.nnodes, link, aloc, succ, indeg, cnt, ws, L.off, L.kids, L.srt, L.bsum,
                              jstate + 8, acc, status);
@@ -438,8 +436,10 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
                                                                       pathp)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, 0, g.nnodes)));
+    // the per-exit coefficients take the adjoint's second word buffer
     resolve_float<true>(st, false, g.nnodes, link, aloc, succ, indeg, cnt, ws, L.off, L.kids, L.srt, L.bsum,
-                        jstate + 8, acc, status, entry, anode, pathp);
+                        jstate + 8, acc, status, entry, anode, pathp,
+                        reinterpret_cast<double *>(ws + A.jw));
     D8_LAUNCH("resolve_ext", st,
               (resolve_ext<true><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, anode, 0, g.nnodes)));
     D8_LAUNCH("absorb_pass2", st,
@@ -930,8 +930,6 @@ int run_streamed(int kind, const uint8_t *dirs_h, const float *v_h, void *out_h,
                                                               reinterpret_cast<uint32_t *>(ws + L.val32), entry,
                                                               succ, indeg, acc,
                                                               reinterpret_cast<uint32_t *>(ws + L.ext64))));
-        D8_LAUNCH("stream_resolve_check", st,
-                  (resolve_check<<<nbn, kNodeBlock, 0, st>>>(g.nnodes, link, indeg, acc, nullptr, status)));
     }
     // pass 2 over the bands: code, value and result slots b & 1
     (void)hipEventRecord(ev[kEvP1], st);

@@ -9,10 +9,11 @@
 //                     edge or a corner) and to that cell's exit; counts each
 //                     exit's children.
 //   resolve_fwd_*     accumulates the forest of exit cells and records each
-//                     perimeter cell's cross-tile inflow; resolve_check
-//                     reports exits whose children never all arrived.
+//                     perimeter cell's cross-tile inflow (float weights: in
+//                     a fixed order, over children lists, csr_*).
 //   fwd_walk<2>       Algorithm 1 again per tile with the inflow added to the
-//                     receiving cell's own weight (EVICT), writes A.
+//                     receiving cell's own weight (EVICT), writes A; reports
+//                     exits of its tile whose children never all arrived.
 // Adjoint (lambda = (I-P)^-T g, not in the paper):
 //   adj_walk          per tile: upstream walks give lambda_loc (the sum of g
 //                     along each cell's in-tile path) and each cell's root
@@ -377,20 +378,10 @@ __global__ void resolve_fwd_u32(int64_t nnodes, const uint16_t *__restrict__ lin
     }
 }
 
-// After the resolve: an exit whose children did not all arrive lies on, or
-// below, a cycle of exits.  Arrivals are the low word of `packed` (unit
-// counts) or `cnt` (float weights).
-__global__ void resolve_check(int64_t nnodes, const uint16_t *__restrict__ link,
-                              const uint32_t *__restrict__ indeg,
-                              const unsigned long long *__restrict__ packed,
-                              const uint32_t *__restrict__ cnt, uint32_t *status)
-{
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
-    if (id < nnodes && link[id] == kLinkExt)
-        bad = (packed ? (uint32_t)packed[id] : cnt[id]) != indeg[id];
-    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) set_status(status, kStatusCycle);
-}
+// Exits on or below a cycle of exits are never finished: their children
+// never all arrive.  Forward pass 2 checks its tile's exits (arrivals equal
+// to the child count for unit counts, a count left at zero for float
+// weights) and reports a cycle; no separate pass over the nodes is needed.
 
 // -------------------------------------------------------------- adjoint ----
 // mu(e) = lambda(entry(e)) = S(entry(e)) + mu(succ(e)): a downstream path sum
@@ -763,21 +754,45 @@ __global__ void adj_jump_finish(uint32_t *state, int rounds, uint32_t *status)
 // is summed by the child that arrives last (arrival counter counted down
 // from the child count), reading its children's V with atomics (they may
 // have been written on another XCD).  Absorption (ABS): a child u contributes
-// alpha(u) V(u) times the path product of the cell it enters, and ext(n)
-// sums alpha(u) V(u).
+// coef(u) V(u), coef(u) = alpha(u) times the path product of the cell it
+// enters, and ext(n) sums alpha(u) V(u).
 
 // Only nodes with two children or more get a list: the walker that reaches
 // a node's only child goes on without reading it.
 __device__ inline uint32_t csr_len(uint32_t k) { return k >= 2u ? k : 0u; }
+
+// A lane's kCompactPer list lengths (16-byte loads when its run of nodes is
+// whole: the node arrays start on 256-byte boundaries).
+__device__ inline void csr_lens(int64_t nnodes, int64_t n0, const uint32_t *__restrict__ indeg,
+                                uint32_t (&v)[kCompactPer])
+{
+    if (n0 + kCompactPer <= nnodes) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(indeg + n0);
+#pragma unroll
+        for (int i = 0; i < kCompactPer / 4; ++i) {
+            const uint4 x = q[i];
+            v[4 * i] = x.x;
+            v[4 * i + 1] = x.y;
+            v[4 * i + 2] = x.z;
+            v[4 * i + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kCompactPer; ++j) v[j] = n0 + j < nnodes ? indeg[n0 + j] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) v[j] = csr_len(v[j]);
+}
 
 // Listed children per block of 4096 nodes.
 __global__ void __launch_bounds__(kCompactBlock)
 csr_count(int64_t nnodes, const uint32_t *__restrict__ indeg, uint32_t *__restrict__ bsum)
 {
     const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
-    uint32_t c = 0;
-    for (int j = 0; j < kCompactPer; ++j)
-        if (n0 + j < nnodes) c += csr_len(indeg[n0 + j]);
+    uint32_t v[kCompactPer], c = 0;
+    csr_lens(nnodes, n0, indeg, v);
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) c += v[j];
     uint32_t total;
     block_excl_scan(c, &total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
@@ -790,13 +805,30 @@ csr_offsets(int64_t nnodes, const uint32_t *__restrict__ indeg, const uint32_t *
 {
     const int64_t n0 = (int64_t)blockIdx.x * kCompactNodes + (int64_t)threadIdx.x * kCompactPer;
     uint32_t v[kCompactPer], c = 0;
+    csr_lens(nnodes, n0, indeg, v);
 #pragma unroll
-    for (int j = 0; j < kCompactPer; ++j) {
-        v[j] = n0 + j < nnodes ? csr_len(indeg[n0 + j]) : 0u;
-        c += v[j];
-    }
+    for (int j = 0; j < kCompactPer; ++j) c += v[j];
     uint32_t total;
     uint32_t run = bsum[blockIdx.x] + block_excl_scan(c, &total);
+    if (n0 + kCompactPer <= nnodes) {
+        uint4 *qo = reinterpret_cast<uint4 *>(off + n0);
+        uint4 *qc = reinterpret_cast<uint4 *>(cnt + n0);
+#pragma unroll
+        for (int i = 0; i < kCompactPer / 4; ++i) {
+            uint4 o;
+            o.x = run;
+            run += v[4 * i];
+            o.y = run;
+            run += v[4 * i + 1];
+            o.z = run;
+            run += v[4 * i + 2];
+            o.w = run;
+            run += v[4 * i + 3];
+            qo[i] = o;
+            qc[i] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < kCompactPer; ++j) {
         if (n0 + j < nnodes) {
@@ -808,14 +840,21 @@ csr_offsets(int64_t nnodes, const uint32_t *__restrict__ indeg, const uint32_t *
 }
 
 // cnt[s] ends as s's child count (the arrivals the resolve counts down).
+// Absorption: coef[u] = alpha(u) times the path product of the cell u's flow
+// enters, the factor of V(u) in its parent's sum (exact in double: a product
+// of two floats).
+template <bool ABS>
 __global__ void csr_fill(int64_t nnodes, const uint16_t *__restrict__ link, const uint32_t *__restrict__ succ,
                          const uint32_t *__restrict__ indeg, const uint32_t *__restrict__ off, uint32_t *cnt,
-                         uint32_t *__restrict__ kids)
+                         uint32_t *__restrict__ kids, const uint32_t *__restrict__ entry = nullptr,
+                         const float *__restrict__ anode = nullptr, const float *__restrict__ pathp = nullptr,
+                         double *__restrict__ coef = nullptr)
 {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nnodes || link[id] != kLinkExt) return;
     const uint32_t s = succ[id];
     if (s == kNone) return;
+    if constexpr (ABS) coef[id] = (double)anode[id] * (double)pathp[entry[id]];
     if (indeg[s] < 2u) {
         cnt[s] = 1u;  // the only child
         return;
@@ -857,19 +896,13 @@ __device__ inline double v_read(unsigned long long *vn, uint32_t u)
 // has returned; the last child to arrive reads its siblings' V (its own is
 // in hand), eight at a time with every load in flight together (indices
 // clamped to the list, so the loads take no branches), and adds them in list
-// order.
+// order.  One walker from leaf id.
 template <typename T, bool ABS>
-__global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
-                                const uint32_t *__restrict__ succ, const uint32_t *__restrict__ indeg,
-                                const uint32_t *__restrict__ off, const uint32_t *__restrict__ kids,
-                                uint32_t *cnt, unsigned long long *vn,
-                                const uint32_t *__restrict__ entry = nullptr,
-                                const float *__restrict__ anode = nullptr,
-                                const float *__restrict__ pathp = nullptr)
+__device__ inline void resolve_walk(int64_t id, const T *__restrict__ aloc, const uint32_t *__restrict__ succ,
+                                        const uint32_t *__restrict__ indeg, const uint32_t *__restrict__ off,
+                                        const uint32_t *__restrict__ kids, uint32_t *cnt, unsigned long long *vn,
+                                        const double *__restrict__ coef)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nnodes) return;
-    if (link[id] != kLinkExt || indeg[id] != 0) return;
     uint32_t u = (uint32_t)id;
     double v = (double)aloc[u];
     uint32_t s = succ[u];
@@ -883,7 +916,7 @@ __global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ lin
         if (k == 1u) {
             vn[u] = (unsigned long long)__double_as_longlong(v);
             cnt[s] = 0u;
-            v = as + (ABS ? ((double)anode[u] * v) * (double)pathp[entry[u]] : v);
+            v = as + (ABS ? coef[u] * v : v);
             u = s;
             s = s2;
             continue;
@@ -912,7 +945,7 @@ __global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ lin
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 double x = c[j] == u ? v : vc[j];
-                if constexpr (ABS) x = ((double)anode[c[j]] * x) * (double)pathp[entry[c[j]]];
+                if constexpr (ABS) x = coef[c[j]] * x;
                 sum += i0 + (uint32_t)j < k ? x : 0.0;
             }
         }
@@ -922,13 +955,16 @@ __global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ lin
     }
 }
 
-// Exits whose children did not all arrive lie on or below a cycle.
-__global__ void resolve_det_check(int64_t nnodes, const uint16_t *__restrict__ link,
-                                  const uint32_t *__restrict__ cnt, uint32_t *status)
+// One lane per node; walkers start at the leaf exits.
+template <typename T, bool ABS>
+__global__ void resolve_fwd_det(int64_t nnodes, const uint16_t *__restrict__ link, const T *__restrict__ aloc,
+                                const uint32_t *__restrict__ succ, const uint32_t *__restrict__ indeg,
+                                const uint32_t *__restrict__ off, const uint32_t *__restrict__ kids,
+                                uint32_t *cnt, unsigned long long *vn, const double *__restrict__ coef = nullptr)
 {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool bad = id < nnodes && link[id] == kLinkExt && cnt[id] != 0;
-    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) set_status(status, kStatusCycle);
+    if (id >= nnodes || link[id] != kLinkExt || indeg[id] != 0) return;
+    resolve_walk<T, ABS>(id, aloc, succ, indeg, off, kids, cnt, vn, coef);
 }
 
 // ext(n) of one perimeter node (id within a raster whose nodes start at

@@ -1126,13 +1126,28 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
     if constexpr (ABS) rows_in(Tl, g, alp, alpha);
     if constexpr (PASS == 2) {
         __syncthreads();
-        // all of a lane's loads first (a ring has at most 4 x 64 cells)
+        // all of a lane's loads first (a ring has at most 4 x 64 cells),
+        // with what tells whether the tile's exits were finished by the
+        // resolve: arrivals (the low word of acc) equal to the child count
+        // for unit counts, an arrival count left at zero for float weights
+        constexpr bool kCounts = std::is_same<T, uint32_t>::value;
         E e[kRingPerLane];
+        uint32_t lk[kRingPerLane], ar[kRingPerLane], kc[kRingPerLane];
 #pragma unroll
         for (int k = 0; k < kRingPerLane; ++k) {
             const int p = lane + 64 * k;
-            e[k] = p < Tl.P ? ext[Tl.base + p] : (E)0;
+            const int64_t id = Tl.base + (p < Tl.P ? p : 0);
+            e[k] = p < Tl.P ? ext[id] : (E)0;
+            lk[k] = p < Tl.P ? link[id] : 0u;
+            if constexpr (kCounts) {
+                ar[k] = reinterpret_cast<const uint32_t *>(acc)[2 * id];
+                kc[k] = indeg[id];
+            } else {
+                ar[k] = cnt[id];
+                kc[k] = 0u;
+            }
         }
+        bool open = false;
 #pragma unroll
         for (int k = 0; k < kRingPerLane; ++k) {
             const int p = lane + 64 * k;
@@ -1140,8 +1155,10 @@ __device__ __forceinline__ void fwd_tile(const uint8_t *__restrict__ dirs, const
                 int qr, qc;
                 ring_cell(p, Tl.h, Tl.w, qr, qc);
                 avp[cidx(Tl, qr, qc)] += (VT)e[k];
+                open |= lk[k] == kLinkExt && ar[k] != kc[k];
             }
         }
+        if (__ballot(open) != 0 && lane == 0) set_status(status, kStatusCycle);
     } else {
         for (int p = lane; p < Tl.P; p += 64) ll[p] = kLlTerm;
     }

@@ -271,17 +271,23 @@ def test_data_errors_reported(d8m):
     with pytest.raises(d8m.D8Error) as e:
         d8m.check_status(ws)
     assert e.value.code == -4
-    # a two-cell cycle inside one tile, and one across a tile boundary
+    # a two-cell cycle inside one tile, and one across a tile boundary (a
+    # cycle of exits, found by forward pass 2 / the adjoint's jumps), for the
+    # unit-count, float32 and absorbing forwards and the adjoint
+    ones = np.ones((64, 64), np.float32)
     for (r, c), tile in [((10, 10), (0, 0)), ((10, 31), (32, 32))]:
         d = random_acyclic_dirs(64, 64, 32)
         d[r, c], d[r, c + 1] = 4, 3
         ws = d8m.Workspace(64, 64, tile)
-        for fn in (lambda: d8m.flow_accum(dev(d), ws=ws, tile=tile),
-                   lambda: d8m.flow_accum_adjoint(dev(d), dev(np.ones_like(d, np.float32)),
-                                                  ws=ws, tile=tile)):
+        wsa = torch.empty(d8m._lib.load().d8_absorb_workspace_bytes(64, 64, *tile), dtype=torch.uint8,
+                          device="cuda")
+        for fn, w in ((lambda: d8m.flow_accum(dev(d), ws=ws, tile=tile), ws),
+                      (lambda: d8m.flow_accum(dev(d), dev(ones), acc_type="f32", ws=ws, tile=tile), ws),
+                      (lambda: d8m.flow_accum_absorb(dev(d), dev(0.5 * ones), dev(ones), tile=tile, ws=wsa), wsa),
+                      (lambda: d8m.flow_accum_adjoint(dev(d), dev(ones), ws=ws, tile=tile), ws)):
             fn()
             with pytest.raises(d8m.D8Error) as e:
-                d8m.check_status(ws)
+                d8m.check_status(w)
             assert e.value.code == -5
     # a clean call afterwards resets the status
     d = random_acyclic_dirs(64, 64, 33)
