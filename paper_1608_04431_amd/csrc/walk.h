@@ -709,8 +709,33 @@ __device__ inline void link_walks(const WTile &Tl, const uint8_t *cb8, uint32_t 
 // Cell bytes hold donor masks until a walk reaches the cell, then its label.
 // Queue entries: index | donor mask << 13 | label << 22.  Roots that do not
 // fit the queue wait in the lanes' masks; side donors that do not fit go to
-// the pending bitmap pend (their label already in their byte; the donor mask
-// is rebuilt from the direction raster when they are queued).
+// the pending bitmap (their label already in their byte; the donor mask is
+// rebuilt from the direction raster when they are queued).  The upstream
+// walks never leave the tile, so the value slots of the frame columns are
+// free: row r's pending bits for columns 0..31 live in its slot of column
+// -1, those for columns 32..63 in its slot of column w.
+struct PendRows {
+    uint32_t *v;  // the value area, as words, indexed like the cells
+    WTile Tl;
+    __device__ uint64_t get(int r) const
+    {
+        if (r >= Tl.h) return 0;
+        const uint32_t lo = v[cidx(Tl, r, -1)];
+        const uint32_t hi = kW > 32 ? v[cidx(Tl, r, Tl.w)] : 0u;
+        return (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+    __device__ void put(int r, uint64_t m) const
+    {
+        if (r >= Tl.h) return;
+        v[cidx(Tl, r, -1)] = (uint32_t)m;
+        if (kW > 32) v[cidx(Tl, r, Tl.w)] = (uint32_t)(m >> 32);
+    }
+    __device__ void add(int r, int c) const
+    {
+        if (kW <= 32 || c < 32) atomicOr(&v[cidx(Tl, r, -1)], 1u << (c & 31));
+        else atomicOr(&v[cidx(Tl, r, Tl.w)], 1u << (c & 31));
+    }
+};
 constexpr uint32_t kLabelTerm = 254;
 constexpr uint32_t kLabelNoData = 255;
 
@@ -771,8 +796,9 @@ __device__ inline uint32_t fill_up(uint32_t *q, uint32_t cap, const WTile &Tl, c
 template <bool ABS = false>
 __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__restrict__ dirs,
                                uint8_t *cb8, float *avp, uint32_t *q, uint32_t qcap, uint64_t roots,
-                               uint64_t *pend, const uint32_t *exitbits, float *alp = nullptr)
+                               const uint32_t *exitbits, float *alp = nullptr)
 {
+    const PendRows pend{reinterpret_cast<uint32_t *>(avp), Tl};
     const int S = Tl.S;
     const int lane = lane_id();
     int visited = 0;
@@ -781,7 +807,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
         fill_up<true>(q, qcap, Tl, g, dirs, cb8, exitbits, roots));
     bool roots_left = __ballot(roots != 0) != 0;
     bool pending = false;
-    pend[lane] = 0;
+    pend.put(lane, 0);
     int cur = -1;
     uint32_t mask = 0, label = 0;
     float a = 0.0f, pp = 1.0f;
@@ -795,12 +821,11 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
                 roots_left = __ballot(roots != 0) != 0;
             } else if (pending) {
                 // queue empty: move pending side donors into it
-                uint64_t m = pend[lane];
-                pend[lane] = 0;
+                uint64_t m = pend.get(lane);
                 head = 0;
                 tail = __builtin_amdgcn_readfirstlane(
                     fill_up<false>(q, qcap, Tl, g, dirs, cb8, exitbits, m));
-                if (m != 0) pend[lane] = m;
+                pend.put(lane, m);
                 pending = __ballot(m != 0) != 0;
             } else if (idle == ~0ull) {
                 break;
@@ -878,7 +903,7 @@ __device__ inline int up_walks(const WTile &Tl, const Geo &g, const uint8_t *__r
                 } else {
                     int rr, cc;
                     idx_rc(Tl, d, rr, cc);
-                    atomicOr(reinterpret_cast<unsigned long long *>(&pend[rr]), 1ull << cc);
+                    pend.add(rr, cc);
                 }
             }
             uint32_t nb = (uint32_t)__popcll(b);
@@ -921,14 +946,14 @@ __host__ __device__ inline WLayout walk_layout(int th, int tw, int kind, int vby
     // absorption: each cell's alpha after the values, laid out like them
     L.al = L.av + ((th * S * vbytes + 15) & ~15);
     L.q = absorb ? L.al + ((th * S * 4 + 15) & ~15) : L.al;
-    // queue entries: the adjoint's queue also takes side donors as walks
-    // branch (256 keep overflow rare); forward queues hold start cells and
-    // are refilled from the lanes' masks when empty
-    L.qcap = kind == kWalkAdj1 ? 256u : 128u;
+    // queue entries: start cells (forward queues, refilled from the lanes'
+    // masks when empty) or roots and side donors as walks branch (adjoint;
+    // side donors that do not fit wait in the pending bitmap)
+    L.qcap = 128u;
     L.tail = L.q + (int)L.qcap * 4;
     int tail = 0;
     if (kind == kWalkFwd1) tail = (ring_size(th, tw) * 2 + 2 + 15) & ~15;  // links + a spare slot
-    if (kind == kWalkAdj1) tail = 64 * 8 + 32;  // pending bitmap, exit bitmap (adjoint)
+    if (kind == kWalkAdj1) tail = 32;  // exit bitmap (the pending bitmap uses the frame value slots)
     L.total = L.tail + tail;
     return L;
 }
@@ -1228,8 +1253,7 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
     float *avp = reinterpret_cast<float *>(lds8 + L.av) - Tl.S;
     float *alp = reinterpret_cast<float *>(lds8 + L.al) - Tl.S;  // ABS only
     uint32_t *q = reinterpret_cast<uint32_t *>(lds8 + L.q);
-    uint64_t *pend = reinterpret_cast<uint64_t *>(lds8 + L.tail);
-    uint32_t *exitbits = reinterpret_cast<uint32_t *>(lds8 + L.tail + 64 * 8);
+    uint32_t *exitbits = reinterpret_cast<uint32_t *>(lds8 + L.tail);
     const int lane = lane_id();
 
     Setup St = setup_tile<2, false>(dirs, g, Tl, cb8, status);
@@ -1277,7 +1301,7 @@ __device__ __forceinline__ void adj_tile(const uint8_t *__restrict__ dirs, const
         }
         __syncthreads();
     }
-    int visited = up_walks<ABS>(Tl, g, dirs, cb8, avp, q, L.qcap, St.root, pend, exitbits, alp);
+    int visited = up_walks<ABS>(Tl, g, dirs, cb8, avp, q, L.qcap, St.root, exitbits, alp);
     if (wave_sum(visited + __popcll(St.root)) != wave_sum(__popcll(St.valid)) && lane == 0)
         set_status(status, kStatusCycle);
     __syncthreads();
