@@ -159,7 +159,7 @@ thread_local int g_launch_rc = D8_OK;
 inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // Downstream sums over the exit forest: dense numbering of the exits (count,
-// scan, map), initial words, then ceil(log2 N) + 1 pointer-jumping rounds and
+// scan, map), initial words, then ceil(log3 N) + 1 pointer-jumping rounds and
 // the convergence check.  bsum takes one word per 4096 nodes, cmap one per
 // node; the sums end in jw[jstate[0]] at the exits' dense numbers.  Returns
 // the number of rounds.
@@ -190,8 +190,10 @@ int jump_exits(hipStream_t st, int64_t N, const JumpGraph &G, const uint16_t *li
     const unsigned jb = std::min<unsigned>(blocks_for(N, 2 * kNodeBlock), 4096u);
     D8_LAUNCH(JNAME("adj_jump_init"), st,
               (adj_jump_init<<<jb, kNodeBlock, 0, st>>>(nexit, inv, G, link, S, cmap, jw[0])));
+    // each round triples the path a word covers: ceil(log3 N) + 1 rounds
+    // leave every chain of an acyclic forest complete
     int rounds = 1;
-    while (((int64_t)1 << (rounds - 1)) <= N) ++rounds;
+    for (int64_t span = 1; span <= N; span *= 3) ++rounds;
     for (int r = 0; r < rounds; ++r)
         D8_LAUNCH(JNAME("adj_jump_round"), st,
                   (adj_jump_round<<<jb, kNodeBlock, 0, st>>>(nexit, jw[r & 1], jw[(r + 1) & 1], jstate, r)));
@@ -1265,7 +1267,7 @@ int flow_accum_absorb_adjoint(const uint8_t *dirs, const float *alpha, const flo
     D8_LAUNCH("absorb_jump_init", st,
               (adj_jump_init_absorb<<<jb, kNodeBlock, 0, st>>>(nexit, inv, G, link, S, P, cmap, jw[0])));
     int rounds = 1;
-    while (((int64_t)1 << (rounds - 1)) <= g.nnodes) ++rounds;
+    for (int64_t span = 1; span <= g.nnodes; span *= 3) ++rounds;
     for (int r = 0; r < rounds; ++r)
         D8_LAUNCH("absorb_jump_round", st,
                   (adj_jump_round_absorb<<<jb, kNodeBlock, 0, st>>>(nexit, jw[r & 1], jw[(r + 1) & 1], jstate,

@@ -582,13 +582,41 @@ adj_jump_init(const uint32_t *__restrict__ nexit, const uint32_t *__restrict__ i
 }
 
 // One synchronous round r over the exits (their count is *nexit): reads
-// buffer r&1, writes buffer (r+1)&1: val' = val + val[ptr], ptr' = ptr[ptr].
-// live[r%3] is set when any pointer is still live after the round; round r
-// reads live[(r-1)%3] and, if nothing was live, records the final buffer in
-// state[0] and does nothing.  live[(r+1)%3] is cleared here for the next
-// round (its previous contents were read by round r-1, which has completed).
-// A fixed grid strides over the exits, so rounds after convergence cost one
-// small launch.
+// buffer r&1, writes buffer (r+1)&1.  Each word is composed with the next two
+// along its chain, val' = val + val[ptr] + val[ptr[ptr]] and ptr' =
+// ptr[ptr[ptr]], so a round triples the stretch of path a word covers and
+// ceil(log3 N) rounds finish any chain (a word whose successor is complete
+// becomes complete).  live[r%3] is set when any pointer is still live after
+// the round; round r reads live[(r-1)%3] and, if nothing was live, records
+// the final buffer in state[0] and does nothing.  live[(r+1)%3] is cleared
+// here for the next round (its previous contents were read by round r-1,
+// which has completed).  A fixed grid strides over the exits, so rounds after
+// convergence cost one small launch.
+__device__ inline bool jump_live(uint32_t p) { return p != kNone && p != kJumpDone; }
+
+__device__ inline void jump_compose(unsigned long long *w_in, unsigned long long *__restrict__ w_out, int64_t i,
+                                    unsigned long long w, unsigned long long t, unsigned long long u, bool &alive)
+{
+    const uint32_t p = (uint32_t)w;
+    if (p == kNone) {
+        // complete since the last round: the same word, done, in both
+        // buffers (readers of w_in see the same sum either way)
+        const unsigned long long d = jump_word(kJumpDone, jump_val(w));
+        w_out[i] = d;
+        w_in[i] = d;
+    } else if (p != kJumpDone) {
+        const float s = jump_val(w) + jump_val(t);
+        if (!jump_live((uint32_t)t)) {
+            w_out[i] = jump_word(kNone, s);
+        } else {
+            uint32_t np = (uint32_t)u;
+            if (np == kJumpDone) np = kNone;
+            alive |= np != kNone;
+            w_out[i] = jump_word(np, s + jump_val(u));
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256)
 adj_jump_round(const uint32_t *__restrict__ nexit, unsigned long long *w_in,
                unsigned long long *__restrict__ w_out, uint32_t *state, int round)
@@ -612,34 +640,15 @@ adj_jump_round(const uint32_t *__restrict__ nexit, unsigned long long *w_in,
         const unsigned long long w = w_in[i];
         const unsigned long long w2 = j < E ? w_in[j] : jump_word(kJumpDone, 0.0f);
         const uint32_t p = (uint32_t)w, p2 = (uint32_t)w2;
-        const bool go = p != kNone && p != kJumpDone, go2 = p2 != kNone && p2 != kJumpDone;
-        unsigned long long t = 0, t2 = 0;
-        if (go) t = w_in[p];
-        if (go2) t2 = w_in[p2];
-        if (p == kNone) {
-            // complete since the last round: the same word, done, in both
-            // buffers (readers of w_in see the same sum either way)
-            const unsigned long long d = jump_word(kJumpDone, jump_val(w));
-            w_out[i] = d;
-            w_in[i] = d;
-        } else if (go) {
-            uint32_t np = (uint32_t)t;
-            if (np == kJumpDone) np = kNone;
-            alive |= np != kNone;
-            w_out[i] = jump_word(np, jump_val(w) + jump_val(t));
-        }
-        if (j < E) {
-            if (p2 == kNone) {
-                const unsigned long long d = jump_word(kJumpDone, jump_val(w2));
-                w_out[j] = d;
-                w_in[j] = d;
-            } else if (go2) {
-                uint32_t np = (uint32_t)t2;
-                if (np == kJumpDone) np = kNone;
-                alive |= np != kNone;
-                w_out[j] = jump_word(np, jump_val(w2) + jump_val(t2));
-            }
-        }
+        unsigned long long t = jump_word(kNone, 0.0f), t2 = jump_word(kNone, 0.0f);
+        if (jump_live(p)) t = w_in[p];
+        if (jump_live(p2)) t2 = w_in[p2];
+        const uint32_t q = (uint32_t)t, q2 = (uint32_t)t2;
+        unsigned long long u = 0, u2 = 0;
+        if (jump_live(p) && jump_live(q)) u = w_in[q];
+        if (jump_live(p2) && jump_live(q2)) u2 = w_in[q2];
+        jump_compose(w_in, w_out, i, w, t, u, alive);
+        if (j < E) jump_compose(w_in, w_out, j, w2, t2, u2, alive);
     }
     if (__ballot(alive) != 0 && (threadIdx.x & 63) == 0) live[round % 3] = 1;
 }
@@ -647,8 +656,9 @@ adj_jump_round(const uint32_t *__restrict__ nexit, unsigned long long *w_in,
 // With absorption, mu(e) = S(entry(e)) + P(entry(e)) mu(succ(e)): an affine
 // chain.  Words of 16 bytes: pointer, sum a and product b, with
 // mu(e) = a + b mu(pointer); a round composes a word with its pointer's
-// word, (a, b) o (a', b') = (a + b a', b b').  Same conventions as above
-// (kNone: complete; kJumpDone: complete in both buffers).
+// word, (a, b) o (a', b') = (a + b a', b b'), here with the next two words.
+// Same conventions as above (kNone: complete; kJumpDone: complete in both
+// buffers).
 __global__ void __launch_bounds__(256)
 adj_jump_init_absorb(const uint32_t *__restrict__ nexit, const uint32_t *__restrict__ inv,
                      JumpGraph G, const uint16_t *__restrict__ link, const float *__restrict__ S,
@@ -684,6 +694,8 @@ adj_jump_round_absorb(const uint32_t *__restrict__ nexit, uint4 *w_in, uint4 *__
     if (id0 == 0) live[(round + 1) % 3] = 0;
     bool alive = false;
     for (int64_t i = id0; i < E; i += stride) {
+        // composed with the next two words, as in adj_jump_round:
+        // (a, b) o (a2, b2) o (a3, b3), left to right
         const uint4 w = w_in[i];
         const uint32_t p = w.x;
         if (p == kNone) {
@@ -692,12 +704,19 @@ adj_jump_round_absorb(const uint32_t *__restrict__ nexit, uint4 *w_in, uint4 *__
             w_in[i] = d;
         } else if (p != kJumpDone) {
             const uint4 t = w_in[p];
-            uint32_t np = t.x;
-            if (np == kJumpDone) np = kNone;
-            alive |= np != kNone;
+            const bool more = jump_live(t.x);
+            const uint4 u = more ? w_in[t.x] : make_uint4(kNone, 0u, 0u, 0u);
             const float a = __uint_as_float(w.y), b = __uint_as_float(w.z);
             const float a2 = __uint_as_float(t.y), b2 = __uint_as_float(t.z);
-            w_out[i] = make_uint4(np, __float_as_uint(a + b * a2), __float_as_uint(b * b2), 0u);
+            float na = a + b * a2, nb = b * b2;
+            uint32_t np = kNone;
+            if (more) {
+                np = u.x == kJumpDone ? kNone : u.x;
+                na = na + nb * __uint_as_float(u.y);
+                nb = nb * __uint_as_float(u.z);
+            }
+            alive |= np != kNone;
+            w_out[i] = make_uint4(np, __float_as_uint(na), __float_as_uint(nb), 0u);
         }
     }
     if (__ballot(alive) != 0 && (threadIdx.x & 63) == 0) live[round % 3] = 1;
