@@ -262,6 +262,30 @@ def test_adjoint_unit_cotangent_catchment(d8m):
     assert lam.sum() == A[r, c]
 
 
+@pytest.mark.parametrize("length", [2186, 2187, 2188, 6562])
+def test_long_chain_of_exits(d8m, length):
+    """One row flowing east with 1x1 tiles: every cell is a tile and its
+    exit, so the exit forest is a single chain of `length` nodes (the flow
+    leaves the raster at the east end).  Lengths around powers of three
+    check the pointer-jumping round count (each round composes three words)
+    and that a complete chain raises no cycle; forward counts are exact, the
+    float forward and the adjoint (plain and absorbing) follow the oracle."""
+    d = np.full((1, length), 4, dtype=np.uint8)  # code 4 = E
+    tile = (1, 1)
+    A = d8m.flow_accum(dev(d), acc_type="u32", tile=tile, check=True).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(A[0].astype(np.int64), np.arange(1, length + 1))
+    w = synth.uniform(d.shape, 41)
+    g = synth.uniform(d.shape, 42)
+    valid = np.ones(d.shape, bool)
+    Af = d8m.flow_accum(dev(d), dev(w), acc_type="f32", tile=tile, check=True).cpu().numpy()
+    assert_rel(Af, oracle.accum_f64(d, w), valid, what="f32 forward")
+    lam = d8m.flow_accum_adjoint(dev(d), dev(g), tile=tile, check=True).cpu().numpy()
+    assert_rel(lam, oracle.transpose_f64(d, g), valid, what="adjoint")
+    alpha = np.full(d.shape, 0.999, dtype=np.float32)
+    lam_a = d8m.flow_accum_absorb_adjoint(dev(d), dev(alpha), dev(g), tile=tile, check=True).cpu().numpy()
+    assert_rel(lam_a, oracle.transpose_absorb_f64(d, alpha, g), valid, what="absorbing adjoint")
+
+
 # ----------------------------------------------------------------- errors ----
 def test_data_errors_reported(d8m):
     d = random_acyclic_dirs(64, 64, 31)
