@@ -23,7 +23,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 PACKAGED = os.path.join(HERE, "tiles_mi355x.json")
 DEFAULT_TILE = (64, 64)
-CANDIDATES = ((64, 64), (64, 32), (32, 64), (64, 48), (48, 64), (32, 32))
+CANDIDATES = ((64, 64), (64, 44), (64, 40), (64, 32), (32, 64), (64, 48), (48, 64), (32, 32))
 
 
 def size_class(rows: int, cols: int) -> str:
