@@ -1408,12 +1408,31 @@ __device__ __forceinline__ void adj_finish_tile(const Geo &g, int64_t node0, int
         }
         return;
     }
-    const int c = lane;
-    if (c >= Tl.w) return;
-    for (int r = 0; r < Tl.h; ++r) {
-        const int64_t o = (Tl.r0 + r) * g.cols + Tl.c0 + c;
-        const uint32_t l = root8[o];
-        if (l < kLabelTerm) out[o] += ABS ? pcell[o] * mu_l[l] : mu_l[l];
+    // scalar path: the tile's cells in row-major order, lane + 64 k, 16 per
+    // lane at a time with every load issued before use (row = j / w by a
+    // scaled reciprocal, exact for j < 4096 and w <= 64)
+    const int n = Tl.h * Tl.w;
+    const uint32_t invw = ((1u << 20) + (uint32_t)Tl.w - 1u) / (uint32_t)Tl.w;
+    for (int j0 = 0; j0 < n; j0 += 64 * 16) {
+        int64_t o[16];
+        uint32_t l[16];
+        float x[16], pc[ABS ? 16 : 1];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int j = j0 + lane + 64 * k;
+            l[k] = kLabelTerm;
+            o[k] = 0;
+            if (j < n) {
+                const int r = (int)(((uint64_t)(uint32_t)j * invw) >> 20), c = j - r * Tl.w;
+                o[k] = (Tl.r0 + r) * g.cols + Tl.c0 + c;
+                l[k] = root8[o[k]];
+                x[k] = out[o[k]];
+                if constexpr (ABS) pc[k] = pcell[o[k]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (l[k] < kLabelTerm) out[o[k]] = x[k] + (ABS ? pc[k] * mu_l[l[k]] : mu_l[l[k]]);
     }
 }
 
