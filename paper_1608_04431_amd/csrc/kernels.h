@@ -897,7 +897,15 @@ __global__ void csr_rank(int64_t nnodes, const uint16_t *__restrict__ link, cons
     const uint32_t k = indeg[s], o = off[s], u = (uint32_t)id;
     if (k < 2u) return;
     uint32_t r = 0;
-    for (uint32_t i = 0; i < k; ++i) r += kids[o + i] < u ? 1u : 0u;
+    for (uint32_t i0 = 0; i0 < k; i0 += 8) {
+        // eight siblings with their loads in flight together (indices clamped
+        // to the list; the clamped copies are not counted)
+        uint32_t c[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c[j] = kids[o + (i0 + (uint32_t)j < k ? i0 + (uint32_t)j : k - 1u)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r += (i0 + (uint32_t)j < k && c[j] < u) ? 1u : 0u;
+    }
     sorted[o + r] = u;
 }
 
