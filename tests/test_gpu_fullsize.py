@@ -108,10 +108,17 @@ def test_dem32768_full_size(d8m, c3):
     As = d8m.flow_accum_streamed(dirs_h, tile=tile_f)
     assert torch.equal(As, A.cpu())
     del As
-    Ls = d8m.flow_accum_adjoint_streamed(dirs_h, g.cpu().pin_memory(), tile=tile_a).double()
+    g_h = g.cpu().pin_memory()
+    Ls = d8m.flow_accum_adjoint_streamed(dirs_h, g_h, tile=tile_a).double()
     Lm = lam.cpu().double()
     assert float(((Ls - Lm).abs() / Lm.abs().clamp_min(1e-30)).max()) <= 1e-5
-    del Ls, Lm, dirs_h
+    del Ls, Lm
+    # the float32 weighted forward (weights = the cotangent raster): the
+    # streamed call equals the in-memory one bit for bit (fixed-order sums)
+    Af = d8m.flow_accum(dirs, g, acc_type="f32", tile=tile_f)
+    Afs = d8m.flow_accum_streamed_f32(dirs_h, g_h, tile=tile_f)
+    assert torch.equal(Afs, Af.cpu())
+    del Af, Afs, g_h, dirs_h
 
     recv = receivers(dirs)
     data = dirs.view(-1) != 9
