@@ -160,10 +160,13 @@ def accum_f64(dirs: np.ndarray, w: np.ndarray | None = None, want_order: bool = 
     return (A, order[: n.value]) if want_order else A
 
 
-def accum_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, w: np.ndarray | None = None) -> np.ndarray:
-    """Eq. (1) with absorption: A(p) = w(p) + sum over donors n of alpha(n) A(n)."""
+def accum_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, w: np.ndarray | None = None,
+                     order: np.ndarray | None = None) -> np.ndarray:
+    """Eq. (1) with absorption: A(p) = w(p) + sum over donors n of alpha(n) A(n).
+    `order` is accum_u64's Kahn order of the same directions, if at hand."""
     dirs = _dirs(dirs)
-    _, order = accum_u64(dirs, want_order=True)
+    if order is None:
+        _, order = accum_u64(dirs, want_order=True)
     alpha = np.ascontiguousarray(alpha, dtype=np.float32)
     if w is not None:
         w = np.ascontiguousarray(w, dtype=np.float32)
@@ -174,10 +177,13 @@ def accum_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, w: np.ndarray | None =
     return A
 
 
-def transpose_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, g: np.ndarray) -> np.ndarray:
-    """lambda(c) = g(c) + alpha(c) lambda(receiver(c)) (the transpose of accum_absorb_f64)."""
+def transpose_absorb_f64(dirs: np.ndarray, alpha: np.ndarray, g: np.ndarray,
+                         order: np.ndarray | None = None) -> np.ndarray:
+    """lambda(c) = g(c) + alpha(c) lambda(receiver(c)) (the transpose of accum_absorb_f64).
+    `order` is accum_u64's Kahn order of the same directions, if at hand."""
     dirs = _dirs(dirs)
-    _, order = accum_u64(dirs, want_order=True)
+    if order is None:
+        _, order = accum_u64(dirs, want_order=True)
     alpha = np.ascontiguousarray(alpha, dtype=np.float32)
     g = np.ascontiguousarray(g, dtype=np.float32)
     lam = np.empty(dirs.shape, dtype=np.float64)

@@ -57,24 +57,35 @@ def dem32768():
 def c3(d8m, dem32768):
     """The GPU's D8 codes of the 32768^2 workload and the oracle's, and the
     oracle's unit counts (with their Kahn order) and transpose with the
-    benchmark's cotangent, computed on host threads while the GPU tests run
-    (the oracle is serial C; the threads only overlap its calls)."""
+    benchmark's cotangent, then its absorbing forward and transpose (alpha
+    ~ U[0.5, 1), the cotangent raster as weights and as cotangent) on the
+    same order, computed on a host thread while the GPU tests run (the
+    oracle is serial C; the thread only overlaps its calls)."""
     wl = synth.WORKLOADS["dem32768"]
     z = dem32768
     pool = ThreadPoolExecutor(max_workers=1)
     d_ref_f = pool.submit(oracle.d8, z)
     dirs = d8m.d8_directions(torch.from_numpy(z).cuda())
     g_host = synth.uniform(z.shape, wl["seed_g"])
+    alpha_host = (0.5 + 0.5 * synth.uniform(z.shape, wl["seed_g"] + 1)).astype(np.float32)
     d_ref = d_ref_f.result()
+    kahn = {}
 
     def solve():
-        A, order = oracle.accum_u64(d_ref, want_order=True)
-        lam = oracle.transpose_f64(d_ref, g_host, order)
-        del order
+        A, kahn["order"] = oracle.accum_u64(d_ref, want_order=True)
+        lam = oracle.transpose_f64(d_ref, g_host, kahn["order"])
+        return A, lam
+
+    def solve_absorb():
+        order = kahn.pop("order")
+        A = oracle.accum_absorb_f64(d_ref, alpha_host, g_host, order=order)
+        lam = oracle.transpose_absorb_f64(d_ref, alpha_host, g_host, order=order)
         return A, lam
 
     ref_f = pool.submit(solve)
-    yield dict(dirs=dirs, d_ref=d_ref, g_host=g_host, ref=ref_f)
+    ref_absorb_f = pool.submit(solve_absorb)
+    yield dict(dirs=dirs, d_ref=d_ref, g_host=g_host, alpha_host=alpha_host, ref=ref_f,
+               ref_absorb=ref_absorb_f)
     pool.shutdown(wait=True)
 
 
@@ -162,19 +173,20 @@ def test_dem32768_full_size(d8m, c3):
     assert (L_host.ravel()[zero] == 0).all() and (L_host.ravel()[~valid] == 0).all()
 
 
-def test_dem32768_absorb_full_size(d8m, dem32768):
+@pytest.mark.timeout(900)
+def test_dem32768_absorb_full_size(d8m, c3):
     """Absorption at full size in the benchmark's configuration (32 x 48 tiles,
     alpha ~ U[0.5, 1), U[0, 1) weights and cotangents): local balance
     A(c) = w(c) + sum of alpha(n) A(n) over c's donors and the recurrence
     lambda(c) = g(c) + alpha(c) lambda(receiver) at every cell (float32
     tolerance, as for the plain path), the alpha gradient A(n) lambda(receiver)
-    bit for bit, and sampled cells against the oracle's per-cell definitions."""
-    wl = synth.WORKLOADS["dem32768"]
-    rows, cols = dem32768.shape
-    dirs = d8m.d8_directions(torch.from_numpy(dem32768).cuda())
+    bit for bit, sampled cells against the oracle's per-cell definitions, and
+    every cell against the oracle's Kahn-order absorbing forward and its
+    transpose (computed on a host thread meanwhile) within 1e-4 relative."""
+    dirs = c3["dirs"]
+    rows, cols = dirs.shape
     tile = (32, 48)
-    w_host = synth.uniform((rows, cols), wl["seed_g"])
-    alpha_host = (0.5 + 0.5 * synth.uniform((rows, cols), wl["seed_g"] + 1)).astype(np.float32)
+    w_host, alpha_host, d_host = c3["g_host"], c3["alpha_host"], c3["d_ref"]
     w, alpha = torch.from_numpy(w_host).cuda(), torch.from_numpy(alpha_host).cuda()
     A = d8m.flow_accum_absorb(dirs, alpha, w, tile=tile)
     lam = d8m.flow_accum_absorb_adjoint(dirs, alpha, w, tile=tile)
@@ -211,7 +223,6 @@ def test_dem32768_absorb_full_size(d8m, dem32768):
     gen = torch.Generator(device="cuda").manual_seed(12)
     cand = torch.randint(0, rows * cols, (4096,), device="cuda", generator=gen)
     picks = cand[data[cand]][:30].tolist()
-    d_host = dirs.cpu().numpy()
     A_host, L_host = A.cpu().numpy(), lam.cpu().numpy()
     for i in picks:
         r, c = divmod(int(i), cols)
@@ -219,3 +230,17 @@ def test_dem32768_absorb_full_size(d8m, dem32768):
         assert abs(A_host[r, c] - want) <= 1e-4 * max(want, 1e-6), (r, c, A_host[r, c], want)
         want = oracle.downstream_sum_absorb(d_host, r, c, w_host, alpha_host)
         assert abs(L_host[r, c] - want) <= 1e-4 * max(want, 1e-6), (r, c, L_host[r, c], want)
+    del A, lam, w, alpha, dirs, recv, data, has
+
+    # every cell against the oracle (weights and cotangents in [0, 1), so
+    # both results are >= 0 and zero exactly where the oracle's are)
+    A_ref, lam_ref = c3["ref_absorb"].result()
+    valid = d_host.ravel() != 9
+    for got, want_all, name in ((A_host, A_ref, "forward"), (L_host, lam_ref, "adjoint")):
+        got, want_all = got.ravel(), want_all.ravel()
+        pos = valid & (want_all > 0)
+        rel = np.abs(got[pos].astype(np.float64) - want_all[pos]) / want_all[pos]
+        assert rel.max() <= 1e-4, f"{name} max rel err {rel.max():.3e}"
+        zero = valid & (want_all == 0)
+        assert (got[zero] == 0).all() and (got[~valid] == 0).all(), name
+        del rel, pos, zero
