@@ -56,171 +56,261 @@ __global__ void fill_u32(uint32_t *p, uint32_t v, int64_t n)
 // Steepest descent (O'Callaghan and Mark, the rule the paper takes as given):
 // among the in-grid data neighbours strictly lower than the cell, the one with
 // the largest drop per unit distance, the lowest code on ties; none -> NoFlow.
-// The drop is one float32 subtraction; distances 1 and sqrt 2 are compared
-// exactly in double as 2 d_card^2 against d_diag^2 (a float32 squared fits a
-// double).  The best cardinal and the best diagonal are found by float
-// compares of the drops (the key is monotone in the drop), then one double
-// compare picks between them.
+// The drop is one float32 subtraction.  The best cardinal drop bc and the best
+// diagonal drop bd come from float maxima and compares (the key is monotone in
+// the drop); between them the diagonal wins when bd exceeds bc times its
+// distance (sqrt 2 for D8, t = fl32(2 - r) for rho8), compared exactly in
+// double (2 bc^2 against bd^2, or bc t against bd).  A float product decides
+// first: bc * fl32(sqrt 2) is within 2^-23 of bc sqrt 2 and bc * t within 2^-24
+// of bc t, so a margin of 2^-20 (plus the smallest normal float, which keeps
+// underflowed products out) makes the float verdict the exact one; the rare
+// cells inside the margin, and those with no lower neighbour or no data, take
+// the exact compare.
+//
+// Shared drops: fl(a - b) = -fl(b - a), so the drops of a cell toward its N,
+// NW, NE and W neighbours are the negated S, SE, SW and E drops of cells
+// already done (the row above, the cell to the left).  A row of 4 cells needs
+// 19 subtractions instead of 32; the maxima take the negation as an operand
+// modifier.
 //
 // Layout: a block of 256 lanes covers 1024 columns (4 consecutive cells per
-// lane) and walks a strip of kD8Rows rows top to bottom, keeping the rows
-// above, at and below the current one in registers, so every elevation is read
-// from HBM once (plus one halo row per strip edge).  Column neighbours come
-// from the adjacent lane (shuffle) or, at a wavefront's edge, one extra load
-// of a uniform address.  NoData and off-grid neighbours are NaN, which no
-// compare selects.  VEC: rows start 16-byte aligned (cols % 4 == 0 and an
-// aligned dem), so a lane moves its 4 cells with one 16-byte load and one
-// 4-byte store; otherwise per element.  Blocks are mapped XCD-contiguously so
-// vertically and horizontally adjacent blocks share an L2.
+// lane) and walks a strip of kD8Rows rows top to bottom.  Every elevation is
+// read from HBM once (plus one halo row per strip edge); two rows of loads are
+// in flight.  The row loop is unrolled by 6 so that the 3 rows of elevations
+// and the 2 load buffers and 2 sets of shared drops change roles without
+// register copies.  Column neighbours come from the adjacent lane (a
+// wavefront-wide DPP shift) or, at a wavefront's edge, one extra load of a
+// uniform address.  NoData, off-grid and missing cells are NaN, which no
+// maximum selects and no compare matches.  VEC: rows start 16-byte aligned
+// (cols % 4 == 0 and an aligned dem), so a lane moves its 4 cells with one
+// 16-byte load and one 4-byte store; otherwise per element.  Blocks are mapped
+// XCD-contiguously so vertically and horizontally adjacent blocks share an L2.
 constexpr int kD8Threads = 256;
 constexpr int kD8Cols = 4 * kD8Threads;
 constexpr int kD8Rows = 64;
+constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i + 1
+constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i - 1
 
-struct D8Row {
-    float v[4];  // cells c0 .. c0+3
-    float l, r;  // cells c0-1 and c0+4
+// A row as loaded: the lane's 4 cells, the halo cells left of lane 0 and right
+// of lane 63 (the same address in every lane), and whether the row is inside
+// the raster.
+struct D8Raw {
+    float4 q;
+    float hl, hr;
 };
 
-__device__ inline float d8_z(float z, float nodata)
-{
-    return z == nodata ? __builtin_nanf("") : z;
-}
+// A row ready for the stencil: NoData and off-grid cells NaN; l and r the cells
+// left of v[0] and right of v[3].
+struct D8Row {
+    float v[4];
+    float l, r;
+};
+
+// The drops of a row's 4 cells toward the row below: S, SE, SW.
+struct D8Down {
+    float s[4], se[4], sw[4];
+};
+
+// Rows are addressed relative to the strip's first row r0 (k = r - r0 in
+// -1 .. kD8Rows + 2), so that the range checks are 32-bit scalar compares.
+struct D8Lane {
+    int64_t rows, cols, r0, c0, cw;  // cw: first column of the lane's wavefront
+    int nrem;                        // rows r0 .. r0 + nrem - 1 exist (capped)
+    bool above;                      // row r0 - 1 exists
+    bool rvalid;                     // the cell right of v[3] is in the raster
+    __device__ bool row_in(int k) const { return (k >= 0 || above) && k < nrem; }
+    __device__ int64_t row_clamped(int k) const
+    {
+        return k < 0 ? (above ? r0 - 1 : r0) : (k < nrem ? r0 + k : r0 + nrem - 1);
+    }
+};
 
 template <bool VEC>
-__device__ inline void d8_row_load(const float *__restrict__ dem, int64_t rows, int64_t cols,
-                                   int64_t r, int64_t c0, float4 &q, float &hl, float &hr)
+__device__ inline D8Raw d8_load(const float *__restrict__ dem, const D8Lane &L, int k)
 {
     const float nan = __builtin_nanf("");
-    q = make_float4(nan, nan, nan, nan);
-    hl = hr = nan;
-    if (r < 0 || r >= rows) return;
-    const float *p = dem + r * cols;
+    const float *p = dem + L.row_clamped(k) * L.cols;  // in bounds; rows outside mapped below
+    D8Raw o;
     if constexpr (VEC) {
-        if (c0 < cols) q = *reinterpret_cast<const float4 *>(p + c0);
+        // lanes past the raster read its last 4 cells: nothing uses their values
+        const int64_t cc = L.c0 < L.cols ? L.c0 : L.cols - 4;
+        o.q = *reinterpret_cast<const float4 *>(p + cc);
     } else {
-        if (c0 < cols) q.x = p[c0];
-        if (c0 + 1 < cols) q.y = p[c0 + 1];
-        if (c0 + 2 < cols) q.z = p[c0 + 2];
-        if (c0 + 3 < cols) q.w = p[c0 + 3];
+        o.q = make_float4(nan, nan, nan, nan);
+        if (L.c0 < L.cols) o.q.x = p[L.c0];
+        if (L.c0 + 1 < L.cols) o.q.y = p[L.c0 + 1];
+        if (L.c0 + 2 < L.cols) o.q.z = p[L.c0 + 2];
+        if (L.c0 + 3 < L.cols) o.q.w = p[L.c0 + 3];
     }
-    // halo of the wavefront: the same address in every lane
-    const int64_t cw = c0 - 4 * (threadIdx.x & 63);
-    if (cw > 0 && cw <= cols) hl = p[cw - 1];
-    if (cw + 256 < cols) hr = p[cw + 256];
-}
-
-__device__ inline D8Row d8_row_finish(float4 q, float hl, float hr, float nodata)
-{
-    D8Row o;
-    o.v[0] = d8_z(q.x, nodata);
-    o.v[1] = d8_z(q.y, nodata);
-    o.v[2] = d8_z(q.z, nodata);
-    o.v[3] = d8_z(q.w, nodata);
-    const int lane = threadIdx.x & 63;
-    const float l = __shfl_up(o.v[3], 1, 64), r = __shfl_down(o.v[0], 1, 64);
-    o.l = lane == 0 ? d8_z(hl, nodata) : l;
-    o.r = lane == 63 ? d8_z(hr, nodata) : r;
+    o.hl = p[L.cw > 0 ? (L.cw - 1 < L.cols ? L.cw - 1 : L.cols - 1) : 0];
+    o.hr = p[L.cw + 256 < L.cols ? L.cw + 256 : L.cols - 1];
     return o;
 }
 
-__device__ inline float d8_at(const D8Row &row, int i)  // i in -1 .. 4
+// NoData (and rows outside the raster) to NaN, and the neighbours across lanes.
+__device__ inline D8Row d8_finish(const D8Raw &a, const D8Lane &L, int k, float nodata)
 {
-    return i < 0 ? row.l : (i > 3 ? row.r : row.v[i]);
+    const float nan = __builtin_nanf("");
+    const bool rin = L.row_in(k);  // uniform
+    D8Row o;
+    o.v[0] = rin && a.q.x != nodata ? a.q.x : nan;
+    o.v[1] = rin && a.q.y != nodata ? a.q.y : nan;
+    o.v[2] = rin && a.q.z != nodata ? a.q.z : nan;
+    o.v[3] = rin && a.q.w != nodata ? a.q.w : nan;
+    const float hl = rin && L.cw > 0 && a.hl != nodata ? a.hl : nan;
+    const float hr = rin && L.cw + 256 < L.cols && a.hr != nodata ? a.hr : nan;
+    o.l = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, hl),
+                                                                __builtin_bit_cast(int, o.v[3]),
+                                                                kDppWaveShr1, 0xF, 0xF, false));
+    const float rr = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, hr),
+                                                                           __builtin_bit_cast(int, o.v[0]),
+                                                                           kDppWaveShl1, 0xF, 0xF, false));
+    o.r = L.rvalid ? rr : nan;
+    return o;
 }
 
-// The largest strictly positive drop among four neighbours (0 when there is
-// none) and the lowest code that has it.  A NaN drop (NoData or off-grid
-// neighbour) is skipped by the maximum (IEEE maxNum) and equals nothing.
-__device__ inline float d8_best4(float zc, float z0, float z1, float z2, float z3, int k0, int k1, int k2,
-                                 int k3, int &code)
+// The drops of `mid` toward `dn` (S, SE, SW).
+__device__ inline D8Down d8_down(const D8Row &mid, const D8Row &dn)
 {
-    const float d0 = __fsub_rn(zc, z0), d1 = __fsub_rn(zc, z1);
-    const float d2 = __fsub_rn(zc, z2), d3 = __fsub_rn(zc, z3);
-    const float m = fmaxf(fmaxf(fmaxf(0.0f, d0), d1), fmaxf(d2, d3));
-    // selects from the last to the first (no branches)
-    int k = k3;
-    k = d2 == m ? k2 : k;
-    k = d1 == m ? k1 : k;
-    k = d0 == m ? k0 : k;
-    code = k;
+    D8Down d;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        d.s[i] = __fsub_rn(mid.v[i], dn.v[i]);
+        d.se[i] = __fsub_rn(mid.v[i], i < 3 ? dn.v[i + 1] : dn.r);
+        d.sw[i] = __fsub_rn(mid.v[i], i > 0 ? dn.v[i - 1] : dn.l);
+    }
+    return d;
+}
+
+// max(0, +-a, +-b) and max(m, a, b) on the VALU's IEEE maximum, which ignores
+// a quiet NaN operand.  Every operand is a difference (so any NaN is quiet) or
+// an earlier maximum; written out so that the compiler neither re-quiets the
+// operands nor spends an instruction on a negation.
+template <bool NA, bool NB>
+__device__ inline float d8_max0(float a, float b)
+{
+    float m;
+    if constexpr (NA && NB)
+        asm("v_max3_f32 %0, 0, -%1, -%2" : "=v"(m) : "v"(a), "v"(b));
+    else if constexpr (NA)
+        asm("v_max3_f32 %0, 0, -%1, %2" : "=v"(m) : "v"(a), "v"(b));
+    else if constexpr (NB)
+        asm("v_max3_f32 %0, 0, %1, -%2" : "=v"(m) : "v"(a), "v"(b));
+    else
+        asm("v_max3_f32 %0, 0, %1, %2" : "=v"(m) : "v"(a), "v"(b));
     return m;
 }
 
-// Cardinal (best drop bc, code kc) against diagonal (bd, kd): the diagonal
-// wins when bd / s > bc with s its distance (sqrt 2 for D8: bd^2 > 2 bc^2;
-// t = fl32(2 - r) for rho8: bd > bc t); equal slopes keep the lower code.
-// The float products decide when both are normal numbers (or infinite) and
-// differ by more than their rounding (each is within 2^-23 of its exact
-// value; the margin is 2^-20); otherwise, rarely, the exact double compare.
+__device__ inline float d8_max(float m, float a, float b)
+{
+    float o;
+    asm("v_max3_f32 %0, %1, %2, %3" : "=v"(o) : "v"(m), "v"(a), "v"(b));
+    return o;
+}
+
+// The exact choice (rare): no data, no lower neighbour, or slopes within the
+// float margin.  Equal slopes keep the lower code (possible for rho8 only).
 template <bool RHO>
-__device__ inline int d8_pick(float bc, int kc, float bd, int kd, float t)
+__device__ inline int d8_pick_exact(float zc, float bc, int kc, float bd, int kd, float t)
+{
+    if (zc != zc) return kNoData;
+    if (!(bc > 0.0f) && !(bd > 0.0f)) return kNoFlow;
+    const double dc = bc, dd = bd;
+    const double keyc = RHO ? dc * (double)t : 2.0 * (dc * dc);
+    const double keyd = RHO ? dd : dd * dd;
+    return keyd > keyc ? kd : (keyc > keyd ? kc : (kc < kd ? kc : kd));
+}
+
+// Codes of the lane's 4 cells in row `mid`: `up` gives only its halo cells
+// (l, r), `in` the drops of the row above toward `mid`, `out` receives mid's
+// drops toward `dn`.  t: rho8's diagonal distances (RHO only).
+template <bool RHO>
+__device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8Row &dn, const D8Down &in,
+                                     D8Down &out, float4 t)
 {
     constexpr float kUp = 1.0f + 0x1p-20f;
     constexpr float kMin = 0x1p-126f;  // smallest normal float
-    const bool cpos = bc > 0.0f, dpos = bd > 0.0f;
-    const float x = RHO ? bd : bd * bd;
-    const float y = RHO ? bc * t : 2.0f * (bc * bc);
-    const bool normal = x >= kMin && y >= kMin;
-    const bool dwin = normal && x > y * kUp, cwin = normal && y > x * kUp;
-    // straight-line selects; the exact compare only where the floats cannot decide
-    int code = cwin ? kc : kd;
-    code = cpos ? code : kd;
-    code = dpos ? code : (cpos ? kc : kNoFlow);
-    if (cpos && dpos && !dwin && !cwin) {
-        const double dc = bc, dd = bd;
-        const double keyc = RHO ? dc * (double)t : 2.0 * (dc * dc);
-        const double keyd = RHO ? dd : dd * dd;
-        code = keyd > keyc ? kd : (keyc > keyd ? kc : (kc < kd ? kc : kd));
-    }
-    return code;
-}
-
-// RHO: rho8 (Fairfield and Leymarie) -- the diagonal distance of cell i is
-// t[i] = fl32(2 - r) for its random r in [0, 1) instead of sqrt 2.
-template <bool RHO = false>
-__device__ inline uint32_t d8_codes4(const D8Row &up, const D8Row &mid, const D8Row &dn,
-                                     const float *t = nullptr)
-{
-    uint32_t out = 0;
+    constexpr float kSqrt2 = 0x1.6a09e6p+0f;  // sqrt 2 rounded to float
+    out = d8_down(mid, dn);
+    float e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = __fsub_rn(mid.v[i], i < 3 ? mid.v[i + 1] : mid.r);
+    const float w0 = __fsub_rn(mid.v[0], mid.l);
+    const float nw0 = __fsub_rn(mid.v[0], up.l), ne3 = __fsub_rn(mid.v[3], up.r);
+    const float tt[4] = {t.x, t.y, t.z, t.w};
+    uint32_t codes = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const float zc = mid.v[i];
-        int code = kNoData;
-        if (zc == zc) {
-            int kc, kd;
-            const float bc = d8_best4(zc, d8_at(up, i), d8_at(mid, i - 1), d8_at(mid, i + 1), d8_at(dn, i),
-                                      1, 3, 4, 6, kc);
-            const float bd = d8_best4(zc, d8_at(up, i - 1), d8_at(up, i + 1), d8_at(dn, i - 1),
-                                      d8_at(dn, i + 1), 0, 2, 5, 7, kd);
-            code = d8_pick<RHO>(bc, kc, bd, kd, RHO ? t[i] : 0.0f);
-        }
-        out |= (uint32_t)code << (8 * i);
+        // cardinal: N = -in.s[i], W = -e[i-1] (w0 for i = 0), E, S
+        const float W = i > 0 ? -e[i - 1] : w0, N = -in.s[i];
+        const float mc = d8_max(i > 0 ? d8_max0<true, true>(in.s[i], e[i > 0 ? i - 1 : 0])
+                                      : d8_max0<true, false>(in.s[i], w0),
+                                e[i], out.s[i]);
+        int kc = e[i] == mc ? 4 : 6;
+        kc = W == mc ? 3 : kc;
+        kc = N == mc ? 1 : kc;
+        // diagonal: NW = -in.se[i-1] (nw0 for i = 0), NE = -in.sw[i+1] (ne3 for i = 3), SW, SE
+        const float NW = i > 0 ? -in.se[i > 0 ? i - 1 : 0] : nw0;
+        const float NE = i < 3 ? -in.sw[i < 3 ? i + 1 : 3] : ne3;
+        float md;
+        if (i == 0)
+            md = d8_max(d8_max0<false, true>(nw0, in.sw[1]), out.sw[i], out.se[i]);
+        else if (i == 3)
+            md = d8_max(d8_max0<true, false>(in.se[2], ne3), out.sw[i], out.se[i]);
+        else
+            md = d8_max(d8_max0<true, true>(in.se[i - 1], in.sw[i + 1]), out.sw[i], out.se[i]);
+        int kd = out.sw[i] == md ? 5 : 7;
+        kd = NE == md ? 2 : kd;
+        kd = NW == md ? 0 : kd;
+        // cardinal against diagonal
+        const float y = mc * (RHO ? tt[i] : kSqrt2);
+        const bool no_dwin = !(md > __builtin_fmaf(y, kUp, kMin));
+        const bool no_cwin = !(y > __builtin_fmaf(md, kUp, kMin));
+        int code = no_cwin ? kd : kc;
+        if (no_dwin && no_cwin) code = d8_pick_exact<RHO>(mid.v[i], mc, kc, md, kd, tt[i]);
+        codes |= (uint32_t)code << (8 * i);
     }
-    return out;
+    return codes;
 }
 
-// rnd (RHO only): rho8's per-cell random values, the dem's layout.
+// rnd (RHO only): rho8's per-cell random values, the dem's layout; returns
+// t = fl32(2 - r).  Rows past the raster read its last row (unused).
 template <bool VEC, bool RHO>
-__device__ inline void d8_rnd_load(const float *__restrict__ rnd, int64_t rows, int64_t cols, int64_t r,
-                                   int64_t c0, float4 &t)
+__device__ inline float4 d8_rnd_load(const float *__restrict__ rnd, const D8Lane &L, int k)
 {
-    t = make_float4(2.0f, 2.0f, 2.0f, 2.0f);
+    float4 t = make_float4(2.0f, 2.0f, 2.0f, 2.0f);
     if constexpr (RHO) {
-        if (r < 0 || r >= rows || c0 >= cols) return;
-        const float *p = rnd + r * cols;
+        const float *p = rnd + L.row_clamped(k) * L.cols;
         float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if constexpr (VEC) {
-            v = *reinterpret_cast<const float4 *>(p + c0);
+            v = *reinterpret_cast<const float4 *>(p + (L.c0 < L.cols ? L.c0 : L.cols - 4));
         } else {
-            v.x = p[c0];
-            if (c0 + 1 < cols) v.y = p[c0 + 1];
-            if (c0 + 2 < cols) v.z = p[c0 + 2];
-            if (c0 + 3 < cols) v.w = p[c0 + 3];
+            if (L.c0 < L.cols) v.x = p[L.c0];
+            if (L.c0 + 1 < L.cols) v.y = p[L.c0 + 1];
+            if (L.c0 + 2 < L.cols) v.z = p[L.c0 + 2];
+            if (L.c0 + 3 < L.cols) v.w = p[L.c0 + 3];
         }
         t = make_float4(__fsub_rn(2.0f, v.x), __fsub_rn(2.0f, v.y), __fsub_rn(2.0f, v.z),
                         __fsub_rn(2.0f, v.w));
     }
+    return t;
 }
+
+template <bool VEC>
+__device__ inline void d8_store(uint8_t *__restrict__ dirs, const D8Lane &L, int k, uint32_t codes)
+{
+    uint8_t *o = dirs + (L.r0 + k) * L.cols + L.c0;
+    if constexpr (VEC) {
+        if (L.c0 < L.cols) *reinterpret_cast<uint32_t *>(o) = codes;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (L.c0 + i < L.cols) o[i] = (uint8_t)(codes >> (8 * i));
+    }
+}
+
+template <int J>
+using D8Step = std::integral_constant<int, J>;
 
 template <bool VEC, bool RHO>
 __global__ void __launch_bounds__(kD8Threads)
@@ -229,39 +319,52 @@ d8_kernel(const float *__restrict__ dem, const float *__restrict__ rnd, uint8_t 
 {
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t strip = strip0 + t / ncb, cb = t - (t / ncb) * ncb;
-    const int64_t c0 = cb * kD8Cols + 4 * (int64_t)threadIdx.x;
-    const int64_t r0 = strip * kD8Rows;
-    const int64_t r1 = rows - r0 < kD8Rows ? rows : r0 + kD8Rows;
-    const float nodata_ = nodata;
-    float4 q, q2, tn;
-    float hl, hr, hl2, hr2;
-    d8_row_load<VEC>(dem, rows, cols, r0 - 1, c0, q, hl, hr);
-    D8Row up = d8_row_finish(q, hl, hr, nodata_);
-    d8_row_load<VEC>(dem, rows, cols, r0, c0, q, hl, hr);
-    D8Row mid = d8_row_finish(q, hl, hr, nodata_);
-    d8_rnd_load<VEC, RHO>(rnd, rows, cols, r0, c0, tn);
-    // two rows in flight: q (row r + 1) and q2 (row r + 2)
-    d8_row_load<VEC>(dem, rows, cols, r0 + 1, c0, q, hl, hr);
-    d8_row_load<VEC>(dem, rows, cols, r0 + 2, c0, q2, hl2, hr2);
-    for (int64_t r = r0; r < r1; ++r) {
-        const D8Row dn = d8_row_finish(q, hl, hr, nodata_);
-        q = q2;
-        hl = hl2;
-        hr = hr2;
-        d8_row_load<VEC>(dem, rows, cols, r + 3, c0, q2, hl2, hr2);  // in flight during two compares
-        const float tr[4] = {tn.x, tn.y, tn.z, tn.w};
-        d8_rnd_load<VEC, RHO>(rnd, rows, cols, r + 1, c0, tn);
-        const uint32_t codes = d8_codes4<RHO>(up, mid, dn, tr);
-        uint8_t *o = dirs + r * cols + c0;
-        if constexpr (VEC) {
-            if (c0 < cols) *reinterpret_cast<uint32_t *>(o) = codes;
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (c0 + i < cols) o[i] = (uint8_t)(codes >> (8 * i));
-        }
-        up = mid;
-        mid = dn;
+    D8Lane L;
+    L.rows = rows;
+    L.cols = cols;
+    L.c0 = cb * kD8Cols + 4 * (int64_t)threadIdx.x;
+    L.cw = cb * kD8Cols + 256 * (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    L.rvalid = L.c0 + 4 < cols;
+    L.r0 = strip * kD8Rows;
+    L.above = L.r0 > 0;
+    L.nrem = rows - L.r0 < kD8Rows + 3 ? (int)(rows - L.r0) : kD8Rows + 3;
+    const int n = L.nrem < kD8Rows ? L.nrem : kD8Rows;  // rows of this strip
+    // rings (k = row - r0): F[k mod 3] holds row k, R[(k - 1) mod 2] the raw row
+    // k + 1 in flight, C[(k + 1) mod 2] the drops of row k - 1 toward row k,
+    // T[k mod 2] rho8's distances of row k
+    D8Row F[3];
+    D8Raw R[2];
+    D8Down C[2];
+    float4 T[2];
+    F[2] = d8_finish(d8_load<VEC>(dem, L, -1), L, -1, nodata);
+    F[0] = d8_finish(d8_load<VEC>(dem, L, 0), L, 0, nodata);
+    C[1] = d8_down(F[2], F[0]);
+    R[1] = d8_load<VEC>(dem, L, 1);
+    R[0] = d8_load<VEC>(dem, L, 2);
+    T[0] = d8_rnd_load<VEC, RHO>(rnd, L, 0);
+    T[1] = d8_rnd_load<VEC, RHO>(rnd, L, 1);
+    auto step = [&](auto J, int k) {
+        constexpr int j = decltype(J)::value;
+        // row k: mid F[j % 3], below F[(j + 1) % 3] (finished now from R), above F[(j + 2) % 3]
+        F[(j + 1) % 3] = d8_finish(R[(j + 1) % 2], L, k + 1, nodata);
+        R[(j + 1) % 2] = d8_load<VEC>(dem, L, k + 3);
+        const uint32_t codes =
+            d8_codes4<RHO>(F[(j + 2) % 3], F[j % 3], F[(j + 1) % 3], C[(j + 1) % 2], C[j % 2], T[j % 2]);
+        T[j % 2] = d8_rnd_load<VEC, RHO>(rnd, L, k + 2);
+        d8_store<VEC>(dirs, L, k, codes);
+    };
+    for (int k = 0; k < n; k += 6) {
+        step(D8Step<0>{}, k);
+        if (k + 1 >= n) break;
+        step(D8Step<1>{}, k + 1);
+        if (k + 2 >= n) break;
+        step(D8Step<2>{}, k + 2);
+        if (k + 3 >= n) break;
+        step(D8Step<3>{}, k + 3);
+        if (k + 4 >= n) break;
+        step(D8Step<4>{}, k + 4);
+        if (k + 5 >= n) break;
+        step(D8Step<5>{}, k + 5);
     }
 }
 

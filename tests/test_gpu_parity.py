@@ -109,6 +109,31 @@ def test_d8_directions_strips_blocks_and_alignment(d8m):
         assert int(obuf[0]) == 0 and (obuf[1 + z.size:] == 0).all()
 
 
+def test_d8_directions_extreme_magnitudes_and_strip_ends(d8m):
+    """Drops whose float products underflow (subnormal and tiny elevations) or
+    come near the largest float, where the float slope compare must defer to
+    the exact one; and strips whose last row falls on every position of the
+    kernel's 6-row unrolled loop (heights 64 + 1 .. 64 + 6 and 6 k), both
+    16-byte aligned rows and per-element rows."""
+    rng = np.random.default_rng(17)
+    scales = [np.float32(2.0 ** -140), np.float32(1e-38), np.float32(2.0 ** -100),
+              np.float32(1e38), np.float32(3.0e38)]
+    for k, scale in enumerate(scales):
+        for shape in [(67, 260), (70, 131)]:
+            with np.errstate(over="ignore"):  # 3 x 3e38 becomes +-inf, on purpose
+                z = (rng.integers(-3, 4, shape) * scale).astype(np.float32)
+            z[rng.random(shape) < 0.03] = -9999.0
+            if k >= 3:
+                z[rng.random(shape) < 0.02] = np.float32(-3.4e38)
+            np.testing.assert_array_equal(d8m.d8_directions(dev(z)).cpu().numpy(), oracle.d8(z),
+                                          err_msg=f"scale {scale} shape {shape}")
+    for rows in [65, 66, 67, 68, 69, 70, 6, 12, 126, 127]:
+        for cols in (256, 257):
+            z = synth.dem(rows, cols, seed=rows, lambda0=16, ocean=True)
+            np.testing.assert_array_equal(d8m.d8_directions(dev(z)).cpu().numpy(), oracle.d8(z),
+                                          err_msg=f"{rows}x{cols}")
+
+
 def test_d8_directions_near_sqrt2(d8m):
     """The slope compare where the diagonal drop is within a few ulps of
     sqrt(2) times the cardinal one (the kernel's float fast path must defer
