@@ -71,18 +71,24 @@ class Tuner:
 
     def lookup(self, rows: int, cols: int, batch: bool = False, kind: str | None = None):
         """The cached tile for the size class: this device's entry, else one
-        for its architecture (the packaged table is keyed by architecture).
+        for its architecture (the packaged table is keyed by architecture),
+        else the entry of the nearest tuned class.
         kind "fwd" / "adj" takes that call's own shape where one is stored."""
         cls = size_class(rows, cols)
         arch = self.key.split("|")[-1]
         keys = (self._key(batch), arch + ("|batch" if batch else ""))
-        for table in (self.user, self.packaged):
-            for key in keys:
-                entry = table.get(key, {}).get(cls)
-                if entry:
-                    t = entry.get(f"tile_{kind}") if kind else None
-                    return tuple(int(v) for v in (t or entry["tile"]))
-        return None
+        tables = [table.get(key, {}) for table in (self.user, self.packaged) for key in keys]
+        entry = next((t[cls] for t in tables if t.get(cls)), None)
+        if entry is None:
+            # no entry for the class: the nearest tuned class (in powers of
+            # two; the larger on a tie), the user's cache first
+            near = [(abs(int(c).bit_length() - int(cls).bit_length()), -int(c), i, e)
+                    for i, t in enumerate(tables) for c, e in t.items() if e]
+            if not near:
+                return None
+            entry = min(near, key=lambda x: x[:3])[3]
+        t = entry.get(f"tile_{kind}") if kind else None
+        return tuple(int(v) for v in (t or entry["tile"]))
 
     def tile_for(self, rows: int, cols: int, batch: bool = False, kind: str | None = None) -> tuple[int, int]:
         """Tile shape for a raster run on its own, or (batch=True) as one of

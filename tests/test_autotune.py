@@ -28,8 +28,8 @@ def test_lookup_order_and_fallback(tmp_path, monkeypatch):
     t.key = "Some GPU|gfx950"
     assert t.tile_for(300, 500) == (32, 64)                # packaged, by architecture
     assert t.tile_for(300, 500, batch=True) == (48, 64)
-    assert t.tile_for(3000, 10) == autotune.DEFAULT_TILE   # no entry for the class
-    assert t.tile_for(3000, 10, batch=True) == autotune.DEFAULT_TILE
+    assert t.tile_for(3000, 10) == (32, 64)                # nearest tuned class (512)
+    assert t.tile_for(3000, 10, batch=True) == (48, 64)
     t.user = {"Some GPU|gfx950": {"512": {"tile": [64, 32]}}}
     assert t.tile_for(300, 500) == (64, 32)                # user cache first
     assert t.tile_for(300, 500, batch=True) == (48, 64)    # batch keeps its own entry
@@ -43,7 +43,32 @@ def test_lookup_order_and_fallback(tmp_path, monkeypatch):
     t.user = {"Some GPU|gfx950": {"512": {"tile": [64, 32]}}}
     assert t.tile_for(300, 500, kind="fwd") == (64, 32)
     t.key = "Other|gfx942"
-    assert t.tile_for(300, 500) == autotune.DEFAULT_TILE
+    assert t.tile_for(300, 500) == autotune.DEFAULT_TILE   # nothing for the architecture
+
+
+def test_nearest_class(tmp_path, monkeypatch):
+    """A size class with no entry takes the nearest tuned class in powers of
+    two (the larger on a tie); the user's cache first at equal distance."""
+    packaged = tmp_path / "packaged.json"
+    packaged.write_text(json.dumps({"gfx950": {"8192": {"tile": [64, 40]}, "32768": {"tile": [64, 32]},
+                                               "128": {"tile": [32, 32]}}}))
+    monkeypatch.setattr(autotune, "PACKAGED", str(packaged))
+    t = autotune.Tuner(path=str(tmp_path / "user.json"))
+    t.key = "Some GPU|gfx950"
+    assert t.tile_for(44001, 53688) == (64, 32)     # 65536 -> 32768
+    assert t.tile_for(1 << 20, 5) == (64, 32)
+    assert t.tile_for(16384, 100) == (64, 32)       # 16384: 8192 and 32768 tie -> the larger
+    assert t.tile_for(3000, 3000) == (64, 40)       # 4096 -> 8192
+    assert t.tile_for(200, 100) == (32, 32)         # 256 -> 128
+    assert t.tile_for(8192, 8192) == (64, 40)       # exact
+    t.user = {"Some GPU|gfx950": {"16384": {"tile": [48, 64]}}}
+    assert t.tile_for(30000, 7) == (64, 32)         # exact packaged entry beats a near user one
+    assert t.tile_for(10000, 7) == (48, 64)         # exact user entry
+    t.user = {"Some GPU|gfx950": {"65536": {"tile": [48, 64]}}}
+    assert t.tile_for(100000, 100) == (48, 64)      # 131072: the user's 65536 is nearer than 32768
+    assert t.tile_for(16384, 100) == (64, 32)       # 16384: 32768 (distance 1) before 65536 (2)
+    t.user = {"Some GPU|gfx950": {"8192": {"tile": [48, 64]}}}
+    assert t.tile_for(3000, 3000) == (48, 64)       # 4096 -> 8192, the user's entry first
 
 
 def test_table_from_bench():

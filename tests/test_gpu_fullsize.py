@@ -244,3 +244,121 @@ def test_dem32768_absorb_full_size(d8m, c3):
         zero = valid & (want_all == 0)
         assert (got[zero] == 0).all() and (got[~valid] == 0).all(), name
         del rel, pos, zero
+
+
+def receivers_band(dirs: torch.Tensor, r0: int, r1: int) -> torch.Tensor:
+    """receivers() for rows r0 .. r1 - 1 of `dirs` (flat indices into the
+    whole raster), so that the checks below stay within memory at any size."""
+    rows, cols = dirs.shape
+    k = dirs[r0:r1].long()
+    r = torch.arange(r0, r1, device=dirs.device).view(-1, 1).expand(r1 - r0, cols)
+    c = torch.arange(cols, device=dirs.device).view(1, -1).expand(r1 - r0, cols)
+    dr = torch.tensor(DR + (0, 0), device=dirs.device)[k.clamp(max=9)]
+    dc = torch.tensor(DC + (0, 0), device=dirs.device)[k.clamp(max=9)]
+    nr, nc = r + dr, c + dc
+    ok = (k < 8) & (nr >= 0) & (nr < rows) & (nc >= 0) & (nc < cols)
+    idx = nr.clamp(0, rows - 1) * cols + nc.clamp(0, cols - 1)
+    ok &= dirs.view(-1)[idx.view(-1)].view(r1 - r0, cols) != 9
+    return torch.where(ok, idx, torch.full_like(idx, -1)).view(-1)
+
+
+@pytest.mark.timeout(900)
+def test_over_2p31_cells(d8m):
+    """A raster of 44001 x 53688 = 2.36e9 cells, past 2^31 (flat indices
+    cross it at row 40000), ragged against the tile shapes in both
+    directions, in the launch configuration of its size class: D8 codes on
+    windows (the last rows among them) against the oracle, then unit counts
+    and the float32 adjoint through local balance, outlet mass and the
+    adjoint recurrence at every cell, and sampled cells past index 2^31
+    against the oracle's per-cell definitions.  The DEM (a tilted surface
+    with long waves, seeded noise and NoData discs) is made on the device:
+    the terrain generator would take minutes at this size."""
+    rows, cols = 44001, 53688
+    n = rows * cols
+    assert n > 2 ** 31 + 2 ** 27
+    gen = torch.Generator(device="cuda").manual_seed(2031)
+    z = torch.empty(rows, cols, dtype=torch.float32, device="cuda")
+    band = 4096
+    for r0 in range(0, rows, band):
+        r1 = min(rows, r0 + band)
+        rr = torch.arange(r0, r1, device="cuda", dtype=torch.float32).view(-1, 1)
+        cc = torch.arange(cols, device="cuda", dtype=torch.float32).view(1, -1)
+        zb = 0.002 * rr + 0.001 * cc + 3.0 * torch.sin(rr / 300.0) * torch.sin(cc / 450.0)
+        zb += 0.01 * torch.rand(r1 - r0, cols, device="cuda", generator=gen)
+        z[r0:r1] = zb
+        del zb
+    for (rc, ccen, rad) in ((1000, 2000, 300), (20000, 30000, 900), (41000, 50000, 700), (43990, 100, 60)):
+        a0, a1, b0, b1 = max(0, rc - rad), min(rows, rc + rad), max(0, ccen - rad), min(cols, ccen + rad)
+        rr = torch.arange(a0, a1, device="cuda").view(-1, 1)
+        cc = torch.arange(b0, b1, device="cuda").view(1, -1)
+        disc = (rr - rc) ** 2 + (cc - ccen) ** 2 < rad * rad
+        z[a0:a1, b0:b1][disc] = -9999.0
+    dirs = d8m.d8_directions(z)
+    torch.cuda.synchronize()
+
+    # D8 on windows: each window plus a one-cell margin (clipped to the
+    # raster) through the oracle; the window's cells have all their
+    # neighbours inside the margin or off the raster
+    for (w0, w1, v0, v1) in ((0, 300, 0, 700), (20500, 20800, 29000, 30300), (40900, 41200, 49000, 50700),
+                             (43700, rows, cols - 900, cols), (39990, 40010, 0, cols)):
+        e0, e1, f0, f1 = max(0, w0 - 1), min(rows, w1 + 1), max(0, v0 - 1), min(cols, v1 + 1)
+        want = oracle.d8(z[e0:e1, f0:f1].cpu().numpy())[w0 - e0:w1 - e0, v0 - f0:v1 - f0]
+        np.testing.assert_array_equal(dirs[w0:w1, v0:v1].cpu().numpy(), want, err_msg=f"window {w0}:{w1}")
+
+    from paper_1608_04431_amd.autotune import Tuner
+    tuner = Tuner()
+    tile_f, tile_a = tuner.tile_for(rows, cols, kind="fwd"), tuner.tile_for(rows, cols, kind="adj")
+    assert rows % tile_f[0] and cols % tile_f[1] and rows % tile_a[0] and cols % tile_a[1]
+    A = d8m.flow_accum(dirs, acc_type="u32", tile=tile_f)
+    g = torch.rand(rows, cols, device="cuda", generator=gen)
+    lam = d8m.flow_accum_adjoint(dirs, g, tile=tile_a)
+    torch.cuda.synchronize()
+
+    Av, Lv, Gv, Dv = A.view(-1), lam.view(-1), g.view(-1), dirs.view(-1)
+    inflow = torch.zeros(n, dtype=torch.int64, device="cuda")
+    outlet_mass, data_cells = 0, 0
+    step = 2048
+    for r0 in range(0, rows, step):
+        r1 = min(rows, r0 + step)
+        s = slice(r0 * cols, r1 * cols)
+        recv = receivers_band(dirs, r0, r1)
+        has = recv >= 0
+        data = Dv[s] != 9
+        A64 = Av[s].long() & 0xFFFFFFFF
+        inflow.index_add_(0, recv[has], A64[has])
+        outlet_mass += int(A64[data & ~has].sum())
+        data_cells += int(data.sum())
+        # adjoint recurrence lambda(c) = g(c) + lambda(receiver), float32 tolerance
+        L = Lv[s].double()
+        down = torch.zeros_like(L)
+        down[has] = Lv[recv[has]].double()
+        res = (L - Gv[s].double() - down)[data].abs()
+        scale = (L.abs() + down.abs())[data]
+        assert (res <= 1e-4 * scale + 1e-6).all(), (r0, float((res / (scale + 1e-30)).max()))
+        assert (L[~data] == 0).all()
+        del recv, has, data, A64, L, down, res, scale
+    # the outlets hold every data cell once
+    assert outlet_mass == data_cells
+    for r0 in range(0, rows, step):
+        s = slice(r0 * cols, min(rows, r0 + step) * cols)
+        data = Dv[s] != 9
+        A64 = Av[s].long() & 0xFFFFFFFF
+        assert torch.equal(A64[data], 1 + inflow[s][data]), r0
+        assert (A64[~data] == 0).all()
+    del inflow
+
+    # sampled cells past 2^31 (and a few before) against the per-cell
+    # definitions: catchment search for A, downstream path sum for lambda
+    d_host = dirs.cpu().numpy()
+    g_host = g.cpu().numpy()
+    cand = torch.randint(2 ** 31, n, (4096,), device="cuda", generator=gen)
+    cand = torch.cat([cand, torch.randint(0, 2 ** 31, (1024,), device="cuda", generator=gen)])
+    ok = (Dv[cand] != 9) & ((Av[cand].long() & 0xFFFFFFFF) < 200000)
+    picks = cand[ok][:24].tolist() + cand[ok][-8:].tolist()
+    assert sum(i >= 2 ** 31 for i in picks) >= 20
+    for i in picks:
+        r, c = divmod(int(i), cols)
+        assert int(A[r, c].item()) & 0xFFFFFFFF == int(oracle.upstream_sum(d_host, r, c)), (r, c)
+        want = oracle.downstream_sum(d_host, r, c, g_host)
+        got = float(lam[r, c].item())
+        assert abs(got - want) <= 1e-4 * max(want, 1e-6), (r, c, got, want)
