@@ -44,14 +44,6 @@ using namespace w64;
 
 namespace d8 {
 
-// ------------------------------------------------------------------ misc ---
-
-__global__ void fill_u32(uint32_t *p, uint32_t v, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // ------------------------------------------------------------------- D8 ----
 // Steepest descent (O'Callaghan and Mark, the rule the paper takes as given):
 // among the in-grid data neighbours strictly lower than the cell, the one with
