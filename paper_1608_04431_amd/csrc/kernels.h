@@ -71,8 +71,8 @@ namespace d8 {
 // in flight.  The row loop is unrolled by 6 so that the 3 rows of elevations
 // and the 2 load buffers and 2 sets of shared drops change roles without
 // register copies.  Column neighbours come from the adjacent lane (a
-// wavefront-wide DPP shift) or, at a wavefront's edge, one extra load of a
-// uniform address.  NoData, off-grid and missing cells are NaN, which no
+// wavefront-wide DPP shift) or, at a wavefront's edge, one extra vector load
+// whose address is the same in every lane.  NoData, off-grid and missing cells are NaN, which no
 // maximum selects and no compare matches.  VEC: rows start 16-byte aligned
 // (cols % 4 == 0 and an aligned dem), so a lane moves its 4 cells with one
 // 16-byte load and one 4-byte store; otherwise per element.  Blocks are mapped
@@ -315,7 +315,9 @@ d8_kernel(const float *__restrict__ dem, const float *__restrict__ rnd, uint8_t 
     L.rows = rows;
     L.cols = cols;
     L.c0 = cb * kD8Cols + 4 * (int64_t)threadIdx.x;
-    L.cw = cb * kD8Cols + 256 * (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the wavefront's halo cells are read by every lane with one vector load
+    // (the same address): as scalar loads they each fetched their own line
+    L.cw = L.c0 - 4 * (int64_t)(threadIdx.x & 63);
     L.rvalid = L.c0 + 4 < cols;
     L.r0 = strip * kD8Rows;
     L.above = L.r0 > 0;
