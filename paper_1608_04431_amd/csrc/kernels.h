@@ -67,13 +67,14 @@ namespace d8 {
 //
 // Layout: a block of 256 lanes covers 1024 columns (4 consecutive cells per
 // lane) and walks a strip of kD8Rows rows top to bottom.  Every elevation is
-// read from HBM once (plus one halo row per strip edge); two rows of loads are
-// in flight.  The row loop is unrolled by 6 so that the 3 rows of elevations
-// and the 2 load buffers and 2 sets of shared drops change roles without
-// register copies.  Column neighbours come from the adjacent lane (a
-// wavefront-wide DPP shift) or, at a wavefront's edge, one extra vector load
-// whose address is the same in every lane.  NoData, off-grid and missing cells are NaN, which no
-// maximum selects and no compare matches.  VEC: rows start 16-byte aligned
+// read from HBM once, plus the row above and the three rows below the strip
+// (the loads run two rows ahead).  The row loop is unrolled by 6 so that the 3
+// rows of elevations and the 2 load buffers and 2 sets of shared drops change
+// roles without register copies.  Column neighbours come from the adjacent
+// lane (a wavefront-wide DPP shift) or, at a wavefront's edge, one extra vector
+// load whose address is the same in every lane.  NoData, off-grid and missing
+// cells are NaN, which no maximum selects and no compare matches.  VEC: rows
+// start 16-byte aligned
 // (cols % 4 == 0 and an aligned dem), so a lane moves its 4 cells with one
 // 16-byte load and one 4-byte store; otherwise per element.  Blocks are mapped
 // XCD-contiguously so vertically and horizontally adjacent blocks share an L2.
@@ -83,9 +84,8 @@ constexpr int kD8Rows = 64;
 constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i + 1
 constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i - 1
 
-// A row as loaded: the lane's 4 cells, the halo cells left of lane 0 and right
-// of lane 63 (the same address in every lane), and whether the row is inside
-// the raster.
+// A row as loaded: the lane's 4 cells and the halo cells left of lane 0 and
+// right of lane 63 (the same address in every lane).
 struct D8Raw {
     float4 q;
     float hl, hr;
