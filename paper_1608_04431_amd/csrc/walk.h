@@ -202,16 +202,22 @@ __device__ inline void load_codes(const uint8_t *__restrict__ row, int w, uint32
         for (int m = 0; m < kWords; ++m)
             if (4 * m < w) W[m] = row4[m];
     } else {
+        // the aligned 4-byte words that cover the row, joined with byte
+        // funnel shifts: the first and the last word reach at most 3 bytes
+        // outside the row, inside the aligned word of a byte of the row (so
+        // on its page); bytes past the row's end are left for the caller
+        const uintptr_t a = reinterpret_cast<uintptr_t>(row);
+        const uint32_t *base = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a & 3);
+        const int nw = (int)((sh + (uint32_t)w + 3u) >> 2);  // words over the row's bytes
+        uint32_t cur = base[0];
 #pragma unroll
         for (int m = 0; m < kWords; ++m) {
-            uint32_t v = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                int c = 4 * m + b;
-                uint32_t k = c < w ? row[c] : 0xFFu;
-                v |= k << (8 * b);
+            if (4 * m < w) {
+                const uint32_t nxt = base[m + 1 < nw ? m + 1 : nw - 1];
+                W[m] = __builtin_amdgcn_alignbyte(nxt, cur, sh);
+                cur = nxt;
             }
-            W[m] = v;
         }
     }
 }

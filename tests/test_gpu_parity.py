@@ -193,6 +193,35 @@ def test_forward_u32_random(d8m, shape, tile):
     assert_u32_exact(gpu_u32(d8m, d, tile), d)
 
 
+def test_tile_passes_unaligned_code_rows(d8m):
+    """The tile passes read a row of codes that does not start on a 4-byte
+    boundary as the aligned words that cover it: widths that are not a
+    multiple of four (rows start at every byte offset), and the same rasters
+    through code pointers 1, 2 and 3 bytes past an aligned address.  Unit
+    counts exact against the oracle, the adjoint within the float32
+    tolerance, and the float32 forward and the adjoint equal bit for bit to
+    the aligned call."""
+    for shape, seed in (((70, 131), 31), ((67, 256), 32), ((45, 97), 33), ((130, 45), 34)):
+        d = random_acyclic_dirs(*shape, seed=seed)
+        g = dev(synth.uniform(shape, seed + 100))
+        want_a = oracle.transpose_f64(d, g.cpu().numpy())
+        for tile in ((64, 32), (64, 44), (64, 64), (16, 40)):
+            ref_f = d8m.flow_accum(dev(d), g, acc_type="f32", tile=tile)
+            ref_a = d8m.flow_accum_adjoint(dev(d), g, tile=tile)
+            for off in (0, 1, 2, 3):
+                flat = torch.full((d.size + 8,), 0xEE, dtype=torch.uint8, device="cuda")
+                flat[off:off + d.size] = dev(d).flatten()
+                dv = flat[off:off + d.size].view(shape)
+                assert dv.data_ptr() % 4 == off % 4
+                what = f"{shape} {tile} +{off}"
+                got = d8m.flow_accum(dv, acc_type="u32", tile=tile).cpu().numpy().view(np.uint32)
+                assert_u32_exact(got, d)
+                assert torch.equal(d8m.flow_accum(dv, g, acc_type="f32", tile=tile), ref_f), what
+                lam = d8m.flow_accum_adjoint(dv, g, tile=tile)
+                assert torch.equal(lam, ref_a), what
+                assert_rel(lam.cpu().numpy(), want_a, d != 9, what=what)
+
+
 def test_forward_all_nodata_and_outlets(d8m):
     d = np.full((50, 70), 9, dtype=np.uint8)
     assert (gpu_u32(d8m, d) == 0).all()
