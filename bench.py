@@ -45,7 +45,7 @@ SWEEP_TILES = ((64, 64), (64, 48), (64, 44), (64, 40), (64, 36), (64, 32), (64, 
                (56, 48), (48, 48), (48, 32))
 
 
-ABSORB_TILE = (32, 48)  # the absorption entry points' default shape
+ABSORB_TILE = (48, 32)  # the absorption entry points' default shape
 
 KERNEL_NAMES = {  # timing label -> kernel symbol prefix in profiler output
     "fwd_pass1": "fwd_walk<1, unsigned int",

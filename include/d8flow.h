@@ -166,7 +166,7 @@ int flow_accum_adjoint(const uint8_t *dirs, const float *grad_acc, float *grad_w
  * cell (values outside [0, 1] are used as given); acc: float32 A (out), 0 on
  * NoData cells.  ws: at least d8_absorb_workspace_bytes(...) (256-byte
  * aligned).  Other arguments and returns as for flow_accum, except that
- * tile_rows = tile_cols = 0 picks 32 x 48: the tile's LDS holds alpha besides
+ * tile_rows = tile_cols = 0 picks 48 x 32: the tile's LDS holds alpha besides
  * the values, so smaller tiles keep more of them resident per CU.
  */
 size_t d8_absorb_workspace_bytes(int64_t rows, int64_t cols, int tile_rows, int tile_cols);

@@ -20,8 +20,9 @@ namespace {
 
 constexpr int kDefaultTile = 64;
 // Absorption keeps alpha beside the values in LDS, so its tiles default to a
-// smaller shape (more tiles resident per CU): 32 x 48.
-constexpr int kAbsorbTileRows = 32, kAbsorbTileCols = 48;
+// smaller shape (more tiles resident per CU): 48 x 32, which also takes the
+// kernels' narrowest register-row copy.
+constexpr int kAbsorbTileRows = 48, kAbsorbTileCols = 32;
 inline void absorb_default_tile(int &th, int &tw)
 {
     if (th == 0 && tw == 0) {
@@ -247,6 +248,25 @@ decltype(&w64::fwd_walk<PASS, T, V, E>) fwd_walk_k(int tw)
     }
 }
 
+template <int PASS>
+decltype(&w64::fwd_walk_absorb<PASS>) fwd_walk_absorb_k(int tw)
+{
+    switch (row_width(tw)) {
+    case 32: return &w32::fwd_walk_absorb<PASS>;
+    case 44: return &w44::fwd_walk_absorb<PASS>;
+    default: return &w64::fwd_walk_absorb<PASS>;
+    }
+}
+
+decltype(&w64::adj_walk_absorb) adj_walk_absorb_k(int tw)
+{
+    switch (row_width(tw)) {
+    case 32: return &w32::adj_walk_absorb;
+    case 44: return &w44::adj_walk_absorb;
+    default: return &w64::adj_walk_absorb;
+    }
+}
+
 decltype(&w64::adj_walk) adj_walk_k(int tw)
 {
     switch (row_width(tw)) {
@@ -429,13 +449,13 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
     const int ntiles = g.nty * g.ntx;
     const size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkFwd1, 4, true);
     const size_t lds2 = walk_lds_bytes(g.th, g.tw, kWalkFwd2, 4, true);
-    if (allow_lds(fwd_walk_absorb<1>, lds1) || allow_lds(fwd_walk_absorb<2>, lds2)) return D8_EHIP;
+    const auto pass1 = fwd_walk_absorb_k<1>(g.tw), pass2 = fwd_walk_absorb_k<2>(g.tw);
+    if (allow_lds(pass1, lds1) || allow_lds(pass2, lds2)) return D8_EHIP;
     const unsigned nb = blocks_for(g.nnodes, kNodeBlock);
     init_state<<<1, 1, 0, st>>>(status, jstate);
     D8_LAUNCH("absorb_pass1", st,
-              (fwd_walk_absorb<1><<<ntiles, kTileThreads, lds1, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt,
-                                                                      acc, ext, nullptr, status, anode,
-                                                                      pathp)));
+              (pass1<<<ntiles, kTileThreads, lds1, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt, acc, ext,
+                                                         nullptr, status, anode, pathp)));
     D8_LAUNCH("graph_build", st,
               (graph_build<<<nb, kNodeBlock, 0, st>>>(dirs, g, link, entry, succ, indeg, 0, g.nnodes)));
     // the per-exit coefficients take the adjoint's second word buffer
@@ -445,8 +465,8 @@ int run_forward_absorb(const uint8_t *dirs, const float *w, const float *alpha, 
     D8_LAUNCH("resolve_ext", st,
               (resolve_ext<true><<<nb, kNodeBlock, 0, st>>>(dirs, g, link, acc, ext, anode, 0, g.nnodes)));
     D8_LAUNCH("absorb_pass2", st,
-              (fwd_walk_absorb<2><<<ntiles, kTileThreads, lds2, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt,
-                                                                      acc, ext, out, status, anode, pathp)));
+              (pass2<<<ntiles, kTileThreads, lds2, st>>>(dirs, w, alpha, g, link, aloc, indeg, cnt, acc, ext,
+                                                         out, status, anode, pathp)));
     return last_error();
 }
 
@@ -1254,11 +1274,12 @@ int flow_accum_absorb_adjoint(const uint8_t *dirs, const float *alpha, const flo
     const int ntiles = g.nty * g.ntx;
     const size_t lds1 = walk_lds_bytes(g.th, g.tw, kWalkAdj1, 4, true);
     begin_call();
-    if (allow_lds(adj_walk_absorb, lds1)) return D8_EHIP;
+    const auto apass1 = adj_walk_absorb_k(g.tw);
+    if (allow_lds(apass1, lds1)) return D8_EHIP;
     init_state<<<1, 1, 0, st>>>(status, jstate);
     D8_LAUNCH("absorb_adj_pass1", st,
-              (adj_walk_absorb<<<ntiles, kTileThreads, lds1, st>>>(dirs, grad_acc, alpha, g, link, S, P,
-                                                                   grad_weights, pcell, root8, status)));
+              (apass1<<<ntiles, kTileThreads, lds1, st>>>(dirs, grad_acc, alpha, g, link, S, P, grad_weights,
+                                                          pcell, root8, status)));
     // inv (dense index -> node) lives in jw[1] until round 0 overwrites it
     uint32_t *inv = reinterpret_cast<uint32_t *>(jw[1]);
     compact_exits(st, g.nnodes, link, bsum, cmap, inv, nexit, false);

@@ -45,7 +45,8 @@ def assert_rel(got, want, valid):
 
 
 @pytest.mark.parametrize("shape,tile", [((300, 257), (32, 32)), ((130, 200), (64, 48)),
-                                        ((97, 64), (16, 64)), ((200, 131), (64, 64))])
+                                        ((97, 64), (16, 64)), ((200, 131), (64, 64)),
+                                        ((150, 171), (32, 44)), ((129, 97), (64, 40))])
 def test_absorb_matches_oracle(d8m, shape, tile):
     cases = [random_acyclic_dirs(*shape, seed=sum(shape)),
              oracle.d8(synth.dem(*shape, seed=13, lambda0=32, ocean=True))]
@@ -85,7 +86,8 @@ def test_absorb_empty_and_single_tile(d8m):
 
 
 @pytest.mark.parametrize("shape,tile", [((300, 257), (32, 32)), ((130, 200), (64, 48)),
-                                        ((97, 64), (16, 64)), ((200, 131), (64, 64))])
+                                        ((97, 64), (16, 64)), ((200, 131), (64, 64)),
+                                        ((150, 171), (32, 44)), ((129, 97), (64, 40))])
 def test_absorb_adjoint_matches_oracle(d8m, shape, tile):
     cases = [random_acyclic_dirs(*shape, seed=sum(shape) + 1),
              oracle.d8(synth.dem(*shape, seed=17, lambda0=32, ocean=True))]

@@ -175,7 +175,7 @@ def test_dem32768_full_size(d8m, c3):
 
 @pytest.mark.timeout(900)
 def test_dem32768_absorb_full_size(d8m, c3):
-    """Absorption at full size in the benchmark's configuration (32 x 48 tiles,
+    """Absorption at full size in the benchmark's configuration (48 x 32 tiles,
     alpha ~ U[0.5, 1), U[0, 1) weights and cotangents): local balance
     A(c) = w(c) + sum of alpha(n) A(n) over c's donors and the recurrence
     lambda(c) = g(c) + alpha(c) lambda(receiver) at every cell (float32
@@ -185,7 +185,7 @@ def test_dem32768_absorb_full_size(d8m, c3):
     transpose (computed on a host thread meanwhile) within 1e-4 relative."""
     dirs = c3["dirs"]
     rows, cols = dirs.shape
-    tile = (32, 48)
+    tile = (48, 32)
     w_host, alpha_host, d_host = c3["g_host"], c3["alpha_host"], c3["d_ref"]
     w, alpha = torch.from_numpy(w_host).cuda(), torch.from_numpy(alpha_host).cuda()
     A = d8m.flow_accum_absorb(dirs, alpha, w, tile=tile)
