@@ -5,8 +5,10 @@ oracle; unit-count accumulation and the float32 adjoint first through
 properties that determine them (local balance against the donors, the
 adjoint recurrence along receivers, computed here with plain tensor ops,
 independently of the library), then every cell against the oracle's Kahn
-sweep and its transpose.  Absorption at full size: the same properties and
-sampled cells against the oracle's per-cell definitions."""
+sweep and its transpose.  Absorption at full size: the same properties,
+sampled cells against the oracle's per-cell definitions and every cell
+against the oracle.  rho8 codes over the whole raster, and a raster past 2^31
+cells."""
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -362,3 +364,47 @@ def test_over_2p31_cells(d8m):
         want = oracle.downstream_sum(d_host, r, c, g_host)
         got = float(lam[r, c].item())
         assert abs(got - want) <= 1e-4 * max(want, 1e-6), (r, c, got, want)
+
+
+@pytest.mark.timeout(900)
+def test_dem32768_rho8_whole_raster(d8m, dem32768):
+    """rho8 directions (one U[0, 1) draw per cell) over the whole 32768^2
+    raster, code for code against the oracle (run on a host thread
+    meanwhile); then unit counts over them through local balance and outlet
+    mass at every cell (rho8, like D8, sends each cell to a strictly lower
+    neighbour, so its directions are acyclic)."""
+    rows, cols = dem32768.shape
+    rnd = synth.uniform((rows, cols), 77)
+    pool = ThreadPoolExecutor(max_workers=1)
+    ref = pool.submit(oracle.rho8, dem32768, rnd)
+    dirs = d8m.d8_directions_rho8(torch.from_numpy(dem32768).cuda(), torch.from_numpy(rnd).cuda())
+    from paper_1608_04431_amd.autotune import Tuner
+    A = d8m.flow_accum(dirs, acc_type="u32", tile=Tuner().tile_for(rows, cols, kind="fwd"))
+    torch.cuda.synchronize()
+    got = dirs.cpu().numpy()
+    want = ref.result()
+    pool.shutdown(wait=True)
+    bad = np.flatnonzero(got.ravel() != want.ravel())
+    assert bad.size == 0, f"{bad.size} codes differ, first at {divmod(int(bad[0]), cols)}"
+    del got, want, rnd
+
+    Dv, Av = dirs.view(-1), A.view(-1)
+    inflow = torch.zeros(rows * cols, dtype=torch.int64, device="cuda")
+    outlet_mass, data_cells = 0, 0
+    step = 4096
+    for r0 in range(0, rows, step):
+        s = slice(r0 * cols, min(rows, r0 + step) * cols)
+        recv = receivers_band(dirs, r0, min(rows, r0 + step))
+        has = recv >= 0
+        data = Dv[s] != 9
+        A64 = Av[s].long() & 0xFFFFFFFF
+        inflow.index_add_(0, recv[has], A64[has])
+        outlet_mass += int(A64[data & ~has].sum())
+        data_cells += int(data.sum())
+    assert outlet_mass == data_cells
+    for r0 in range(0, rows, step):
+        s = slice(r0 * cols, min(rows, r0 + step) * cols)
+        data = Dv[s] != 9
+        A64 = Av[s].long() & 0xFFFFFFFF
+        assert torch.equal(A64[data], 1 + inflow[s][data]), r0
+        assert (A64[~data] == 0).all()
