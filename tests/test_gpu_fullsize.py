@@ -271,8 +271,9 @@ def test_over_2p31_cells(d8m):
     directions, in the launch configuration of its size class: D8 codes on
     windows (the last rows among them) against the oracle, then unit counts
     and the float32 adjoint through local balance, outlet mass and the
-    adjoint recurrence at every cell, and sampled cells past index 2^31
-    against the oracle's per-cell definitions.  The DEM (a tilted surface
+    adjoint recurrence at every cell, the same properties for absorption
+    (alpha ~ U[0.5, 1), the cotangent raster as weights and cotangent), and
+    sampled cells past index 2^31 against the oracle's per-cell definitions.  The DEM (a tilted surface
     with long waves, seeded noise and NoData discs) is made on the device:
     the terrain generator would take minutes at this size."""
     rows, cols = 44001, 53688
@@ -348,6 +349,38 @@ def test_over_2p31_cells(d8m):
         assert torch.equal(A64[data], 1 + inflow[s][data]), r0
         assert (A64[~data] == 0).all()
     del inflow
+
+    # absorption at the same size (its own per-node and per-cell arrays):
+    # local balance and the adjoint recurrence at every cell
+    alpha = 0.5 + 0.5 * torch.rand(rows, cols, device="cuda", generator=gen)
+    Ab = d8m.flow_accum_absorb(dirs, alpha, g)
+    Lb = d8m.flow_accum_absorb_adjoint(dirs, alpha, g)
+    torch.cuda.synchronize()
+    Abv, Lbv, Alv = Ab.view(-1), Lb.view(-1), alpha.view(-1)
+    inflow = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for r0 in range(0, rows, step):
+        s = slice(r0 * cols, min(rows, r0 + step) * cols)
+        recv = receivers_band(dirs, r0, min(rows, r0 + step))
+        has = recv >= 0
+        data = Dv[s] != 9
+        inflow.index_add_(0, recv[has], (Alv[s][has].double() * Abv[s][has].double()))
+        L = Lbv[s].double()
+        down = torch.zeros_like(L)
+        down[has] = Alv[s][has].double() * Lbv[recv[has]].double()
+        res = (L - Gv[s].double() - down)[data].abs()
+        scale = (L.abs() + down.abs())[data]
+        assert (res <= 1e-4 * scale + 1e-6).all(), ("absorb adjoint", r0)
+        assert (L[~data] == 0).all()
+        del recv, has, data, L, down, res, scale
+    for r0 in range(0, rows, step):
+        s = slice(r0 * cols, min(rows, r0 + step) * cols)
+        data = Dv[s] != 9
+        Ad = Abv[s].double()
+        res = (Ad - Gv[s].double() - inflow[s])[data].abs()
+        scale = (Ad.abs() + inflow[s].abs())[data]
+        assert (res <= 1e-4 * scale + 1e-6).all(), ("absorb forward", r0)
+        assert (Ad[~data] == 0).all()
+    del inflow, Ab, Lb, alpha, Abv, Lbv, Alv
 
     # sampled cells past 2^31 (and a few before) against the per-cell
     # definitions: catchment search for A, downstream path sum for lambda
