@@ -271,7 +271,8 @@ def test_over_2p31_cells(d8m):
     directions, in the launch configuration of its size class: D8 codes on
     windows (the last rows among them) against the oracle, then unit counts
     and the float32 adjoint through local balance, outlet mass and the
-    adjoint recurrence at every cell, the same properties for absorption
+    adjoint recurrence at every cell, the streamed forward and adjoint equal
+    to the in-memory calls, the same properties for absorption
     (alpha ~ U[0.5, 1), the cotangent raster as weights and cotangent), and
     sampled cells past index 2^31 against the oracle's per-cell definitions.  The DEM (a tilted surface
     with long waves, seeded noise and NoData discs) is made on the device:
@@ -349,6 +350,18 @@ def test_over_2p31_cells(d8m):
         assert torch.equal(A64[data], 1 + inflow[s][data]), r0
         assert (A64[~data] == 0).all()
     del inflow
+
+    # the same calls with the raster in host memory, streamed in bands: counts
+    # bit for bit, the adjoint within float32 rounding of the in-memory one
+    dirs_h = dirs.cpu().pin_memory()
+    As = d8m.flow_accum_streamed(dirs_h, tile=tile_f)
+    assert torch.equal(As, A.cpu())
+    del As
+    g_h = g.cpu().pin_memory()
+    Ls = d8m.flow_accum_adjoint_streamed(dirs_h, g_h, tile=tile_a)
+    Lm = lam.cpu()
+    assert float(((Ls.double() - Lm.double()).abs() / Lm.double().abs().clamp_min(1e-30)).max()) <= 1e-5
+    del Ls, Lm, g_h, dirs_h
 
     # absorption at the same size (its own per-node and per-cell arrays):
     # local balance and the adjoint recurrence at every cell
